@@ -1,0 +1,219 @@
+/*
+ * Plain FP64 CPU oracle for direct inverse ray-shooting.
+ *
+ * Vernardos & Fluke 2014, Section 2.1: rays on a regular image-plane grid are
+ * deflected by N_* point masses plus a smooth sheet kappa_s and an external
+ * shear gamma (eq. 1), then counted on a pixellated source plane; a pixel's
+ * magnification is its ray count over the count expected without lensing
+ * (eq. 4). The smooth fraction s = kappa_s / kappa (eq. 2) defines kappa_s.
+ *
+ * TEST INFRASTRUCTURE ONLY: used by the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark. It is deliberately the slow, obvious
+ * form: one ray at a time, lenses summed in input order, FP64 throughout,
+ * compiled with -ffp-contract=off and without fast-math so that every
+ * operation is a single IEEE-754 double operation.
+ *
+ * Readings of points the paper leaves open (all listed with their reasons in
+ * the design notes of the repository):
+ *   - rays sit at cell centres: x = (c - h) + (i + 1/2) * (2h / n);
+ *   - the shear acts along x1 (the diagonal matrix of eq. 1);
+ *   - pixels are half-open [lo, lo + W/P); rays outside the window, rays with a
+ *     non-finite position and rays that hit a lens exactly (r^2 == 0, where
+ *     eq. 1 is singular) are counted as escaped;
+ *   - N_avg is the unlensed ray density times the pixel area.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stddef.h>
+#include <omp.h>
+
+static int grid_ok(int64_t n1, int64_t n2, double h1, double h2) {
+    return n1 > 0 && n2 > 0 && isfinite(h1) && isfinite(h2) && h1 > 0.0 && h2 > 0.0;
+}
+
+static int window_ok(int32_t p1, int32_t p2, double w1, double w2, double W1, double W2) {
+    return p1 > 0 && p2 > 0 && isfinite(w1) && isfinite(w2) && isfinite(W1) && isfinite(W2) &&
+           W1 > 0.0 && W2 > 0.0;
+}
+
+/* One ray through eq. 1 (Section 2.1): the deflection is the sum over lenses of
+ * m_k (x - x_k) / |x - x_k|^2, taken in input order; the macro part is
+ * diag(1 - gamma, 1 + gamma) x - kappa_s x. */
+static void shoot_one(const double* lx1, const double* lx2, const double* lm, int64_t n_lens,
+                      double a1, double a2, double x1, double x2,
+                      double* y1, double* y2, int* singular, double* rmin) {
+    double alpha1 = 0.0;
+    double alpha2 = 0.0;
+    double r2min = INFINITY;
+    int sing = 0;
+    for (int64_t k = 0; k < n_lens; ++k) {
+        const double d1 = x1 - lx1[k];
+        const double d2 = x2 - lx2[k];
+        const double r2 = d1 * d1 + d2 * d2;
+        if (r2 == 0.0) sing = 1;
+        if (r2 < r2min) r2min = r2;
+        const double m = lm ? lm[k] : 1.0;
+        const double q = m / r2;
+        alpha1 = alpha1 + q * d1;
+        alpha2 = alpha2 + q * d2;
+    }
+    *y1 = a1 * x1 - alpha1;
+    *y2 = a2 * x2 - alpha2;
+    *singular = sing;
+    if (rmin) *rmin = sqrt(r2min);
+}
+
+/* Pixel of a source-plane position, or -1 when the ray escapes the window.
+ * u = (y - lo) * P / W per axis; binned iff 0 <= u < P on both axes (NaN fails
+ * every comparison, so non-finite positions escape). Truncation equals floor
+ * because u >= 0 here. */
+static int64_t pixel_of(double y1, double y2, int32_t p1, int32_t p2,
+                        double lo1, double lo2, double inv1, double inv2) {
+    const double u1 = (y1 - lo1) * inv1;
+    const double u2 = (y2 - lo2) * inv2;
+    if (!(u1 >= 0.0 && u1 < (double)p1)) return -1;
+    if (!(u2 >= 0.0 && u2 < (double)p2)) return -1;
+    const int64_t ix = (int64_t)u1;
+    const int64_t iy = (int64_t)u2;
+    return iy * (int64_t)p1 + ix;
+}
+
+int oracle_max_threads(void) { return omp_get_max_threads(); }
+
+int oracle_ray_positions(const double* lx1, const double* lx2, const double* lm, int64_t n_lens,
+                         double kappa, double gamma, double s,
+                         int64_t n1, int64_t n2, double c1, double c2, double h1, double h2,
+                         int64_t row_begin, int64_t row_end,
+                         double* y1, double* y2, uint8_t* singular, double* rmin) {
+    if (!grid_ok(n1, n2, h1, h2) || n_lens < 0) return -1;
+    if (!isfinite(kappa) || !isfinite(gamma) || !isfinite(s) || !isfinite(c1) || !isfinite(c2)) return -1;
+    if (row_begin < 0 || row_end < row_begin || row_end > n2) return -1;
+    if (n_lens > 0 && (!lx1 || !lx2)) return -1;
+    if (!y1 || !y2 || !singular) return -1;
+
+    const double kappa_s = s * kappa;                /* eq. 2 */
+    const double a1 = (1.0 - gamma) - kappa_s;       /* eq. 1, x1 diagonal */
+    const double a2 = (1.0 + gamma) - kappa_s;       /* eq. 1, x2 diagonal */
+    const double d1 = (2.0 * h1) / (double)n1;
+    const double d2 = (2.0 * h2) / (double)n2;
+    const double base1 = c1 - h1;
+    const double base2 = c2 - h2;
+
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t j = row_begin; j < row_end; ++j) {
+        const double x2 = base2 + ((double)j + 0.5) * d2;
+        for (int64_t i = 0; i < n1; ++i) {
+            const double x1 = base1 + ((double)i + 0.5) * d1;
+            const int64_t o = (j - row_begin) * n1 + i;
+            int sing = 0;
+            shoot_one(lx1, lx2, lm, n_lens, a1, a2, x1, x2, &y1[o], &y2[o], &sing,
+                      rmin ? &rmin[o] : NULL);
+            singular[o] = (uint8_t)sing;
+        }
+    }
+    return 0;
+}
+
+int oracle_bin(const double* y1, const double* y2, const uint8_t* singular, int64_t n,
+               int32_t p1, int32_t p2, double w1, double w2, double W1, double W2,
+               int32_t* counts, int64_t* escaped) {
+    if (n < 0 || !window_ok(p1, p2, w1, w2, W1, W2)) return -1;
+    if (n > 0 && (!y1 || !y2)) return -1;
+    if (!counts || !escaped) return -1;
+    const double lo1 = w1 - 0.5 * W1;
+    const double lo2 = w2 - 0.5 * W2;
+    const double inv1 = (double)p1 / W1;
+    const double inv2 = (double)p2 / W2;
+    int64_t esc = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t pix = (singular && singular[k]) ? -1
+                          : pixel_of(y1[k], y2[k], p1, p2, lo1, lo2, inv1, inv2);
+        if (pix < 0) esc += 1;
+        else counts[pix] += 1;
+    }
+    *escaped += esc;
+    return 0;
+}
+
+int oracle_shoot(const double* lx1, const double* lx2, const double* lm, int64_t n_lens,
+                 double kappa, double gamma, double s,
+                 int64_t n1, int64_t n2, double c1, double c2, double h1, double h2,
+                 int32_t p1, int32_t p2, double w1, double w2, double W1, double W2,
+                 int64_t row_begin, int64_t row_end,
+                 int32_t* counts, int64_t* escaped, int nthreads) {
+    if (!grid_ok(n1, n2, h1, h2) || n_lens < 0) return -1;
+    if (!window_ok(p1, p2, w1, w2, W1, W2)) return -1;
+    if (!isfinite(kappa) || !isfinite(gamma) || !isfinite(s) || !isfinite(c1) || !isfinite(c2)) return -1;
+    if (row_begin < 0 || row_end < row_begin || row_end > n2) return -1;
+    if (n_lens > 0 && (!lx1 || !lx2)) return -1;
+    if (!counts || !escaped) return -1;
+
+    const double kappa_s = s * kappa;
+    const double a1 = (1.0 - gamma) - kappa_s;
+    const double a2 = (1.0 + gamma) - kappa_s;
+    const double d1 = (2.0 * h1) / (double)n1;
+    const double d2 = (2.0 * h2) / (double)n2;
+    const double base1 = c1 - h1;
+    const double base2 = c2 - h2;
+    const double lo1 = w1 - 0.5 * W1;
+    const double lo2 = w2 - 0.5 * W2;
+    const double inv1 = (double)p1 / W1;
+    const double inv2 = (double)p2 / W2;
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+
+    int64_t esc = 0;
+    /* Integer counts are order-free, so the rows can be split across threads
+     * and each increment made atomically without changing the result. */
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads) reduction(+ : esc)
+    for (int64_t j = row_begin; j < row_end; ++j) {
+        const double x2 = base2 + ((double)j + 0.5) * d2;
+        for (int64_t i = 0; i < n1; ++i) {
+            const double x1 = base1 + ((double)i + 0.5) * d1;
+            double y1, y2;
+            int sing = 0;
+            shoot_one(lx1, lx2, lm, n_lens, a1, a2, x1, x2, &y1, &y2, &sing, NULL);
+            const int64_t pix = sing ? -1 : pixel_of(y1, y2, p1, p2, lo1, lo2, inv1, inv2);
+            if (pix < 0) {
+                esc += 1;
+            } else {
+#pragma omp atomic
+                counts[pix] += 1;
+            }
+        }
+    }
+    *escaped += esc;
+    return 0;
+}
+
+/* Eq. 4's N_avg: rays per unit image-plane area times the pixel area, i.e. the
+ * count a pixel receives when nothing deflects the rays. */
+double oracle_n_avg(int64_t n1, int64_t n2, double h1, double h2,
+                    int32_t p1, int32_t p2, double W1, double W2) {
+    const double ray_density = ((double)n1 * (double)n2) / (4.0 * h1 * h2);
+    const double pixel_area = (W1 / (double)p1) * (W2 / (double)p2);
+    return ray_density * pixel_area;
+}
+
+/* Eq. 4: mu_ij = N_ij / N_avg. */
+int oracle_normalise(const int32_t* counts, int64_t n_pix, double n_avg, float* mu) {
+    if (n_pix < 0 || !(n_avg > 0.0) || !isfinite(n_avg)) return -1;
+    if (n_pix > 0 && (!counts || !mu)) return -1;
+    for (int64_t k = 0; k < n_pix; ++k) mu[k] = (float)((double)counts[k] / n_avg);
+    return 0;
+}
+
+int oracle_stats(const int32_t* counts, int64_t n_pix, double n_avg, double kappa, double gamma,
+                 double* out) {
+    if (n_pix <= 0 || !counts || !out || !(n_avg > 0.0)) return -1;
+    int64_t total = 0;
+    for (int64_t k = 0; k < n_pix; ++k) total += counts[k];
+    const double mean_count = (double)total / (double)n_pix;
+    out[0] = (double)total;
+    out[1] = mean_count;
+    out[2] = mean_count / n_avg;
+    /* macro-magnification of the smooth model (Section 4.4, used to place the
+     * probability thresholds): 1 / ((1 - kappa)^2 - gamma^2). */
+    out[3] = 1.0 / ((1.0 - kappa) * (1.0 - kappa) - gamma * gamma);
+    return 0;
+}

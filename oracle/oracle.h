@@ -1,0 +1,67 @@
+/*
+ * Plain FP64 CPU oracle for direct inverse ray-shooting (Vernardos & Fluke 2014,
+ * "Adventures in the microlensing cloud", Section 2.1).
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing on the product path may include, link or
+ * call this code: only the test suite, the smoke check and the CPU-baseline leg
+ * of the benchmark use it. It shares no code, header, table or helper with the
+ * HIP library; both sides implement the paper's equations independently.
+ *
+ * Every routine returns 0 on success and a negative value on invalid arguments.
+ * All pointers are host pointers; the caller owns every buffer.
+ */
+#ifndef RAYSHOOT_ORACLE_H
+#define RAYSHOOT_ORACLE_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Per-ray source-plane positions (eq. 1), for ray rows [row_begin, row_end).
+ * Lens positions lx1/lx2 and masses lm (lm == NULL means unit masses) in units
+ * of the Einstein radius of the mean mass. Rays sit at cell centres of an
+ * n1 x n2 grid covering [c1-h1, c1+h1) x [c2-h2, c2+h2). Outputs are row-major,
+ * x1 fastest, (row_end-row_begin)*n1 entries each. singular[k] is set to 1 when
+ * the ray coincides exactly with a lens (r^2 == 0). rmin (nullable) receives the
+ * distance to the nearest lens. */
+int oracle_ray_positions(const double* lx1, const double* lx2, const double* lm, int64_t n_lens,
+                         double kappa, double gamma, double s,
+                         int64_t n1, int64_t n2, double c1, double c2, double h1, double h2,
+                         int64_t row_begin, int64_t row_end,
+                         double* y1, double* y2, uint8_t* singular, double* rmin);
+
+/* Bins given source-plane positions into a p1 x p2 pixel window of widths
+ * W1 x W2 centred at (w1, w2). Pixels are half-open; counts is row-major
+ * (x1 fastest) and is ACCUMULATED into; *escaped is accumulated too.
+ * singular may be NULL. */
+int oracle_bin(const double* y1, const double* y2, const uint8_t* singular, int64_t n,
+               int32_t p1, int32_t p2, double w1, double w2, double W1, double W2,
+               int32_t* counts, int64_t* escaped);
+
+/* Full shoot of rows [row_begin,row_end): eq. 1 per ray followed by binning.
+ * Accumulates into counts / *escaped. nthreads <= 0 uses the OpenMP default. */
+int oracle_shoot(const double* lx1, const double* lx2, const double* lm, int64_t n_lens,
+                 double kappa, double gamma, double s,
+                 int64_t n1, int64_t n2, double c1, double c2, double h1, double h2,
+                 int32_t p1, int32_t p2, double w1, double w2, double W1, double W2,
+                 int64_t row_begin, int64_t row_end,
+                 int32_t* counts, int64_t* escaped, int nthreads);
+
+/* Rays per pixel in the absence of lensing (eq. 4's N_avg). */
+double oracle_n_avg(int64_t n1, int64_t n2, double h1, double h2,
+                    int32_t p1, int32_t p2, double W1, double W2);
+
+/* mu_ij = N_ij / N_avg (eq. 4), one FP64 division per pixel rounded once to float. */
+int oracle_normalise(const int32_t* counts, int64_t n_pix, double n_avg, float* mu);
+
+/* Map statistics: out[0]=binned (sum of counts), out[1]=mean count, out[2]=mean mu,
+ * out[3]=theoretical macro-magnification 1/((1-kappa)^2-gamma^2). */
+int oracle_stats(const int32_t* counts, int64_t n_pix, double n_avg, double kappa, double gamma,
+                 double* out);
+
+int oracle_max_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
