@@ -1,0 +1,233 @@
+/*
+ * raylens — direct inverse ray-shooting on MI355X (gfx950).
+ *
+ * The method is the brute-force ray-shooting of Vernardos & Fluke 2014
+ * (Section 2.1): every ray of a regular image-plane grid is taken through the
+ * lens equation (eq. 1) with a smooth sheet kappa_s, an external shear gamma
+ * and N_* point masses,
+ *
+ *     y = diag(1 - gamma, 1 + gamma) x - kappa_s x - sum_k m_k (x - x_k) / |x - x_k|^2,
+ *
+ * with kappa_s = s * kappa (eq. 2), and counted on a pixellated source plane;
+ * a pixel's magnification is its count over the count N_avg it would receive
+ * without lensing (eq. 4). A map is defined by (kappa, gamma, s) plus the
+ * lens positions, width and resolution (Section 3.2.1's map-table fields); its
+ * outputs are the int32 ray counts per pixel and the mean count and mean
+ * magnification (the map.bin / mapmeta.dat contents of Section 3.2.1).
+ *
+ * Conventions for every entry point
+ *   - Every call returns rl_status; RL_OK is 0. No C++ exception crosses the
+ *     ABI. On failure rl_last_error() gives a message (thread-local, valid
+ *     until the next rl_* call on the same thread).
+ *   - Every argument is validated on the host before any HIP call is made, so
+ *     an invalid call fails with RL_E_INVALID even on a machine without a GPU.
+ *   - "d_" pointers are device pointers (HIP device memory of the context's
+ *     device); "h_" pointers are host pointers. The caller owns every buffer;
+ *     the library never frees caller memory. Only the context owns memory of
+ *     its own (prepared lens copies, work lists, statistics scratch).
+ *   - Work is enqueued on the given stream (NULL = the default stream) and is
+ *     asynchronous unless stated otherwise. Buffers passed in must stay alive
+ *     until the stream reaches that work.
+ *   - Lengths are in Einstein radii of the mean microlens mass <M> (eq. 5);
+ *     masses are in units of <M>.
+ *   - Layouts: count and magnification maps are row-major p2 x p1 (x1
+ *     fastest, row index = x2 pixel); per-ray outputs are row-major
+ *     (row_end - row_begin) x n1 (x1 fastest).
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef RAYLENS_H
+#define RAYLENS_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RL_OK = 0,
+    RL_E_INVALID = 1,   /* an argument failed validation */
+    RL_E_NOMEM = 2,     /* a device or host allocation failed */
+    RL_E_DEVICE = 3,    /* a HIP call failed (no device, launch error, ...) */
+    RL_E_BUSY = 4,      /* reserved */
+    RL_E_CANCELLED = 5, /* reserved */
+    RL_E_OVERFLOW = 6   /* a pixel count reached INT32_MAX */
+} rl_status;
+
+/* Macro model of eq. 1-2: total convergence kappa, shear gamma (acting along
+ * x1) and smooth-matter fraction s = kappa_s / kappa. kappa_* = (1 - s) kappa
+ * only sets how many point lenses the caller places (eq. 3). All finite. */
+typedef struct {
+    double kappa;
+    double gamma;
+    double s;
+} rl_macro;
+
+/* Regular ray grid (Fig. 1): n1 x n2 rays at the centres of the cells of
+ * [c1 - half1, c1 + half1) x [c2 - half2, c2 + half2), i.e. ray (i, j) sits at
+ * x1 = (c1 - half1) + (i + 1/2) * 2 half1 / n1 and likewise for x2.
+ * n1, n2 > 0; half-widths finite and > 0. */
+typedef struct {
+    int64_t n1;
+    int64_t n2;
+    double c1;
+    double c2;
+    double half1;
+    double half2;
+} rl_raygrid;
+
+/* Source-plane map window: p1 x p2 half-open pixels covering
+ * [c1 - width1/2, c1 + width1/2) x [c2 - width2/2, c2 + width2/2).
+ * p1, p2 > 0; widths finite and > 0. */
+typedef struct {
+    int32_t p1;
+    int32_t p2;
+    double c1;
+    double c2;
+    double width1;
+    double width2;
+} rl_window;
+
+/* Point lenses as a device structure of arrays (the lenspos.dat content of
+ * Section 3.2.1): positions x1[n], x2[n] and masses m[n] in FP64.
+ * m == NULL means unit masses. n >= 0 (n == 0 is a pure sheet); with n > 0
+ * x1 and x2 must be non-NULL. */
+typedef struct {
+    const double* x1;
+    const double* x2;
+    const double* m;
+    int64_t n;
+} rl_lenses;
+
+typedef enum {
+    /* Deflection sum in FP32 with lens coordinates rebased to per-cell
+     * origins and blocked TwoSum compensation; FP64 only for the final
+     * y = a x - alpha and the binning. */
+    RL_FP32_COMP = 0,
+    /* Everything in FP64 in the oracle's operation order (bit-identical to a
+     * plain sequential FP64 evaluation of eq. 1 with no contraction). */
+    RL_FP64_PLAIN = 1
+} rl_precision;
+
+/* Map statistics (mapmeta.dat of Section 3.2.1, eq. 4). */
+typedef struct {
+    int64_t shot;        /* rays shot (rows x n1 over the rows given) */
+    int64_t binned;      /* sum of all pixel counts */
+    int64_t escaped;     /* rays outside the window or singular */
+    double n_avg;        /* unlensed rays per pixel, eq. 4 */
+    double mean_count;   /* <N> = binned / (p1 p2) */
+    double mean_mu;      /* <mu> = <N> / N_avg */
+    double mu_th;        /* 1 / ((1 - kappa)^2 - gamma^2), signed */
+    int32_t max_count;   /* largest pixel count */
+} rl_stats;
+
+typedef struct rl_context rl_context;
+
+/* Creates a context bound to HIP device `hip_device`. No HIP call is made
+ * here; the device is touched on first use, so creation never fails for
+ * want of a GPU. *out receives the context. */
+rl_status rl_create(int32_t hip_device, rl_context** out);
+
+/* Releases the context and the device memory it owns. NULL is accepted. */
+rl_status rl_destroy(rl_context* ctx);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* rl_last_error(void);
+
+/* Library version string. */
+const char* rl_version(void);
+
+/* N_avg of eq. 4 (rays per pixel without lensing) for a grid and window:
+ * (n1 n2 / (4 half1 half2)) * (width1 / p1) * (width2 / p2). Host only. */
+rl_status rl_n_avg(const rl_raygrid* grid, const rl_window* win, double* h_out);
+
+/* Shoots ray rows [row_begin, row_end) (0 <= row_begin <= row_end <= n2)
+ * through eq. 1 and ACCUMULATES them into the caller-zeroed count map
+ * d_counts (int32, p2 x p1) and the escaped counter *d_escaped (int64).
+ * Calling it with [0, n2) shoots one whole map; disjoint row ranges add up
+ * exactly to the whole map. A ray is binned iff 0 <= (y - lo) P / W < P on
+ * both axes (lo = window centre - width/2); rays outside, with a non-finite
+ * position, or exactly on a lens are escaped. Asynchronous on `stream`. */
+rl_status rl_shoot(rl_context* ctx, const rl_lenses* lenses, const rl_macro* macro,
+                   const rl_raygrid* grid, const rl_window* win, rl_precision precision,
+                   int64_t row_begin, int64_t row_end,
+                   int32_t* d_counts, int64_t* d_escaped, hipStream_t stream);
+
+/* Eq. 4: d_mu[k] = (float)((double)d_counts[k] / n_avg) for the p1 x p2
+ * pixels of `win`. n_avg finite and > 0. Asynchronous. */
+rl_status rl_normalise(rl_context* ctx, const int32_t* d_counts, const rl_window* win,
+                       double n_avg, float* d_mu, hipStream_t stream);
+
+/* Statistics of a finished map (rows [0, n2) shot once). Synchronises the
+ * stream. Returns RL_E_OVERFLOW (with *h_out filled) if a pixel count reached
+ * INT32_MAX. */
+rl_status rl_stats_get(rl_context* ctx, const int32_t* d_counts, const int64_t* d_escaped,
+                       const rl_macro* macro, const rl_raygrid* grid, const rl_window* win,
+                       rl_stats* h_out, hipStream_t stream);
+
+/* Parity hook for the binning step alone: bins n given FP64 source-plane
+ * positions d_y1[n], d_y2[n] with the rule of rl_shoot, accumulating into
+ * d_counts and *d_escaped. n >= 0. Asynchronous. */
+rl_status rl_bin_positions(rl_context* ctx, const double* d_y1, const double* d_y2, int64_t n,
+                           const rl_window* win, int32_t* d_counts, int64_t* d_escaped,
+                           hipStream_t stream);
+
+/* Parity hook for eq. 1 alone: writes the FP64 source-plane position of every
+ * ray of rows [row_begin, row_end) to d_y1, d_y2 (row-major, (row_end -
+ * row_begin) x n1 each), computed exactly as rl_shoot computes it for the
+ * given precision. Asynchronous. */
+rl_status rl_ray_positions(rl_context* ctx, const rl_lenses* lenses, const rl_macro* macro,
+                           const rl_raygrid* grid, rl_precision precision,
+                           int64_t row_begin, int64_t row_end,
+                           double* d_y1, double* d_y2, hipStream_t stream);
+
+/* One map of a batch: its own lenses, macro model, grid, window, row range and
+ * (caller-zeroed) outputs. Pointers inside are device pointers. */
+typedef struct {
+    rl_lenses lenses;
+    rl_macro macro;
+    rl_raygrid grid;
+    rl_window win;
+    int64_t row_begin;
+    int64_t row_end;
+    int32_t* d_counts;
+    int64_t* d_escaped;
+} rl_map_desc;
+
+/* Shoots every map of h_maps[0 .. n_maps-1] (host array of descriptors) in
+ * ONE persistent launch: workgroups pull (map, ray-cell range) items from a
+ * shared counter until the list is empty, so maps of uneven lens counts and
+ * sizes share the GPU. Results equal per-map rl_shoot calls bit for bit.
+ * n_maps >= 0. Asynchronous; the descriptors are copied before return. */
+rl_status rl_shoot_batch(rl_context* ctx, const rl_map_desc* h_maps, int32_t n_maps,
+                         rl_precision precision, hipStream_t stream);
+
+/* Kernel shape. None of these knobs changes any result bit: they only decide
+ * how rays are spread over lanes and waves and how lenses are staged.
+ *   rays_x, rays_y : rays per lane along x1 and x2 (product 16: 4x4, 2x8, 8x2)
+ *   lens_tile      : lenses staged in LDS per pass (multiple of 128, <= 2048)
+ *   waves          : waves per workgroup (1, 2 or 4)
+ *   submap         : 1 = bin through an LDS-privatised sub-map, 0 = global atomics
+ *   item_cells     : ray cells per work item in rl_shoot_batch (>= 1) */
+typedef struct {
+    int32_t rays_x;
+    int32_t rays_y;
+    int32_t lens_tile;
+    int32_t waves;
+    int32_t submap;
+    int32_t item_cells;
+} rl_tuning;
+
+/* Reads / sets the kernel shape used for `precision` and lens-count class
+ * `n_class` (0: n < 1000, 1: n < 10000, 2: n >= 10000). Host only. */
+rl_status rl_get_tuning(rl_context* ctx, rl_precision precision, int32_t n_class,
+                        rl_tuning* h_out);
+rl_status rl_set_tuning(rl_context* ctx, rl_precision precision, int32_t n_class,
+                        const rl_tuning* h_tuning);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RAYLENS_H */

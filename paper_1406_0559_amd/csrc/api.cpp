@@ -1,0 +1,639 @@
+// C-ABI of the raylens library: argument validation, per-map parameter
+// records, the context's scratch memory, batching work lists and statistics.
+// The declarations and their contracts are in include/raylens.h.
+#include "raylens.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace {
+
+thread_local std::string g_error;
+
+rl_status fail(rl_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return st;
+}
+
+rl_status hip_fail(hipError_t e, const char* what) {
+    return fail(e == hipErrorOutOfMemory ? RL_E_NOMEM : RL_E_DEVICE, "%s: %s", what,
+                hipGetErrorString(e));
+}
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+// ---------------------------------------------------------------------------
+// validation (host only, before any HIP call)
+// ---------------------------------------------------------------------------
+
+rl_status check_grid(const rl_raygrid* g) {
+    if (!g) return fail(RL_E_INVALID, "ray grid is NULL");
+    if (g->n1 <= 0 || g->n2 <= 0) return fail(RL_E_INVALID, "ray grid needs n1, n2 > 0");
+    if (g->n1 > (int64_t)1 << 40 || g->n2 > (int64_t)1 << 40)
+        return fail(RL_E_INVALID, "ray grid too large");
+    if (!is_finite(g->c1) || !is_finite(g->c2)) return fail(RL_E_INVALID, "ray grid centre not finite");
+    if (!is_finite(g->half1) || !is_finite(g->half2) || !(g->half1 > 0.0) || !(g->half2 > 0.0))
+        return fail(RL_E_INVALID, "ray grid half-widths must be finite and > 0");
+    return RL_OK;
+}
+
+rl_status check_window(const rl_window* w) {
+    if (!w) return fail(RL_E_INVALID, "window is NULL");
+    if (w->p1 <= 0 || w->p2 <= 0) return fail(RL_E_INVALID, "window needs p1, p2 > 0");
+    if (!is_finite(w->c1) || !is_finite(w->c2)) return fail(RL_E_INVALID, "window centre not finite");
+    if (!is_finite(w->width1) || !is_finite(w->width2) || !(w->width1 > 0.0) || !(w->width2 > 0.0))
+        return fail(RL_E_INVALID, "window widths must be finite and > 0");
+    return RL_OK;
+}
+
+rl_status check_macro(const rl_macro* m) {
+    if (!m) return fail(RL_E_INVALID, "macro model is NULL");
+    if (!is_finite(m->kappa) || !is_finite(m->gamma) || !is_finite(m->s))
+        return fail(RL_E_INVALID, "kappa, gamma and s must be finite");
+    return RL_OK;
+}
+
+rl_status check_lenses(const rl_lenses* l) {
+    if (!l) return fail(RL_E_INVALID, "lenses is NULL");
+    if (l->n < 0) return fail(RL_E_INVALID, "lens count must be >= 0");
+    if (l->n > ((int64_t)1 << 31)) return fail(RL_E_INVALID, "lens count too large");
+    if (l->n > 0 && (!l->x1 || !l->x2)) return fail(RL_E_INVALID, "lens positions are NULL");
+    return RL_OK;
+}
+
+rl_status check_precision(rl_precision p) {
+    if (p != RL_FP32_COMP && p != RL_FP64_PLAIN) return fail(RL_E_INVALID, "unknown precision");
+    return RL_OK;
+}
+
+rl_status check_rows(const rl_raygrid* g, int64_t rb, int64_t re) {
+    if (rb < 0 || re < rb || re > g->n2)
+        return fail(RL_E_INVALID, "row range [%lld, %lld) outside [0, %lld]", (long long)rb,
+                    (long long)re, (long long)g->n2);
+    return RL_OK;
+}
+
+#define RL_TRY(expr)                      \
+    do {                                  \
+        rl_status st_ = (expr);           \
+        if (st_ != RL_OK) return st_;     \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// parameter records
+// ---------------------------------------------------------------------------
+
+// Cell shape: 1024 rays, cx x cy with cx*d1 ~ cy*d2 (square on the sky), cx a
+// power of two in [8, 128]. Depends only on the grid.
+void cell_shape(double d1, double d2, int32_t* cx, int32_t* cy) {
+    const int cands[5] = {8, 16, 32, 64, 128};
+    int best = 32;
+    double best_err = 1e300;
+    for (int c : cands) {
+        const double ext1 = c * d1, ext2 = (double)(rl::kCellRays / c) * d2;
+        const double err = std::fabs(std::log(ext1 / ext2));
+        if (err < best_err - 1e-12) { best_err = err; best = c; }
+    }
+    *cx = best;
+    *cy = rl::kCellRays / best;
+}
+
+void build_params(const rl_macro* M, const rl_raygrid* G, const rl_window* W, int64_t rb,
+                  int64_t re, rl::MapParams* P) {
+    std::memset(P, 0, sizeof(*P));
+    P->n1 = G->n1;
+    P->n2 = G->n2;
+    // ray (i, j) at base + (i + 1/2) d, d = 2 h / n (cell centres)
+    P->base1 = G->c1 - G->half1;
+    P->base2 = G->c2 - G->half2;
+    P->d1 = (2.0 * G->half1) / (double)G->n1;
+    P->d2 = (2.0 * G->half2) / (double)G->n2;
+    P->d1f = (float)P->d1;
+    P->d2f = (float)P->d2;
+    cell_shape(P->d1, P->d2, &P->cx, &P->cy);
+    P->cells_x = (G->n1 + P->cx - 1) / P->cx;
+    P->row_begin = rb;
+    P->row_end = re;
+    if (re > rb) {
+        P->cell_row0 = rb / P->cy;
+        const int64_t last = (re - 1) / P->cy;
+        P->n_cells = (last - P->cell_row0 + 1) * P->cells_x;
+    } else {
+        P->cell_row0 = 0;
+        P->n_cells = 0;
+    }
+    // eq. 1 with kappa_s = s kappa (eq. 2): diag(1 - gamma, 1 + gamma) - kappa_s
+    const double kappa_s = M->s * M->kappa;
+    P->a1 = (1.0 - M->gamma) - kappa_s;
+    P->a2 = (1.0 + M->gamma) - kappa_s;
+    // half-open pixels from lo = centre - width / 2, u = (y - lo) * p / width
+    P->p1 = W->p1;
+    P->p2 = W->p2;
+    P->lo1 = W->c1 - 0.5 * W->width1;
+    P->lo2 = W->c2 - 0.5 * W->width2;
+    P->inv1 = (double)W->p1 / W->width1;
+    P->inv2 = (double)W->p2 / W->width2;
+}
+
+int n_class(int64_t n) { return n < 1000 ? 0 : (n < 10000 ? 1 : 2); }
+
+// RAII: make the context's device current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    hipError_t err = hipSuccess;
+    explicit DeviceGuard(int dev) {
+        err = hipGetDevice(&prev);
+        if (err != hipSuccess) { ok = false; return; }
+        if (prev != dev) {
+            err = hipSetDevice(dev);
+            if (err != hipSuccess) ok = false;
+        }
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (ok && hipGetDevice(&cur) == hipSuccess && cur != prev && prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+// Device scratch reused across calls in stream order: a new user waits (on the
+// GPU) for the previous user's work before touching it.
+struct Scratch {
+    void* ptr = nullptr;
+    size_t cap = 0;
+    hipEvent_t last = nullptr;
+    bool used = false;
+
+    hipError_t acquire(size_t bytes, hipStream_t s) {
+        hipError_t e;
+        if (!last) {
+            e = hipEventCreateWithFlags(&last, hipEventDisableTiming);
+            if (e != hipSuccess) return e;
+        }
+        if (used) {
+            e = hipStreamWaitEvent(s, last, 0);
+            if (e != hipSuccess) return e;
+        }
+        if (cap < bytes) {
+            if (ptr) {
+                e = hipDeviceSynchronize();
+                if (e != hipSuccess) return e;
+                e = hipFree(ptr);
+                if (e != hipSuccess) return e;
+                ptr = nullptr;
+                cap = 0;
+            }
+            size_t want = std::max<size_t>(bytes, 1 << 16);
+            want = (want + 4095) & ~(size_t)4095;
+            e = hipMalloc(&ptr, want);
+            if (e != hipSuccess) { ptr = nullptr; return e; }
+            cap = want;
+        }
+        return hipSuccess;
+    }
+    hipError_t release(hipStream_t s) {
+        used = true;
+        return hipEventRecord(last, s);
+    }
+    void destroy() {
+        if (ptr) (void)hipFree(ptr);
+        if (last) (void)hipEventDestroy(last);
+        ptr = nullptr;
+        last = nullptr;
+    }
+};
+
+}  // namespace
+
+struct rl_context {
+    int device = 0;
+    bool ready = false;
+    int num_cus = 256;
+    Scratch lens;        // FP32 lens copies
+    Scratch batch;       // map records + work items + counter
+    Scratch stats;       // reduction outputs
+    void* host_stage = nullptr;  // pinned staging for batch records
+    size_t host_cap = 0;
+    hipEvent_t stage_done = nullptr;
+    bool stage_used = false;
+    rl::KernelShape tuning[2][3];
+};
+
+namespace {
+
+rl_status ensure_ready(rl_context* ctx) {
+    if (ctx->ready) return RL_OK;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n <= 0) return fail(RL_E_DEVICE, "no HIP device available");
+    if (ctx->device >= n) return fail(RL_E_DEVICE, "device %d not present (%d devices)", ctx->device, n);
+    int cus = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+    ctx->num_cus = cus > 0 ? cus : 256;
+    e = hipEventCreateWithFlags(&ctx->stage_done, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    ctx->ready = true;
+    return RL_OK;
+}
+
+// Prepares FP32 hi/lo lens copies in the context's lens scratch.
+rl_status prepare_lenses_f32(rl_context* ctx, const rl_lenses* L, bool force_mass,
+                             rl::MapParams* P, hipStream_t s) {
+    const int64_t n = L->n;
+    const bool masses = L->m != nullptr || force_mass;
+    const size_t bytes = (size_t)std::max<int64_t>(n, 1) * (sizeof(float4) + sizeof(float));
+    hipError_t e = ctx->lens.acquire(bytes, s);
+    if (e != hipSuccess) return hip_fail(e, "lens scratch");
+    float4* xy = static_cast<float4*>(ctx->lens.ptr);
+    float* mf = reinterpret_cast<float*>(xy + std::max<int64_t>(n, 1));
+    e = rl::launch_prep_lenses(L->x1, L->x2, L->m, n, xy, masses ? mf : nullptr, true, s);
+    if (e != hipSuccess) return hip_fail(e, "prep_lenses launch");
+    P->lens32 = xy;
+    P->mass32 = masses ? mf : nullptr;
+    P->n_lens = n;
+    return RL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rl_last_error(void) { return g_error.c_str(); }
+
+const char* rl_version(void) { return "raylens 0.1 (gfx950)"; }
+
+rl_status rl_create(int32_t hip_device, rl_context** out) {
+    g_error.clear();
+    if (!out) return fail(RL_E_INVALID, "out is NULL");
+    if (hip_device < 0) return fail(RL_E_INVALID, "device index must be >= 0");
+    rl_context* c = new (std::nothrow) rl_context();
+    if (!c) return fail(RL_E_NOMEM, "context allocation failed");
+    c->device = hip_device;
+    for (int p = 0; p < 2; ++p)
+        for (int k = 0; k < 3; ++k)
+            c->tuning[p][k] = rl::KernelShape{4, 4, 256, 4, 1, 16};
+    *out = c;
+    return RL_OK;
+}
+
+rl_status rl_destroy(rl_context* ctx) {
+    g_error.clear();
+    if (!ctx) return RL_OK;
+    if (ctx->ready) {
+        DeviceGuard dg(ctx->device);
+        (void)hipDeviceSynchronize();
+        ctx->lens.destroy();
+        ctx->batch.destroy();
+        ctx->stats.destroy();
+        if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
+        if (ctx->stage_done) (void)hipEventDestroy(ctx->stage_done);
+    }
+    delete ctx;
+    return RL_OK;
+}
+
+rl_status rl_n_avg(const rl_raygrid* grid, const rl_window* win, double* h_out) {
+    g_error.clear();
+    RL_TRY(check_grid(grid));
+    RL_TRY(check_window(win));
+    if (!h_out) return fail(RL_E_INVALID, "h_out is NULL");
+    // eq. 4's N_avg: unlensed ray density times the pixel area
+    const double ray_density = ((double)grid->n1 * (double)grid->n2) / (4.0 * grid->half1 * grid->half2);
+    const double pixel_area = (win->width1 / (double)win->p1) * (win->width2 / (double)win->p2);
+    *h_out = ray_density * pixel_area;
+    return RL_OK;
+}
+
+rl_status rl_get_tuning(rl_context* ctx, rl_precision precision, int32_t n_cls, rl_tuning* h_out) {
+    g_error.clear();
+    if (!ctx) return fail(RL_E_INVALID, "context is NULL");
+    RL_TRY(check_precision(precision));
+    if (n_cls < 0 || n_cls > 2) return fail(RL_E_INVALID, "lens-count class must be 0, 1 or 2");
+    if (!h_out) return fail(RL_E_INVALID, "h_out is NULL");
+    const rl::KernelShape& k = ctx->tuning[precision][n_cls];
+    *h_out = rl_tuning{k.rays_x, k.rays_y, k.lens_tile, k.waves, k.submap, k.item_cells};
+    return RL_OK;
+}
+
+rl_status rl_set_tuning(rl_context* ctx, rl_precision precision, int32_t n_cls, const rl_tuning* t) {
+    g_error.clear();
+    if (!ctx) return fail(RL_E_INVALID, "context is NULL");
+    RL_TRY(check_precision(precision));
+    if (n_cls < 0 || n_cls > 2) return fail(RL_E_INVALID, "lens-count class must be 0, 1 or 2");
+    if (!t) return fail(RL_E_INVALID, "tuning is NULL");
+    rl::KernelShape k{t->rays_x, t->rays_y, t->lens_tile, t->waves, t->submap, t->item_cells};
+    if (!rl::shape_supported((rl::Precision)precision, k))
+        return fail(RL_E_INVALID, "unsupported kernel shape (%d x %d rays, tile %d, %d waves, submap %d, item %d)",
+                    k.rays_x, k.rays_y, k.lens_tile, k.waves, k.submap, k.item_cells);
+    ctx->tuning[precision][n_cls] = k;
+    return RL_OK;
+}
+
+rl_status rl_shoot(rl_context* ctx, const rl_lenses* lenses, const rl_macro* macro,
+                   const rl_raygrid* grid, const rl_window* win, rl_precision precision,
+                   int64_t row_begin, int64_t row_end, int32_t* d_counts, int64_t* d_escaped,
+                   hipStream_t stream) {
+    g_error.clear();
+    if (!ctx) return fail(RL_E_INVALID, "context is NULL");
+    RL_TRY(check_lenses(lenses));
+    RL_TRY(check_macro(macro));
+    RL_TRY(check_grid(grid));
+    RL_TRY(check_window(win));
+    RL_TRY(check_precision(precision));
+    RL_TRY(check_rows(grid, row_begin, row_end));
+    if (!d_counts || !d_escaped) return fail(RL_E_INVALID, "output pointers are NULL");
+    if (row_end == row_begin) return RL_OK;
+
+    rl::MapParams P;
+    build_params(macro, grid, win, row_begin, row_end, &P);
+    P.counts = d_counts;
+    P.escaped = reinterpret_cast<unsigned long long*>(d_escaped);
+
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return hip_fail(dg.err, "hipSetDevice");
+    RL_TRY(ensure_ready(ctx));
+    const rl::KernelShape& ks = ctx->tuning[precision][n_class(lenses->n)];
+    hipError_t e;
+    if (precision == RL_FP32_COMP) {
+        RL_TRY(prepare_lenses_f32(ctx, lenses, false, &P, stream));
+        e = rl::launch_shoot(P, rl::kFP32Comp, ks, false, ctx->num_cus, stream);
+        hipError_t e2 = ctx->lens.release(stream);
+        if (e == hipSuccess) e = e2;
+    } else {
+        P.lx1 = lenses->x1;
+        P.lx2 = lenses->x2;
+        P.lm = lenses->m;
+        P.n_lens = lenses->n;
+        e = rl::launch_shoot(P, rl::kFP64Plain, ks, false, ctx->num_cus, stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "shoot launch");
+    return RL_OK;
+}
+
+rl_status rl_ray_positions(rl_context* ctx, const rl_lenses* lenses, const rl_macro* macro,
+                           const rl_raygrid* grid, rl_precision precision, int64_t row_begin,
+                           int64_t row_end, double* d_y1, double* d_y2, hipStream_t stream) {
+    g_error.clear();
+    if (!ctx) return fail(RL_E_INVALID, "context is NULL");
+    RL_TRY(check_lenses(lenses));
+    RL_TRY(check_macro(macro));
+    RL_TRY(check_grid(grid));
+    RL_TRY(check_precision(precision));
+    RL_TRY(check_rows(grid, row_begin, row_end));
+    if (!d_y1 || !d_y2) return fail(RL_E_INVALID, "output pointers are NULL");
+    if (row_end == row_begin) return RL_OK;
+
+    rl_window dummy{1, 1, 0.0, 0.0, 1.0, 1.0};
+    rl::MapParams P;
+    build_params(macro, grid, &dummy, row_begin, row_end, &P);
+    P.out_y1 = d_y1;
+    P.out_y2 = d_y2;
+
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return hip_fail(dg.err, "hipSetDevice");
+    RL_TRY(ensure_ready(ctx));
+    rl::KernelShape ks = ctx->tuning[precision][n_class(lenses->n)];
+    hipError_t e;
+    if (precision == RL_FP32_COMP) {
+        RL_TRY(prepare_lenses_f32(ctx, lenses, false, &P, stream));
+        e = rl::launch_shoot(P, rl::kFP32Comp, ks, true, ctx->num_cus, stream);
+        hipError_t e2 = ctx->lens.release(stream);
+        if (e == hipSuccess) e = e2;
+    } else {
+        P.lx1 = lenses->x1;
+        P.lx2 = lenses->x2;
+        P.lm = lenses->m;
+        P.n_lens = lenses->n;
+        e = rl::launch_shoot(P, rl::kFP64Plain, ks, true, ctx->num_cus, stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "ray_positions launch");
+    return RL_OK;
+}
+
+rl_status rl_bin_positions(rl_context* ctx, const double* d_y1, const double* d_y2, int64_t n,
+                           const rl_window* win, int32_t* d_counts, int64_t* d_escaped,
+                           hipStream_t stream) {
+    g_error.clear();
+    if (!ctx) return fail(RL_E_INVALID, "context is NULL");
+    if (n < 0) return fail(RL_E_INVALID, "n must be >= 0");
+    RL_TRY(check_window(win));
+    if (n > 0 && (!d_y1 || !d_y2)) return fail(RL_E_INVALID, "position pointers are NULL");
+    if (!d_counts || !d_escaped) return fail(RL_E_INVALID, "output pointers are NULL");
+    if (n == 0) return RL_OK;
+    const double lo1 = win->c1 - 0.5 * win->width1;
+    const double lo2 = win->c2 - 0.5 * win->width2;
+    const double inv1 = (double)win->p1 / win->width1;
+    const double inv2 = (double)win->p2 / win->width2;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return hip_fail(dg.err, "hipSetDevice");
+    RL_TRY(ensure_ready(ctx));
+    hipError_t e = rl::launch_bin_positions(d_y1, d_y2, n, win->p1, win->p2, lo1, lo2, inv1, inv2,
+                                            d_counts, reinterpret_cast<unsigned long long*>(d_escaped),
+                                            stream);
+    if (e != hipSuccess) return hip_fail(e, "bin_positions launch");
+    return RL_OK;
+}
+
+rl_status rl_normalise(rl_context* ctx, const int32_t* d_counts, const rl_window* win,
+                       double n_avg, float* d_mu, hipStream_t stream) {
+    g_error.clear();
+    if (!ctx) return fail(RL_E_INVALID, "context is NULL");
+    RL_TRY(check_window(win));
+    if (!is_finite(n_avg) || !(n_avg > 0.0)) return fail(RL_E_INVALID, "n_avg must be finite and > 0");
+    if (!d_counts || !d_mu) return fail(RL_E_INVALID, "buffer pointers are NULL");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return hip_fail(dg.err, "hipSetDevice");
+    RL_TRY(ensure_ready(ctx));
+    hipError_t e = rl::launch_normalise(d_counts, (int64_t)win->p1 * win->p2, n_avg, d_mu, stream);
+    if (e != hipSuccess) return hip_fail(e, "normalise launch");
+    return RL_OK;
+}
+
+rl_status rl_stats_get(rl_context* ctx, const int32_t* d_counts, const int64_t* d_escaped,
+                       const rl_macro* macro, const rl_raygrid* grid, const rl_window* win,
+                       rl_stats* h_out, hipStream_t stream) {
+    g_error.clear();
+    if (!ctx) return fail(RL_E_INVALID, "context is NULL");
+    RL_TRY(check_macro(macro));
+    RL_TRY(check_grid(grid));
+    RL_TRY(check_window(win));
+    if (!d_counts || !d_escaped || !h_out) return fail(RL_E_INVALID, "pointers are NULL");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return hip_fail(dg.err, "hipSetDevice");
+    RL_TRY(ensure_ready(ctx));
+    hipError_t e = ctx->stats.acquire(4 * sizeof(unsigned long long), stream);
+    if (e != hipSuccess) return hip_fail(e, "stats scratch");
+    unsigned long long* acc = static_cast<unsigned long long*>(ctx->stats.ptr);
+    e = rl::launch_fill_u32(reinterpret_cast<unsigned int*>(acc), 8, 0u, stream);
+    if (e == hipSuccess)
+        e = rl::launch_count_stats(d_counts, (int64_t)win->p1 * win->p2, acc, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(acc + 2, d_escaped, sizeof(int64_t), hipMemcpyDeviceToDevice, stream);
+    unsigned long long host[3] = {0, 0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(host, acc, sizeof(host), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    hipError_t e2 = ctx->stats.release(stream);
+    if (e == hipSuccess) e = e2;
+    if (e != hipSuccess) return hip_fail(e, "stats");
+    double n_avg = 0.0;
+    RL_TRY(rl_n_avg(grid, win, &n_avg));
+    rl_stats st;
+    st.shot = grid->n1 * grid->n2;
+    st.binned = (int64_t)host[0];
+    st.escaped = (int64_t)host[2];
+    st.n_avg = n_avg;
+    st.mean_count = (double)st.binned / ((double)win->p1 * (double)win->p2);
+    st.mean_mu = st.mean_count / n_avg;
+    const double k1 = 1.0 - macro->kappa;
+    st.mu_th = 1.0 / (k1 * k1 - macro->gamma * macro->gamma);
+    st.max_count = (int32_t)host[1];
+    *h_out = st;
+    if ((int64_t)host[1] >= INT32_MAX) return fail(RL_E_OVERFLOW, "a pixel count reached INT32_MAX");
+    return RL_OK;
+}
+
+rl_status rl_shoot_batch(rl_context* ctx, const rl_map_desc* h_maps, int32_t n_maps,
+                         rl_precision precision, hipStream_t stream) {
+    g_error.clear();
+    if (!ctx) return fail(RL_E_INVALID, "context is NULL");
+    if (n_maps < 0) return fail(RL_E_INVALID, "n_maps must be >= 0");
+    if (n_maps > 0 && !h_maps) return fail(RL_E_INVALID, "maps is NULL");
+    RL_TRY(check_precision(precision));
+    for (int32_t i = 0; i < n_maps; ++i) {
+        const rl_map_desc& d = h_maps[i];
+        rl_status st;
+        if ((st = check_lenses(&d.lenses)) != RL_OK || (st = check_macro(&d.macro)) != RL_OK ||
+            (st = check_grid(&d.grid)) != RL_OK || (st = check_window(&d.win)) != RL_OK ||
+            (st = check_rows(&d.grid, d.row_begin, d.row_end)) != RL_OK) {
+            std::string m = g_error;
+            return fail(st, "map %d: %s", (int)i, m.c_str());
+        }
+        if (!d.d_counts || !d.d_escaped) return fail(RL_E_INVALID, "map %d: output pointers are NULL", (int)i);
+    }
+    if (n_maps == 0) return RL_OK;
+
+    // kernel shape: the class of the largest lens count in the batch
+    int64_t nmax = 0;
+    bool masses = false;
+    int64_t total_lens = 0;
+    for (int32_t i = 0; i < n_maps; ++i) {
+        nmax = std::max(nmax, h_maps[i].lenses.n);
+        masses = masses || h_maps[i].lenses.m != nullptr;
+        total_lens += h_maps[i].lenses.n;
+    }
+    const rl::KernelShape ks = ctx->tuning[precision][n_class(nmax)];
+
+    std::vector<rl::MapParams> params((size_t)n_maps);
+    std::vector<rl::WorkItem> items;
+    std::vector<double> cost;
+    for (int32_t i = 0; i < n_maps; ++i) {
+        const rl_map_desc& d = h_maps[i];
+        build_params(&d.macro, &d.grid, &d.win, d.row_begin, d.row_end, &params[i]);
+        params[i].counts = d.d_counts;
+        params[i].escaped = reinterpret_cast<unsigned long long*>(d.d_escaped);
+        params[i].n_lens = d.lenses.n;
+        for (int64_t c = 0; c < params[i].n_cells; c += ks.item_cells) {
+            const int64_t nc = std::min<int64_t>(ks.item_cells, params[i].n_cells - c);
+            items.push_back(rl::WorkItem{i, 0, c, nc});
+        }
+    }
+    if (items.empty()) return RL_OK;
+    // most expensive items first so the tail of the launch is made of cheap ones
+    std::vector<size_t> order(items.size());
+    for (size_t k = 0; k < order.size(); ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+        const double ca = (double)(params[items[a].map].n_lens + 8) * items[a].ncells;
+        const double cb = (double)(params[items[b].map].n_lens + 8) * items[b].ncells;
+        return ca > cb;
+    });
+    std::vector<rl::WorkItem> sorted(items.size());
+    for (size_t k = 0; k < order.size(); ++k) sorted[k] = items[order[k]];
+
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return hip_fail(dg.err, "hipSetDevice");
+    RL_TRY(ensure_ready(ctx));
+    hipError_t e;
+
+    // FP32 lens copies for every map, one region per map
+    if (precision == RL_FP32_COMP) {
+        const size_t bytes = (size_t)std::max<int64_t>(total_lens, 1) * (sizeof(float4) + sizeof(float));
+        e = ctx->lens.acquire(bytes, stream);
+        if (e != hipSuccess) return hip_fail(e, "lens scratch");
+        float4* xy = static_cast<float4*>(ctx->lens.ptr);
+        float* mf = reinterpret_cast<float*>(xy + std::max<int64_t>(total_lens, 1));
+        int64_t off = 0;
+        for (int32_t i = 0; i < n_maps; ++i) {
+            const rl_lenses& L = h_maps[i].lenses;
+            e = rl::launch_prep_lenses(L.x1, L.x2, L.m, L.n, xy + off, masses ? mf + off : nullptr, true,
+                                       stream);
+            if (e != hipSuccess) return hip_fail(e, "prep_lenses launch");
+            params[i].lens32 = xy + off;
+            params[i].mass32 = masses ? mf + off : nullptr;
+            off += L.n;
+        }
+    } else {
+        for (int32_t i = 0; i < n_maps; ++i) {
+            params[i].lx1 = h_maps[i].lenses.x1;
+            params[i].lx2 = h_maps[i].lenses.x2;
+            params[i].lm = h_maps[i].lenses.m;
+        }
+    }
+
+    // records: [MapParams x n][WorkItem x n_items][counter]
+    const size_t pbytes = sizeof(rl::MapParams) * (size_t)n_maps;
+    const size_t ioff = (pbytes + 255) & ~(size_t)255;
+    const size_t ibytes = sizeof(rl::WorkItem) * sorted.size();
+    const size_t coff = (ioff + ibytes + 255) & ~(size_t)255;
+    const size_t total = coff + 256;
+    if (ctx->stage_used) {
+        e = hipEventSynchronize(ctx->stage_done);
+        if (e != hipSuccess) return hip_fail(e, "staging wait");
+    }
+    if (ctx->host_cap < total) {
+        if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
+        ctx->host_stage = nullptr;
+        ctx->host_cap = 0;
+        e = hipHostMalloc(&ctx->host_stage, total, hipHostMallocDefault);
+        if (e != hipSuccess) { ctx->host_stage = nullptr; return hip_fail(e, "pinned staging"); }
+        ctx->host_cap = total;
+    }
+    char* hs = static_cast<char*>(ctx->host_stage);
+    std::memset(hs, 0, total);
+    std::memcpy(hs, params.data(), pbytes);
+    std::memcpy(hs + ioff, sorted.data(), ibytes);
+    e = ctx->batch.acquire(total, stream);
+    if (e != hipSuccess) return hip_fail(e, "batch scratch");
+    char* ds = static_cast<char*>(ctx->batch.ptr);
+    e = hipMemcpyAsync(ds, hs, total, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return hip_fail(e, "batch records copy");
+    e = hipEventRecord(ctx->stage_done, stream);
+    if (e != hipSuccess) return hip_fail(e, "staging event");
+    ctx->stage_used = true;
+
+    e = rl::launch_shoot_batch(reinterpret_cast<const rl::MapParams*>(ds),
+                               reinterpret_cast<const rl::WorkItem*>(ds + ioff),
+                               (int64_t)sorted.size(), reinterpret_cast<unsigned int*>(ds + coff),
+                               (rl::Precision)precision, masses, ks, ctx->num_cus, stream);
+    hipError_t e2 = ctx->batch.release(stream);
+    hipError_t e3 = precision == RL_FP32_COMP ? ctx->lens.release(stream) : hipSuccess;
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = e3;
+    if (e != hipSuccess) return hip_fail(e, "batch launch");
+    return RL_OK;
+}
+
+}  // extern "C"

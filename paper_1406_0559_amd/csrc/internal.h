@@ -1,0 +1,95 @@
+// Internal declarations shared by the kernels (kernels.hip) and the C-ABI
+// layer (api.cpp) of the raylens library. Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rl {
+
+// Rays per origin cell and per wave: one wave of 64 lanes holds 16 rays per
+// lane. A cell is the unit whose centre the FP32 lens coordinates are
+// rebased to; its shape depends only on the ray grid, so no kernel-shape
+// knob changes a result bit.
+constexpr int kLanes = 64;
+constexpr int kRaysPerLane = 16;
+constexpr int kCellRays = kLanes * kRaysPerLane;
+// Lenses per compensation block: each block is summed in plain FP32 and the
+// block sums are added with TwoSum. Fixed, so results do not depend on the
+// LDS lens tile.
+constexpr int kBlock = 128;
+// LDS-privatised sub-map edge (pixels).
+constexpr int kSub = 64;
+
+enum Precision : int32_t { kFP32Comp = 0, kFP64Plain = 1 };
+
+// Everything a kernel needs about one map. Built on the host in FP64 with the
+// same IEEE operations the method states, passed by value (single map) or
+// from device memory (batch).
+struct MapParams {
+    // ray grid: x = base + (i + 1/2) * d
+    int64_t n1, n2;
+    double base1, base2, d1, d2;
+    float d1f, d2f;
+    int32_t cx, cy;            // cell shape in rays, cx * cy = kCellRays
+    int64_t cells_x;           // cells along x1 (last one may be partial)
+    int64_t row_begin, row_end;
+    int64_t cell_row0;         // first cell row touching row_begin
+    int64_t n_cells;           // cells covering [row_begin, row_end)
+    // macro model: y1 = a1 x1 - alpha1, y2 = a2 x2 - alpha2
+    double a1, a2;
+    // window: u = (y - lo) * inv; binned iff 0 <= u < p
+    int32_t p1, p2;
+    double lo1, lo2, inv1, inv2;
+    // lenses
+    int64_t n_lens;
+    const float4* lens32;      // FP32 path: {x1 hi, x1 lo, x2 hi, x2 lo}
+    const float* mass32;       // FP32 path masses (nullptr = unit)
+    const double* lx1;         // FP64 path
+    const double* lx2;
+    const double* lm;          // FP64 path masses (nullptr = unit)
+    // outputs
+    int32_t* counts;
+    unsigned long long* escaped;
+    double* out_y1;            // per-ray output mode only
+    double* out_y2;
+};
+
+struct WorkItem {
+    int32_t map;
+    int32_t pad;
+    int64_t cell0;
+    int64_t ncells;
+};
+
+struct KernelShape {
+    int32_t rays_x, rays_y;    // rays per lane along x1 / x2 (product 16)
+    int32_t lens_tile;         // lenses per LDS pass (multiple of kBlock)
+    int32_t waves;             // waves per workgroup
+    int32_t submap;            // 1 = LDS-privatised binning
+    int32_t item_cells;        // cells per batch work item
+};
+
+// Launchers (kernels.hip). Each returns the hipError_t of the launch.
+hipError_t launch_prep_lenses(const double* x1, const double* x2, const double* m, int64_t n,
+                              float4* out_xy, float* out_m, bool write_unit_mass,
+                              hipStream_t stream);
+hipError_t launch_shoot(const MapParams& P, Precision prec, const KernelShape& ks, bool out_y,
+                        int num_cus, hipStream_t stream);
+hipError_t launch_shoot_batch(const MapParams* d_maps, const WorkItem* d_items, int64_t n_items,
+                              unsigned int* d_counter, Precision prec, bool masses,
+                              const KernelShape& ks, int num_cus, hipStream_t stream);
+hipError_t launch_bin_positions(const double* y1, const double* y2, int64_t n, int32_t p1,
+                                int32_t p2, double lo1, double lo2, double inv1, double inv2,
+                                int32_t* counts, unsigned long long* escaped, hipStream_t stream);
+hipError_t launch_normalise(const int32_t* counts, int64_t n, double n_avg, float* mu,
+                            hipStream_t stream);
+// out[0] = sum of counts (u64), out[1] = max count (as u64)
+hipError_t launch_count_stats(const int32_t* counts, int64_t n, unsigned long long* out,
+                              hipStream_t stream);
+hipError_t launch_fill_u32(unsigned int* p, int64_t n, unsigned int v, hipStream_t stream);
+
+bool shape_supported(Precision prec, const KernelShape& ks);
+size_t shoot_lds_bytes(Precision prec, bool masses, const KernelShape& ks);
+
+}  // namespace rl

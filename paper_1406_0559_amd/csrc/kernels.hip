@@ -1,0 +1,641 @@
+// HIP kernels for direct inverse ray-shooting on gfx950 (CDNA4).
+//
+// Method: Vernardos & Fluke 2014, Section 2.1. Each ray x of a regular grid is
+// mapped to y = diag(1-gamma, 1+gamma) x - kappa_s x - sum_k m_k (x-x_k)/|x-x_k|^2
+// (eq. 1) and counted in a source-plane pixel; mu = N_ij / N_avg (eq. 4).
+//
+// Work decomposition (MI355X-first, not the paper's CUDA design):
+//   * A "cell" is a fixed 1024-ray tile of the ray grid (cx x cy rays, shape
+//     chosen from the grid spacing so it is roughly square on the sky). One
+//     wave of 64 lanes processes one cell, each lane holding a KX x KY block
+//     of rays in registers. Rays of a lane share their x1 (per column) and
+//     x2 (per row) offsets, so per lens a lane computes KX + KY differences
+//     and then one fma + one v_rcp_f32 + two fma per ray.
+//   * Lenses are staged per wave into LDS in tiles and read back as
+//     broadcasts (every lane reads the same address). For the FP32 path each
+//     lens is rebased to the cell centre while staging, from an FP32 hi/lo
+//     split of its FP64 position, so FP32 differences carry an error of
+//     ~eps32 * (cell size) instead of ~eps32 * |x|.
+//   * The FP32 deflection sum is blocked: kBlock lenses are summed in plain
+//     FP32, block sums are added into a (sum, compensation) pair by TwoSum.
+//     The block size and the cells are constants of the grid, so the kernel
+//     shape (rays per lane, lens tile, waves, binning mode, batching) never
+//     changes a result bit.
+//   * The final y = a x - alpha, the pixel test and the index are FP64 in the
+//     same operation order as a plain sequential evaluation.
+//   * Binning: either one global int32 atomic per binned ray, or an
+//     LDS-privatised 64 x 64 sub-map per workgroup centred on the mean pixel
+//     of its rays, flushed with one global atomic per touched pixel; rays
+//     that fall outside the sub-map go straight to global memory.
+//   * Block index -> cell mapping is XCD-aware: consecutive cells (adjacent
+//     on the sky, hence adjacent on the source plane) go to workgroups that
+//     run on the same XCD, so their atomics meet in the same L2.
+#include "internal.h"
+
+namespace rl {
+namespace {
+
+// ----------------------------------------------------------------------------
+// small helpers
+// ----------------------------------------------------------------------------
+
+// Rounded FP32 value of (hi + lo) - (ch + cl) from FP32 hi/lo splits, using
+// Knuth's TwoSum for hi - ch so the leading cancellation is exact.
+__device__ __forceinline__ float rebase(float hi, float lo, float ch, float cl) {
+    const float s = hi - ch;
+    const float bb = s - hi;
+    const float e = (hi - (s - bb)) + ((-ch) - bb);
+    return s + (e + (lo - cl));
+}
+
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Bijective remap of a linear block id so that blocks dispatched to the same
+// XCD (round-robin, block b -> XCD b % 8) receive consecutive work.
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
+    const int64_t x = b % 8, idx = b / 8, per = nb / 8, rem = nb % 8;
+    return x < rem ? x * (per + 1) + idx : rem * (per + 1) + (x - rem) * per + idx;
+}
+
+// ----------------------------------------------------------------------------
+// deflection sums
+// ----------------------------------------------------------------------------
+
+template <int KX, int KY, bool MASS>
+__device__ __forceinline__ void lens_step_f32(const float* __restrict__ wl, int k,
+                                              const float (&ox)[KX], const float (&oy)[KY],
+                                              float (&p1)[KX * KY], float (&p2)[KX * KY]) {
+    float lx, ly, lm = 1.0f;
+    if constexpr (MASS) {
+        const float4 v = reinterpret_cast<const float4*>(wl)[k];
+        lx = v.x; ly = v.y; lm = v.z;
+    } else {
+        const float2 v = reinterpret_cast<const float2*>(wl)[k];
+        lx = v.x; ly = v.y;
+    }
+    float dx[KX], wx[KX], dy[KY], dy2[KY], wy[KY];
+#pragma unroll
+    for (int a = 0; a < KX; ++a) {
+        dx[a] = ox[a] - lx;
+        wx[a] = MASS ? lm * dx[a] : dx[a];
+    }
+#pragma unroll
+    for (int b = 0; b < KY; ++b) {
+        dy[b] = oy[b] - ly;
+        dy2[b] = dy[b] * dy[b];
+        wy[b] = MASS ? lm * dy[b] : dy[b];
+    }
+#pragma unroll
+    for (int a = 0; a < KX; ++a) {
+#pragma unroll
+        for (int b = 0; b < KY; ++b) {
+            const float r2 = __builtin_fmaf(dx[a], dx[a], dy2[b]);
+            const float inv = __builtin_amdgcn_rcpf(r2);
+            p1[a * KY + b] = __builtin_fmaf(wx[a], inv, p1[a * KY + b]);
+            p2[a * KY + b] = __builtin_fmaf(wy[b], inv, p2[a * KY + b]);
+        }
+    }
+}
+
+// FP32-compensated deflection of the cell's rays; alpha returned in FP64 as
+// sum + compensation.
+template <int KX, int KY, bool MASS>
+__device__ __forceinline__ void deflect_f32(const MapParams& P, int64_t i0, int64_t j0, int lane,
+                                            int L, float* __restrict__ wl,
+                                            double (&al1)[KX * KY], double (&al2)[KX * KY]) {
+    constexpr int R = KX * KY;
+    const int lanes_x = P.cx / KX;
+    const int lxi = lane % lanes_x, lyi = lane / lanes_x;
+    // cell centre (a grid line between rays): C = base + (i0 + cx/2) d
+    const double C1 = P.base1 + (double)(i0 + P.cx / 2) * P.d1;
+    const double C2 = P.base2 + (double)(j0 + P.cy / 2) * P.d2;
+    const float C1h = (float)C1, C1l = (float)(C1 - (double)C1h);
+    const float C2h = (float)C2, C2l = (float)(C2 - (double)C2h);
+    // ray offsets from the cell centre: (half-integer) * d, one FP32 rounding
+    float ox[KX], oy[KY];
+#pragma unroll
+    for (int a = 0; a < KX; ++a) ox[a] = ((float)(lxi * KX + a - P.cx / 2) + 0.5f) * P.d1f;
+#pragma unroll
+    for (int b = 0; b < KY; ++b) oy[b] = ((float)(lyi * KY + b - P.cy / 2) + 0.5f) * P.d2f;
+
+    float p1[R], p2[R], s1[R], s2[R], c1[R], c2[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) { p1[r] = p2[r] = s1[r] = s2[r] = c1[r] = c2[r] = 0.0f; }
+
+    const int64_t n = P.n_lens;
+    for (int64_t t0 = 0; t0 < n; t0 += L) {
+        const int cnt = (int)((n - t0) < (int64_t)L ? (n - t0) : (int64_t)L);
+        for (int q = lane; q < cnt; q += kLanes) {
+            const float4 h = P.lens32[t0 + q];
+            const float r1 = rebase(h.x, h.y, C1h, C1l);
+            const float r2 = rebase(h.z, h.w, C2h, C2l);
+            if constexpr (MASS) {
+                reinterpret_cast<float4*>(wl)[q] = make_float4(r1, r2, P.mass32[t0 + q], 0.0f);
+            } else {
+                reinterpret_cast<float2*>(wl)[q] = make_float2(r1, r2);
+            }
+        }
+        __syncthreads();
+        for (int b0 = 0; b0 < cnt; b0 += kBlock) {
+            const int bn = (cnt - b0) < kBlock ? (cnt - b0) : kBlock;
+            if (bn == kBlock) {
+#pragma unroll 2
+                for (int k = 0; k < kBlock; ++k) lens_step_f32<KX, KY, MASS>(wl, b0 + k, ox, oy, p1, p2);
+            } else {
+                for (int k = 0; k < bn; ++k) lens_step_f32<KX, KY, MASS>(wl, b0 + k, ox, oy, p1, p2);
+            }
+            // TwoSum of the running sum and the block sum; the rounding error
+            // goes to the compensation term.
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                float t = s1[r] + p1[r];
+                float bb = t - s1[r];
+                c1[r] += (s1[r] - (t - bb)) + (p1[r] - bb);
+                s1[r] = t;
+                t = s2[r] + p2[r];
+                bb = t - s2[r];
+                c2[r] += (s2[r] - (t - bb)) + (p2[r] - bb);
+                s2[r] = t;
+                p1[r] = 0.0f;
+                p2[r] = 0.0f;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        al1[r] = (double)s1[r] + (double)c1[r];
+        al2[r] = (double)s2[r] + (double)c2[r];
+    }
+}
+
+// Plain FP64 deflection in the order of a sequential evaluation of eq. 1:
+// d = x - x_k; r2 = d1*d1 + d2*d2; q = m / r2; alpha += q * d (no contraction).
+template <int KX, int KY, bool MASS>
+__device__ __forceinline__ void deflect_f64(const MapParams& P, int64_t i0, int64_t j0, int lane,
+                                            int L, double* __restrict__ wl,
+                                            double (&al1)[KX * KY], double (&al2)[KX * KY]) {
+    constexpr int R = KX * KY;
+    const int lanes_x = P.cx / KX;
+    const int lxi = lane % lanes_x, lyi = lane / lanes_x;
+    double x1[KX], x2[KY];
+#pragma unroll
+    for (int a = 0; a < KX; ++a) x1[a] = P.base1 + ((double)(i0 + lxi * KX + a) + 0.5) * P.d1;
+#pragma unroll
+    for (int b = 0; b < KY; ++b) x2[b] = P.base2 + ((double)(j0 + lyi * KY + b) + 0.5) * P.d2;
+#pragma unroll
+    for (int r = 0; r < R; ++r) { al1[r] = 0.0; al2[r] = 0.0; }
+
+    const int64_t n = P.n_lens;
+    for (int64_t t0 = 0; t0 < n; t0 += L) {
+        const int cnt = (int)((n - t0) < (int64_t)L ? (n - t0) : (int64_t)L);
+        for (int q = lane; q < cnt; q += kLanes) {
+            if constexpr (MASS) {
+                reinterpret_cast<double4*>(wl)[q] =
+                    make_double4(P.lx1[t0 + q], P.lx2[t0 + q], P.lm ? P.lm[t0 + q] : 1.0, 0.0);
+            } else {
+                reinterpret_cast<double2*>(wl)[q] = make_double2(P.lx1[t0 + q], P.lx2[t0 + q]);
+            }
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int k = 0; k < cnt; ++k) {
+            double lx, ly, lm = 1.0;
+            if constexpr (MASS) {
+                const double4 v = reinterpret_cast<const double4*>(wl)[k];
+                lx = v.x; ly = v.y; lm = v.z;
+            } else {
+                const double2 v = reinterpret_cast<const double2*>(wl)[k];
+                lx = v.x; ly = v.y;
+            }
+            double d1[KX], q1[KX], d2[KY], q2[KY];
+#pragma unroll
+            for (int a = 0; a < KX; ++a) { d1[a] = x1[a] - lx; q1[a] = d1[a] * d1[a]; }
+#pragma unroll
+            for (int b = 0; b < KY; ++b) { d2[b] = x2[b] - ly; q2[b] = d2[b] * d2[b]; }
+#pragma unroll
+            for (int a = 0; a < KX; ++a) {
+#pragma unroll
+                for (int b = 0; b < KY; ++b) {
+                    const double r2 = q1[a] + q2[b];
+                    const double q = lm / r2;
+                    al1[a * KY + b] = al1[a * KY + b] + q * d1[a];
+                    al2[a * KY + b] = al2[a * KY + b] + q * d2[b];
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------------------
+// one cell per wave: deflection, lens equation, binning
+// ----------------------------------------------------------------------------
+
+template <int KX, int KY, bool MASS, bool SUBMAP, bool OUT_Y, int PREC>
+__device__ __forceinline__ void process_cell(const MapParams& P, int64_t cell, bool valid,
+                                             int wave, int lane, int L, char* lens_base,
+                                             int* sub, int* hdr) {
+    constexpr int R = KX * KY;
+    const int64_t col = cell % P.cells_x;
+    const int64_t row = P.cell_row0 + cell / P.cells_x;
+    const int64_t i0 = col * P.cx, j0 = row * P.cy;
+
+    double al1[R], al2[R];
+    if constexpr (PREC == kFP32Comp) {
+        const int stride = MASS ? 16 : 8;
+        deflect_f32<KX, KY, MASS>(P, i0, j0, lane, L,
+                                  reinterpret_cast<float*>(lens_base + (size_t)wave * L * stride),
+                                  al1, al2);
+    } else {
+        const int stride = MASS ? 32 : 16;
+        deflect_f64<KX, KY, MASS>(P, i0, j0, lane, L,
+                                  reinterpret_cast<double*>(lens_base + (size_t)wave * L * stride),
+                                  al1, al2);
+    }
+
+    const int lanes_x = P.cx / KX;
+    const int lxi = lane % lanes_x, lyi = lane / lanes_x;
+    int ixs[R], iys[R];
+    int esc = 0;
+#pragma unroll
+    for (int a = 0; a < KX; ++a) {
+#pragma unroll
+        for (int b = 0; b < KY; ++b) {
+            const int r = a * KY + b;
+            const int64_t i = i0 + lxi * KX + a;
+            const int64_t j = j0 + lyi * KY + b;
+            const bool live = valid && i < P.n1 && j >= P.row_begin && j < P.row_end;
+            const double x1 = P.base1 + ((double)i + 0.5) * P.d1;
+            const double x2 = P.base2 + ((double)j + 0.5) * P.d2;
+            const double y1 = P.a1 * x1 - al1[r];
+            const double y2 = P.a2 * x2 - al2[r];
+            if constexpr (OUT_Y) {
+                if (live) {
+                    const int64_t o = (j - P.row_begin) * P.n1 + i;
+                    P.out_y1[o] = y1;
+                    P.out_y2[o] = y2;
+                }
+                ixs[r] = -1;
+                iys[r] = 0;
+            } else {
+                const double u1 = (y1 - P.lo1) * P.inv1;
+                const double u2 = (y2 - P.lo2) * P.inv2;
+                const bool in = u1 >= 0.0 && u1 < (double)P.p1 && u2 >= 0.0 && u2 < (double)P.p2;
+                // convert only values known to be in range
+                const double v1 = in ? u1 : 0.0;
+                const double v2 = in ? u2 : 0.0;
+                ixs[r] = (live && in) ? (int)v1 : -1;
+                iys[r] = (live && in) ? (int)v2 : 0;
+                esc += (live && !in) ? 1 : 0;
+            }
+        }
+    }
+    if constexpr (OUT_Y) return;
+
+    esc = wave_sum(esc);
+    if (lane == 0 && esc) atomicAdd(P.escaped, (unsigned long long)esc);
+
+    if constexpr (!SUBMAP) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (ixs[r] >= 0) atomicAdd(P.counts + (int64_t)iys[r] * P.p1 + ixs[r], 1);
+    } else {
+        // workgroup-wide: centre the sub-map on the mean pixel of the binned rays
+        int sx = 0, sy = 0, sc = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (ixs[r] >= 0) { sx += ixs[r]; sy += iys[r]; sc += 1; }
+        }
+        sx = wave_sum(sx);
+        sy = wave_sum(sy);
+        sc = wave_sum(sc);
+        if (lane == 0 && sc) {
+            atomicAdd(&hdr[0], sx);
+            atomicAdd(&hdr[1], sy);
+            atomicAdd(&hdr[2], sc);
+        }
+        __syncthreads();
+        const int cnt = hdr[2];
+        if (cnt > 0) {  // uniform across the workgroup
+            const int ox = hdr[0] / cnt - kSub / 2;
+            const int oy = hdr[1] / cnt - kSub / 2;
+            for (int e = threadIdx.x; e < kSub * kSub; e += blockDim.x) sub[e] = 0;
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (ixs[r] >= 0) {
+                    const unsigned dx = (unsigned)(ixs[r] - ox), dy = (unsigned)(iys[r] - oy);
+                    if (dx < (unsigned)kSub && dy < (unsigned)kSub)
+                        atomicAdd(&sub[dy * kSub + dx], 1);
+                    else
+                        atomicAdd(P.counts + (int64_t)iys[r] * P.p1 + ixs[r], 1);
+                }
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < kSub * kSub; e += blockDim.x) {
+                const int v = sub[e];
+                if (v) atomicAdd(P.counts + (int64_t)(oy + e / kSub) * P.p1 + (ox + e % kSub), v);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) { hdr[0] = 0; hdr[1] = 0; hdr[2] = 0; }
+        __syncthreads();
+    }
+}
+
+constexpr int kHdrBytes = 64;
+
+template <int KX, int KY, bool MASS, bool SUBMAP, bool OUT_Y, int PREC>
+__global__ void __launch_bounds__(256) shoot_kernel(MapParams P, int L) {
+    extern __shared__ __align__(16) char smem[];
+    int* hdr = reinterpret_cast<int*>(smem);
+    char* lens_base = smem + kHdrBytes;
+    int* sub = reinterpret_cast<int*>(smem + kHdrBytes);
+    if (threadIdx.x < 16) hdr[threadIdx.x] = 0;
+    __syncthreads();
+    const int wave = threadIdx.x / kLanes, lane = threadIdx.x % kLanes;
+    const int W = blockDim.x / kLanes;
+    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t cell = b * W + wave;
+    const bool valid = cell < P.n_cells;
+    process_cell<KX, KY, MASS, SUBMAP, OUT_Y, PREC>(P, valid ? cell : 0, valid, wave, lane, L,
+                                                    lens_base, sub, hdr);
+}
+
+// Persistent batch kernel: workgroups pull (map, cell range) items from a
+// global counter until the list is exhausted; every workgroup reaches the
+// exit because the counter only grows.
+template <int KX, int KY, bool MASS, bool SUBMAP, int PREC>
+__global__ void __launch_bounds__(256) shoot_batch_kernel(const MapParams* __restrict__ maps,
+                                                          const WorkItem* __restrict__ items,
+                                                          int64_t n_items, unsigned int* counter,
+                                                          int L) {
+    extern __shared__ __align__(16) char smem[];
+    int* hdr = reinterpret_cast<int*>(smem);
+    char* lens_base = smem + kHdrBytes;
+    int* sub = reinterpret_cast<int*>(smem + kHdrBytes);
+    if (threadIdx.x < 16) hdr[threadIdx.x] = 0;
+    __syncthreads();
+    const int wave = threadIdx.x / kLanes, lane = threadIdx.x % kLanes;
+    const int W = blockDim.x / kLanes;
+    for (;;) {
+        if (threadIdx.x == 0) hdr[3] = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int64_t it = (int64_t)(unsigned)__builtin_amdgcn_readfirstlane(hdr[3]);
+        __syncthreads();
+        if (it >= n_items) break;
+        const WorkItem w = items[it];
+        const MapParams& P = maps[w.map];
+        const int64_t end = w.cell0 + w.ncells;
+        for (int64_t c0 = w.cell0; c0 < end; c0 += W) {
+            const int64_t cell = c0 + wave;
+            const bool valid = cell < end;
+            process_cell<KX, KY, MASS, SUBMAP, false, PREC>(P, valid ? cell : w.cell0, valid, wave,
+                                                            lane, L, lens_base, sub, hdr);
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// small kernels
+// ----------------------------------------------------------------------------
+
+// FP64 lens coordinates -> FP32 hi/lo splits (hi = nearest float, lo = the
+// nearest float of the exact remainder) and FP32 masses.
+__global__ void prep_lenses_kernel(const double* __restrict__ x1, const double* __restrict__ x2,
+                                   const double* __restrict__ m, int64_t n, float4* __restrict__ xy,
+                                   float* __restrict__ mo, int write_unit) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const double a = x1[k], b = x2[k];
+        const float ah = (float)a, bh = (float)b;
+        xy[k] = make_float4(ah, (float)(a - (double)ah), bh, (float)(b - (double)bh));
+        if (mo) mo[k] = m ? (float)m[k] : (write_unit ? 1.0f : 0.0f);
+    }
+}
+
+__global__ void bin_positions_kernel(const double* __restrict__ y1, const double* __restrict__ y2,
+                                     int64_t n, int32_t p1, int32_t p2, double lo1, double lo2,
+                                     double inv1, double inv2, int32_t* __restrict__ counts,
+                                     unsigned long long* __restrict__ escaped) {
+    int esc = 0;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const double u1 = (y1[k] - lo1) * inv1;
+        const double u2 = (y2[k] - lo2) * inv2;
+        const bool in = u1 >= 0.0 && u1 < (double)p1 && u2 >= 0.0 && u2 < (double)p2;
+        if (in) {
+            atomicAdd(counts + (int64_t)(int)u2 * p1 + (int)u1, 1);
+        } else {
+            esc += 1;
+        }
+    }
+    esc = wave_sum(esc);
+    if ((threadIdx.x % kLanes) == 0 && esc) atomicAdd(escaped, (unsigned long long)esc);
+}
+
+__global__ void normalise_kernel(const int32_t* __restrict__ counts, int64_t n, double n_avg,
+                                 float* __restrict__ mu) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x)
+        mu[k] = (float)((double)counts[k] / n_avg);
+}
+
+__global__ void count_stats_kernel(const int32_t* __restrict__ counts, int64_t n,
+                                   unsigned long long* __restrict__ out) {
+    unsigned long long s = 0;
+    int mx = 0;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int v = counts[k];
+        s += (unsigned long long)(unsigned)v;
+        mx = v > mx ? v : mx;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        s += __shfl_xor(s, o);
+        const int t = __shfl_xor(mx, o);
+        mx = t > mx ? t : mx;
+    }
+    if ((threadIdx.x % kLanes) == 0) {
+        atomicAdd(&out[0], s);
+        atomicMax(&out[1], (unsigned long long)mx);
+    }
+}
+
+__global__ void fill_u32_kernel(unsigned int* p, int64_t n, unsigned int v) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x)
+        p[k] = v;
+}
+
+int grid_for(int64_t n, int threads, int cap) {
+    int64_t g = (n + threads - 1) / threads;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+// ----------------------------------------------------------------------------
+// dispatch
+// ----------------------------------------------------------------------------
+
+template <int KX, int KY, bool MASS, bool SUBMAP, bool OUT_Y, int PREC>
+hipError_t launch_one(const MapParams& P, const KernelShape& ks, size_t lds, hipStream_t s) {
+    const int W = ks.waves;
+    const int64_t blocks = (P.n_cells + W - 1) / W;
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL((shoot_kernel<KX, KY, MASS, SUBMAP, OUT_Y, PREC>), dim3((unsigned)blocks),
+                       dim3(W * kLanes), lds, s, P, ks.lens_tile);
+    return hipGetLastError();
+}
+
+template <int KX, int KY, bool MASS, bool SUBMAP, int PREC>
+hipError_t launch_batch_one(const MapParams* maps, const WorkItem* items, int64_t n_items,
+                            unsigned int* counter, const KernelShape& ks, size_t lds,
+                            int num_cus, hipStream_t s) {
+    const int W = ks.waves;
+    // enough resident workgroups to fill every CU several times over
+    int64_t blocks = (int64_t)num_cus * (16 / W);
+    if (blocks > n_items) blocks = n_items;
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL((shoot_batch_kernel<KX, KY, MASS, SUBMAP, PREC>), dim3((unsigned)blocks),
+                       dim3(W * kLanes), lds, s, maps, items, n_items, counter, ks.lens_tile);
+    return hipGetLastError();
+}
+
+template <int KX, int KY, int PREC>
+hipError_t dispatch_shape(const MapParams& P, const KernelShape& ks, bool masses, bool out_y,
+                          size_t lds, hipStream_t s) {
+    if (out_y) {
+        return masses ? launch_one<KX, KY, true, false, true, PREC>(P, ks, lds, s)
+                      : launch_one<KX, KY, false, false, true, PREC>(P, ks, lds, s);
+    }
+    if (masses) {
+        return ks.submap ? launch_one<KX, KY, true, true, false, PREC>(P, ks, lds, s)
+                         : launch_one<KX, KY, true, false, false, PREC>(P, ks, lds, s);
+    }
+    return ks.submap ? launch_one<KX, KY, false, true, false, PREC>(P, ks, lds, s)
+                     : launch_one<KX, KY, false, false, false, PREC>(P, ks, lds, s);
+}
+
+template <int KX, int KY, int PREC>
+hipError_t dispatch_batch_shape(const MapParams* maps, const WorkItem* items, int64_t n_items,
+                                unsigned int* counter, bool masses, const KernelShape& ks,
+                                size_t lds, int num_cus, hipStream_t s) {
+    if (masses) {
+        return ks.submap
+                   ? launch_batch_one<KX, KY, true, true, PREC>(maps, items, n_items, counter, ks, lds, num_cus, s)
+                   : launch_batch_one<KX, KY, true, false, PREC>(maps, items, n_items, counter, ks, lds, num_cus, s);
+    }
+    return ks.submap
+               ? launch_batch_one<KX, KY, false, true, PREC>(maps, items, n_items, counter, ks, lds, num_cus, s)
+               : launch_batch_one<KX, KY, false, false, PREC>(maps, items, n_items, counter, ks, lds, num_cus, s);
+}
+
+}  // namespace
+
+bool shape_supported(Precision prec, const KernelShape& ks) {
+    const bool k44 = ks.rays_x == 4 && ks.rays_y == 4;
+    const bool k28 = ks.rays_x == 2 && ks.rays_y == 8;
+    const bool k82 = ks.rays_x == 8 && ks.rays_y == 2;
+    if (prec == kFP64Plain && !k44) return false;
+    if (!(k44 || k28 || k82)) return false;
+    if (ks.lens_tile < kBlock || ks.lens_tile > 2048 || ks.lens_tile % kBlock) return false;
+    if (!(ks.waves == 1 || ks.waves == 2 || ks.waves == 4)) return false;
+    if (!(ks.submap == 0 || ks.submap == 1)) return false;
+    if (ks.item_cells < 1) return false;
+    return true;
+}
+
+// Dynamic LDS per workgroup is kept within 64 KiB: a lens tile that would not
+// fit is shrunk (in whole compensation blocks), which changes no result.
+constexpr size_t kMaxLds = 65536;
+
+KernelShape fit_lds(Precision prec, bool masses, const KernelShape& ks) {
+    const size_t stride = prec == kFP32Comp ? (masses ? 16 : 8) : (masses ? 32 : 16);
+    KernelShape k = ks;
+    const size_t room = kMaxLds - kHdrBytes;
+    while (k.lens_tile > kBlock && (size_t)k.waves * k.lens_tile * stride > room) k.lens_tile -= kBlock;
+    return k;
+}
+
+size_t shoot_lds_bytes(Precision prec, bool masses, const KernelShape& ks) {
+    const size_t stride = prec == kFP32Comp ? (masses ? 16 : 8) : (masses ? 32 : 16);
+    size_t lens = (size_t)ks.waves * ks.lens_tile * stride;
+    const size_t sub = ks.submap ? (size_t)kSub * kSub * sizeof(int) : 0;
+    return kHdrBytes + (lens > sub ? lens : sub);
+}
+
+hipError_t launch_shoot(const MapParams& P, Precision prec, const KernelShape& ks, bool out_y,
+                        int num_cus, hipStream_t s) {
+    (void)num_cus;
+    const bool masses = prec == kFP32Comp ? (P.mass32 != nullptr) : (P.lm != nullptr);
+    KernelShape k = fit_lds(prec, masses, ks);
+    if (out_y) k.submap = 0;
+    const size_t lds = shoot_lds_bytes(prec, masses, k);
+    if (prec == kFP64Plain) return dispatch_shape<4, 4, kFP64Plain>(P, k, masses, out_y, lds, s);
+    if (k.rays_x == 4) return dispatch_shape<4, 4, kFP32Comp>(P, k, masses, out_y, lds, s);
+    if (k.rays_x == 2) return dispatch_shape<2, 8, kFP32Comp>(P, k, masses, out_y, lds, s);
+    return dispatch_shape<8, 2, kFP32Comp>(P, k, masses, out_y, lds, s);
+}
+
+hipError_t launch_shoot_batch(const MapParams* d_maps, const WorkItem* d_items, int64_t n_items,
+                              unsigned int* d_counter, Precision prec, bool masses,
+                              const KernelShape& ks_in, int num_cus, hipStream_t s) {
+    const KernelShape ks = fit_lds(prec, masses, ks_in);
+    const size_t lds = shoot_lds_bytes(prec, masses, ks);
+    if (prec == kFP64Plain)
+        return dispatch_batch_shape<4, 4, kFP64Plain>(d_maps, d_items, n_items, d_counter, masses, ks, lds, num_cus, s);
+    if (ks.rays_x == 4)
+        return dispatch_batch_shape<4, 4, kFP32Comp>(d_maps, d_items, n_items, d_counter, masses, ks, lds, num_cus, s);
+    if (ks.rays_x == 2)
+        return dispatch_batch_shape<2, 8, kFP32Comp>(d_maps, d_items, n_items, d_counter, masses, ks, lds, num_cus, s);
+    return dispatch_batch_shape<8, 2, kFP32Comp>(d_maps, d_items, n_items, d_counter, masses, ks, lds, num_cus, s);
+}
+
+hipError_t launch_prep_lenses(const double* x1, const double* x2, const double* m, int64_t n,
+                              float4* out_xy, float* out_m, bool write_unit_mass, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(prep_lenses_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, x1, x2, m,
+                       n, out_xy, out_m, write_unit_mass ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_positions(const double* y1, const double* y2, int64_t n, int32_t p1,
+                                int32_t p2, double lo1, double lo2, double inv1, double inv2,
+                                int32_t* counts, unsigned long long* escaped, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(bin_positions_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, y1, y2, n,
+                       p1, p2, lo1, lo2, inv1, inv2, counts, escaped);
+    return hipGetLastError();
+}
+
+hipError_t launch_normalise(const int32_t* counts, int64_t n, double n_avg, float* mu,
+                            hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(normalise_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, counts, n,
+                       n_avg, mu);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_stats(const int32_t* counts, int64_t n, unsigned long long* out,
+                              hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(count_stats_kernel, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, counts, n,
+                       out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(unsigned int* p, int64_t n, unsigned int v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace rl

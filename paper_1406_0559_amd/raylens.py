@@ -1,0 +1,350 @@
+"""Thin ctypes binding of the raylens C-ABI (include/raylens.h).
+
+Functions keep the C names (rl_create, rl_shoot, ...) and only marshal
+arguments; every step of the computation runs in the HIP library. A missing
+library is an error: there is no CPU fallback on this path.
+
+The `Context` class adds torch plumbing (device tensors for the lens field,
+count maps and magnification maps; the current torch stream) on top of the
+same calls.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libraylens.so")
+
+RL_OK, RL_E_INVALID, RL_E_NOMEM, RL_E_DEVICE, RL_E_BUSY, RL_E_CANCELLED, RL_E_OVERFLOW = range(7)
+RL_FP32_COMP, RL_FP64_PLAIN = 0, 1
+PRECISIONS = {"fp32c": RL_FP32_COMP, "fp64": RL_FP64_PLAIN}
+
+
+class RaylensError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"raylens status {status}: {message}")
+        self.status = status
+
+
+class rl_macro(C.Structure):
+    _fields_ = [("kappa", C.c_double), ("gamma", C.c_double), ("s", C.c_double)]
+
+
+class rl_raygrid(C.Structure):
+    _fields_ = [("n1", C.c_int64), ("n2", C.c_int64), ("c1", C.c_double), ("c2", C.c_double),
+                ("half1", C.c_double), ("half2", C.c_double)]
+
+
+class rl_window(C.Structure):
+    _fields_ = [("p1", C.c_int32), ("p2", C.c_int32), ("c1", C.c_double), ("c2", C.c_double),
+                ("width1", C.c_double), ("width2", C.c_double)]
+
+
+class rl_lenses(C.Structure):
+    _fields_ = [("x1", C.c_void_p), ("x2", C.c_void_p), ("m", C.c_void_p), ("n", C.c_int64)]
+
+
+class rl_stats(C.Structure):
+    _fields_ = [("shot", C.c_int64), ("binned", C.c_int64), ("escaped", C.c_int64),
+                ("n_avg", C.c_double), ("mean_count", C.c_double), ("mean_mu", C.c_double),
+                ("mu_th", C.c_double), ("max_count", C.c_int32)]
+
+
+class rl_map_desc(C.Structure):
+    _fields_ = [("lenses", rl_lenses), ("macro", rl_macro), ("grid", rl_raygrid),
+                ("win", rl_window), ("row_begin", C.c_int64), ("row_end", C.c_int64),
+                ("d_counts", C.c_void_p), ("d_escaped", C.c_void_p)]
+
+
+class rl_tuning(C.Structure):
+    _fields_ = [("rays_x", C.c_int32), ("rays_y", C.c_int32), ("lens_tile", C.c_int32),
+                ("waves", C.c_int32), ("submap", C.c_int32), ("item_cells", C.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    """Opens libraylens.so (built by paper_1406_0559_amd/build.py)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1406_0559_amd/build.py "
+                           "(or __graft_entry__.build()); there is no fallback")
+    L = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    sig = {
+        "rl_create": [i32, P(vp)],
+        "rl_destroy": [vp],
+        "rl_n_avg": [P(rl_raygrid), P(rl_window), P(dbl)],
+        "rl_shoot": [vp, P(rl_lenses), P(rl_macro), P(rl_raygrid), P(rl_window), C.c_int, i64, i64,
+                     vp, vp, vp],
+        "rl_normalise": [vp, vp, P(rl_window), dbl, vp, vp],
+        "rl_stats_get": [vp, vp, vp, P(rl_macro), P(rl_raygrid), P(rl_window), P(rl_stats), vp],
+        "rl_bin_positions": [vp, vp, vp, i64, P(rl_window), vp, vp, vp],
+        "rl_ray_positions": [vp, P(rl_lenses), P(rl_macro), P(rl_raygrid), C.c_int, i64, i64, vp,
+                             vp, vp],
+        "rl_shoot_batch": [vp, P(rl_map_desc), i32, C.c_int, vp],
+        "rl_get_tuning": [vp, C.c_int, i32, P(rl_tuning)],
+        "rl_set_tuning": [vp, C.c_int, i32, P(rl_tuning)],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    L.rl_last_error.restype = C.c_char_p
+    L.rl_last_error.argtypes = []
+    L.rl_version.restype = C.c_char_p
+    L.rl_version.argtypes = []
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != RL_OK:
+        raise RaylensError(status, load().rl_last_error().decode())
+
+
+# ----------------------------------------------------------------------------
+# same-name wrappers (marshalling only)
+# ----------------------------------------------------------------------------
+
+def rl_version() -> str:
+    return load().rl_version().decode()
+
+
+def rl_last_error() -> str:
+    return load().rl_last_error().decode()
+
+
+def rl_create(device: int = 0) -> int:
+    out = C.c_void_p()
+    _check(load().rl_create(device, C.byref(out)))
+    return out.value
+
+
+def rl_destroy(ctx: int) -> None:
+    _check(load().rl_destroy(ctx))
+
+
+def rl_n_avg(grid: rl_raygrid, win: rl_window) -> float:
+    out = C.c_double()
+    _check(load().rl_n_avg(C.byref(grid), C.byref(win), C.byref(out)))
+    return out.value
+
+
+def rl_shoot(ctx, lenses, macro, grid, win, precision, row_begin, row_end, d_counts, d_escaped,
+             stream=None):
+    _check(load().rl_shoot(ctx, C.byref(lenses), C.byref(macro), C.byref(grid), C.byref(win),
+                           precision, row_begin, row_end, d_counts, d_escaped, stream))
+
+
+def rl_normalise(ctx, d_counts, win, n_avg, d_mu, stream=None):
+    _check(load().rl_normalise(ctx, d_counts, C.byref(win), n_avg, d_mu, stream))
+
+
+def rl_stats_get(ctx, d_counts, d_escaped, macro, grid, win, stream=None, allow_overflow=False):
+    st = rl_stats()
+    status = load().rl_stats_get(ctx, d_counts, d_escaped, C.byref(macro), C.byref(grid),
+                                 C.byref(win), C.byref(st), stream)
+    if not (allow_overflow and status == RL_E_OVERFLOW):
+        _check(status)
+    return st
+
+
+def rl_bin_positions(ctx, d_y1, d_y2, n, win, d_counts, d_escaped, stream=None):
+    _check(load().rl_bin_positions(ctx, d_y1, d_y2, n, C.byref(win), d_counts, d_escaped, stream))
+
+
+def rl_ray_positions(ctx, lenses, macro, grid, precision, row_begin, row_end, d_y1, d_y2,
+                     stream=None):
+    _check(load().rl_ray_positions(ctx, C.byref(lenses), C.byref(macro), C.byref(grid), precision,
+                                   row_begin, row_end, d_y1, d_y2, stream))
+
+
+def rl_shoot_batch(ctx, descs: Sequence[rl_map_desc], precision, stream=None):
+    arr = (rl_map_desc * len(descs))(*descs)
+    _check(load().rl_shoot_batch(ctx, arr, len(descs), precision, stream))
+
+
+def rl_get_tuning(ctx, precision, n_class) -> rl_tuning:
+    t = rl_tuning()
+    _check(load().rl_get_tuning(ctx, precision, n_class, C.byref(t)))
+    return t
+
+
+def rl_set_tuning(ctx, precision, n_class, tuning: rl_tuning):
+    _check(load().rl_set_tuning(ctx, precision, n_class, C.byref(tuning)))
+
+
+# ----------------------------------------------------------------------------
+# torch plumbing
+# ----------------------------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def macro_of(spec) -> rl_macro:
+    return rl_macro(spec.kappa, spec.gamma, spec.s)
+
+
+def grid_of(spec) -> rl_raygrid:
+    return rl_raygrid(spec.n1, spec.n2, spec.c1, spec.c2, spec.h1, spec.h2)
+
+
+def window_of(spec) -> rl_window:
+    return rl_window(spec.p1, spec.p2, spec.w1, spec.w2, spec.W1, spec.W2)
+
+
+class DeviceLenses:
+    """A lens field resident in HBM as FP64 structure-of-arrays tensors."""
+
+    def __init__(self, x1, x2, m=None, device="cuda"):
+        torch = _torch()
+        self.x1 = torch.as_tensor(x1, dtype=torch.float64).to(device).contiguous()
+        self.x2 = torch.as_tensor(x2, dtype=torch.float64).to(device).contiguous()
+        self.m = None if m is None else torch.as_tensor(m, dtype=torch.float64).to(device).contiguous()
+        if self.x1.shape != self.x2.shape or self.x1.dim() != 1:
+            raise ValueError("lens positions must be 1-D tensors of equal length")
+        if self.m is not None and self.m.shape != self.x1.shape:
+            raise ValueError("masses must match the positions")
+
+    @property
+    def n(self):
+        return int(self.x1.numel())
+
+    def struct(self) -> rl_lenses:
+        return rl_lenses(self.x1.data_ptr() if self.n else None,
+                         self.x2.data_ptr() if self.n else None,
+                         None if self.m is None else self.m.data_ptr(), self.n)
+
+    def nbytes(self):
+        return self.x1.numel() * 8 * (3 if self.m is not None else 2)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return _torch().cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+class Context:
+    """An rl_context plus torch-tensor conveniences."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        self.handle = rl_create(device)
+
+    def close(self):
+        if self.handle:
+            rl_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def new_map(self, spec):
+        torch = _torch()
+        dev = f"cuda:{self.device}"
+        counts = torch.zeros((spec.p2, spec.p1), dtype=torch.int32, device=dev)
+        escaped = torch.zeros(1, dtype=torch.int64, device=dev)
+        return counts, escaped
+
+    def shoot(self, lenses: DeviceLenses, spec, precision="fp32c", counts=None, escaped=None,
+              row_begin=0, row_end=None, stream=None):
+        if counts is None or escaped is None:
+            counts, escaped = self.new_map(spec)
+        _check_map_tensors(counts, escaped, spec)
+        rl_shoot(self.handle, lenses.struct(), macro_of(spec), grid_of(spec), window_of(spec),
+                 PRECISIONS[precision], row_begin, spec.n2 if row_end is None else row_end,
+                 counts.data_ptr(), escaped.data_ptr(), _stream_ptr(stream))
+        return counts, escaped
+
+    def ray_positions(self, lenses: DeviceLenses, spec, precision="fp32c", row_begin=0,
+                      row_end=None, stream=None):
+        torch = _torch()
+        row_end = spec.n2 if row_end is None else row_end
+        rows = row_end - row_begin
+        dev = f"cuda:{self.device}"
+        y1 = torch.empty((rows, spec.n1), dtype=torch.float64, device=dev)
+        y2 = torch.empty((rows, spec.n1), dtype=torch.float64, device=dev)
+        rl_ray_positions(self.handle, lenses.struct(), macro_of(spec), grid_of(spec),
+                         PRECISIONS[precision], row_begin, row_end, y1.data_ptr(), y2.data_ptr(),
+                         _stream_ptr(stream))
+        return y1, y2
+
+    def bin_positions(self, y1, y2, spec, counts=None, escaped=None, stream=None):
+        torch = _torch()
+        if counts is None or escaped is None:
+            counts, escaped = self.new_map(spec)
+        _check_map_tensors(counts, escaped, spec)
+        y1 = y1.contiguous()
+        y2 = y2.contiguous()
+        if y1.dtype != torch.float64 or y2.dtype != torch.float64 or y1.numel() != y2.numel():
+            raise ValueError("positions must be float64 tensors of equal size")
+        rl_bin_positions(self.handle, y1.data_ptr(), y2.data_ptr(), y1.numel(), window_of(spec),
+                         counts.data_ptr(), escaped.data_ptr(), _stream_ptr(stream))
+        return counts, escaped
+
+    def normalise(self, counts, spec, n_avg=None, mu=None, stream=None):
+        torch = _torch()
+        if n_avg is None:
+            n_avg = rl_n_avg(grid_of(spec), window_of(spec))
+        if mu is None:
+            mu = torch.empty((spec.p2, spec.p1), dtype=torch.float32, device=counts.device)
+        if counts.dtype != torch.int32 or counts.numel() != spec.p1 * spec.p2 or not counts.is_contiguous():
+            raise ValueError("counts must be a contiguous int32 p2 x p1 tensor")
+        if mu.dtype != torch.float32 or mu.numel() != spec.p1 * spec.p2 or not mu.is_contiguous():
+            raise ValueError("mu must be a contiguous float32 p2 x p1 tensor")
+        rl_normalise(self.handle, counts.data_ptr(), window_of(spec), n_avg, mu.data_ptr(),
+                     _stream_ptr(stream))
+        return mu
+
+    def stats(self, counts, escaped, spec, stream=None):
+        st = rl_stats_get(self.handle, counts.data_ptr(), escaped.data_ptr(), macro_of(spec),
+                          grid_of(spec), window_of(spec), _stream_ptr(stream))
+        return {f: getattr(st, f) for f, _ in rl_stats._fields_}
+
+    def shoot_batch(self, items, precision="fp32c", stream=None):
+        """items: sequence of (DeviceLenses, spec, counts, escaped[, row_begin, row_end])."""
+        descs = []
+        for it in items:
+            lenses, spec, counts, escaped = it[:4]
+            rb = it[4] if len(it) > 4 else 0
+            re = it[5] if len(it) > 5 else spec.n2
+            _check_map_tensors(counts, escaped, spec)
+            descs.append(rl_map_desc(lenses.struct(), macro_of(spec), grid_of(spec), window_of(spec),
+                                     rb, re, counts.data_ptr(), escaped.data_ptr()))
+        rl_shoot_batch(self.handle, descs, PRECISIONS[precision], _stream_ptr(stream))
+
+    def get_tuning(self, precision, n_class):
+        t = rl_get_tuning(self.handle, PRECISIONS[precision], n_class)
+        return {f: getattr(t, f) for f, _ in rl_tuning._fields_}
+
+    def set_tuning(self, precision, n_class, **kw):
+        cur = self.get_tuning(precision, n_class)
+        cur.update(kw)
+        rl_set_tuning(self.handle, PRECISIONS[precision], n_class, rl_tuning(**cur))
+
+
+def _check_map_tensors(counts, escaped, spec):
+    torch = _torch()
+    if counts.dtype != torch.int32 or counts.numel() != spec.p1 * spec.p2 or not counts.is_contiguous():
+        raise ValueError("counts must be a contiguous int32 tensor of p2 x p1 elements")
+    if escaped.dtype != torch.int64 or escaped.numel() < 1:
+        raise ValueError("escaped must be an int64 tensor")
+    if not counts.is_cuda or not escaped.is_cuda:
+        raise ValueError("counts and escaped must be device tensors")
+
+
+def n_class(n: int) -> int:
+    return 0 if n < 1000 else (1 if n < 10000 else 2)

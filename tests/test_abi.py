@@ -1,0 +1,147 @@
+"""The C-ABI library on the CPU: it loads, exports every declared symbol, and
+rejects invalid arguments before any HIP call (no compute happens here)."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1406_0559_amd import raylens as rl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "raylens.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rl_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = rl.load()
+    syms = declared_symbols()
+    assert len(syms) >= 13
+    for s in syms:
+        assert hasattr(lib, s), f"{s} declared in include/raylens.h but not exported"
+
+
+def test_version_and_context_lifecycle_without_device():
+    assert "raylens" in rl.rl_version()
+    ctx = rl.rl_create(0)     # makes no HIP call
+    assert ctx
+    rl.rl_destroy(ctx)
+    rl.rl_destroy(None)
+
+
+def test_invalid_arguments_are_rejected_on_the_host():
+    lib = rl.load()
+    ctx = rl.rl_create(0)
+    try:
+        g = rl.rl_raygrid(64, 64, 0.0, 0.0, 1.0, 1.0)
+        w = rl.rl_window(16, 16, 0.0, 0.0, 2.0, 2.0)
+        m = rl.rl_macro(0.4, 0.3, 0.0)
+        L = rl.rl_lenses(None, None, None, 0)
+        fake = C.c_void_p(0x1000)   # never dereferenced: validation fails first
+        cases = [
+            ("n1 = 0", dict(g=rl.rl_raygrid(0, 64, 0.0, 0.0, 1.0, 1.0))),
+            ("negative half-width", dict(g=rl.rl_raygrid(64, 64, 0.0, 0.0, -1.0, 1.0))),
+            ("nan half-width", dict(g=rl.rl_raygrid(64, 64, 0.0, 0.0, math.nan, 1.0))),
+            ("p2 = 0", dict(w=rl.rl_window(16, 0, 0.0, 0.0, 2.0, 2.0))),
+            ("zero width", dict(w=rl.rl_window(16, 16, 0.0, 0.0, 0.0, 2.0))),
+            ("inf kappa", dict(m=rl.rl_macro(math.inf, 0.3, 0.0))),
+            ("nan gamma", dict(m=rl.rl_macro(0.4, math.nan, 0.0))),
+            ("negative lens count", dict(L=rl.rl_lenses(None, None, None, -1))),
+            ("lenses without positions", dict(L=rl.rl_lenses(None, None, None, 5))),
+            ("rows reversed", dict(rb=10, re=5)),
+            ("rows past the grid", dict(rb=0, re=65)),
+            ("bad precision", dict(prec=7)),
+            ("null counts", dict(counts=None)),
+        ]
+        for label, kw in cases:
+            st = lib.rl_shoot(ctx, C.byref(kw.get("L", L)), C.byref(kw.get("m", m)),
+                              C.byref(kw.get("g", g)), C.byref(kw.get("w", w)),
+                              kw.get("prec", rl.RL_FP32_COMP), kw.get("rb", 0), kw.get("re", 64),
+                              kw.get("counts", fake), fake, None)
+            assert st == rl.RL_E_INVALID, label
+            assert rl.rl_last_error(), label
+        assert lib.rl_shoot(None, C.byref(L), C.byref(m), C.byref(g), C.byref(w), 0, 0, 64, fake,
+                            fake, None) == rl.RL_E_INVALID
+        assert lib.rl_normalise(ctx, fake, C.byref(w), 0.0, fake, None) == rl.RL_E_INVALID
+        assert lib.rl_normalise(ctx, fake, C.byref(w), math.nan, fake, None) == rl.RL_E_INVALID
+        assert lib.rl_bin_positions(ctx, fake, fake, -1, C.byref(w), fake, fake, None) == rl.RL_E_INVALID
+        assert lib.rl_bin_positions(ctx, None, fake, 3, C.byref(w), fake, fake, None) == rl.RL_E_INVALID
+        assert lib.rl_ray_positions(ctx, C.byref(L), C.byref(m), C.byref(g), 0, 3, 2, fake, fake,
+                                    None) == rl.RL_E_INVALID
+        assert lib.rl_shoot_batch(ctx, None, 2, 0, None) == rl.RL_E_INVALID
+        bad = rl.rl_map_desc(L, m, rl.rl_raygrid(0, 1, 0.0, 0.0, 1.0, 1.0), w, 0, 1, fake.value,
+                             fake.value)
+        assert lib.rl_shoot_batch(ctx, C.byref(bad), 1, 0, None) == rl.RL_E_INVALID
+        assert "map 0" in rl.rl_last_error()
+        assert lib.rl_stats_get(ctx, fake, fake, C.byref(m), C.byref(g), C.byref(w), None,
+                                None) == rl.RL_E_INVALID
+    finally:
+        rl.rl_destroy(ctx)
+
+
+def test_empty_work_is_a_no_op():
+    """Zero rows and zero positions return before touching a device."""
+    lib = rl.load()
+    ctx = rl.rl_create(0)
+    try:
+        g = rl.rl_raygrid(64, 64, 0.0, 0.0, 1.0, 1.0)
+        w = rl.rl_window(16, 16, 0.0, 0.0, 2.0, 2.0)
+        m = rl.rl_macro(0.4, 0.3, 0.0)
+        L = rl.rl_lenses(None, None, None, 0)
+        fake = C.c_void_p(0x1000)
+        assert lib.rl_shoot(ctx, C.byref(L), C.byref(m), C.byref(g), C.byref(w), 0, 5, 5, fake,
+                            fake, None) == rl.RL_OK
+        assert lib.rl_bin_positions(ctx, None, None, 0, C.byref(w), fake, fake, None) == rl.RL_OK
+        assert lib.rl_shoot_batch(ctx, None, 0, 0, None) == rl.RL_OK
+    finally:
+        rl.rl_destroy(ctx)
+
+
+def test_n_avg_matches_the_oracle_bit_for_bit():
+    for (n1, n2, h1, h2, p1, p2, W1, W2) in [(1024, 1024, 8.0, 2.67, 256, 256, 4.0, 4.0),
+                                             (30000, 30000, 65.0, 14.2, 4096, 4096, 25.0, 25.0),
+                                             (7, 3, 0.3, 1.9, 5, 11, 0.7, 3.3)]:
+        a = rl.rl_n_avg(rl.rl_raygrid(n1, n2, 0.0, 0.0, h1, h2), rl.rl_window(p1, p2, 0.0, 0.0, W1, W2))
+        b = oracle.n_avg(n1, n2, h1, h2, p1, p2, W1, W2)
+        assert a == b
+
+
+def test_tuning_table_validation():
+    ctx = rl.rl_create(0)
+    try:
+        t = rl.rl_get_tuning(ctx, rl.RL_FP32_COMP, 1)
+        assert t.rays_x * t.rays_y == 16
+        for bad in [dict(rays_x=3), dict(lens_tile=100), dict(lens_tile=4096), dict(waves=3),
+                    dict(submap=2), dict(item_cells=0)]:
+            cur = {f: getattr(t, f) for f, _ in rl.rl_tuning._fields_}
+            cur.update(bad)
+            with pytest.raises(rl.RaylensError):
+                rl.rl_set_tuning(ctx, rl.RL_FP32_COMP, 1, rl.rl_tuning(**cur))
+        ok = rl.rl_tuning(2, 8, 512, 2, 0, 8)
+        rl.rl_set_tuning(ctx, rl.RL_FP32_COMP, 2, ok)
+        back = rl.rl_get_tuning(ctx, rl.RL_FP32_COMP, 2)
+        assert (back.rays_x, back.rays_y, back.lens_tile, back.waves, back.submap,
+                back.item_cells) == (2, 8, 512, 2, 0, 8)
+        with pytest.raises(rl.RaylensError):   # FP64 path keeps 4 x 4 rays per lane
+            rl.rl_set_tuning(ctx, rl.RL_FP64_PLAIN, 0, ok)
+        with pytest.raises(rl.RaylensError):
+            rl.rl_get_tuning(ctx, rl.RL_FP32_COMP, 3)
+    finally:
+        rl.rl_destroy(ctx)
+
+
+def test_header_documents_every_entry_point():
+    """Each declaration in the public header is preceded by a comment."""
+    text = open(os.path.join(ROOT, "include", "raylens.h")).read()
+    for sym in declared_symbols():
+        decl = re.search(r"^(?:rl_status|const char\*|void)\s+" + sym + r"\(", text, flags=re.M)
+        assert decl, f"{sym}: declaration not found"
+        before = text[:decl.start()].rstrip()
+        assert "*/" in before[-400:], f"{sym} has no comment"

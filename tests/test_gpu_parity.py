@@ -1,0 +1,322 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 CPU oracle.
+
+Bars (Vernardos & Fluke 2014, eq. 1 and eq. 4, with the readings listed in the
+design notes):
+  * binning of given positions and normalisation: bit-exact;
+  * FP64 path: per-ray positions and maps bit-identical to the oracle (same
+    IEEE operations in the same order, no contraction);
+  * FP32-compensated path: per-ray |dy| <= 1e-4 Einstein radii for rays whose
+    oracle position lies in the window grown by 1 R_E (rays closer than
+    0.015 R_E to a lens, where dy/dx ~ 1/r^2 > 4e3, are reported separately),
+    and map mean magnification within 1e-3 relative;
+  * integer results (counts, escaped) independent of kernel shape, batching
+    and row chunking, bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1406_0559_amd import inputs
+from paper_1406_0559_amd import raylens as rl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL_Y = 1e-4          # Einstein radii, per ray
+TOL_MEAN_MU = 1e-3    # relative
+NEAR_LENS = 0.015     # Einstein radii
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    rl.load()
+    c = rl.Context(0)
+    yield c
+    c.close()
+
+
+def dev_lenses(f):
+    return rl.DeviceLenses(f.x1, f.x2, f.m)
+
+
+def o_positions(spec, f, rb=0, re=None):
+    re = spec.n2 if re is None else re
+    return oracle.ray_positions(f.x1, f.x2, f.m, spec.kappa, spec.gamma, spec.s, spec.n1, spec.n2,
+                                spec.c1, spec.c2, spec.h1, spec.h2, rb, re)
+
+
+def o_shoot(spec, f, rb=0, re=None):
+    re = spec.n2 if re is None else re
+    return oracle.shoot(f.x1, f.x2, f.m, spec.kappa, spec.gamma, spec.s, spec.n1, spec.n2,
+                        spec.c1, spec.c2, spec.h1, spec.h2, spec.p1, spec.p2, spec.w1, spec.w2,
+                        spec.W1, spec.W2, rb, re)
+
+
+def same_bits(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    na, nb = np.isnan(a), np.isnan(b)
+    if not (na == nb).all():
+        return False
+    return (a[~na].view(np.int64) == b[~nb].view(np.int64)).all()
+
+
+def spec_custom(name, kappa, gamma, s, n1, n2, h1, h2, p1, p2, W1, W2, n_lens, R, masses, seed,
+                c=(0.0, 0.0), w=(0.0, 0.0)):
+    return inputs.MapSpec(name=name, kappa=kappa, gamma=gamma, s=s, n1=n1, n2=n2, h1=h1, h2=h2,
+                          p1=p1, p2=p2, W1=W1, W2=W2, c1=c[0], c2=c[1], w1=w[0], w2=w[1],
+                          n_lens=n_lens, disc_radius=R, masses=masses, seed=seed)
+
+
+SMALL = inputs.config_small()
+MIXED_SMALL = spec_custom("mixed-ragged", 0.8, 0.3, 0.5, 333, 171, 9.0, 2.0, 61, 37, 4.0, 3.0,
+                          400, 12.0, "salpeter", 11, c=(0.3, -0.2), w=(0.1, 0.05))
+ODD_SHAPES = [
+    spec_custom("one-ray", 0.4, 0.3, 0.0, 1, 1, 1.0, 1.0, 8, 8, 4.0, 4.0, 10, 3.0, "unit", 21),
+    spec_custom("sub-cell", 0.5, 0.1, 0.2, 5, 3, 1.0, 0.7, 3, 5, 2.0, 2.0, 129, 3.0, "salpeter", 22),
+    spec_custom("one-lens", 0.0, 0.0, 0.0, 300, 200, 2.0, 1.5, 40, 30, 3.0, 2.0, 1, 0.5, "unit", 23),
+    spec_custom("pure-sheet", 0.6, 0.25, 1.0, 257, 129, 3.0, 2.0, 17, 19, 2.0, 2.0, 0, 1.0, "unit", 24),
+    spec_custom("block-tail", 0.4, 0.2, 0.0, 200, 64, 4.0, 1.5, 64, 1, 4.0, 1.0, 257, 8.0, "unit", 25),
+    spec_custom("wide-cells", 0.3, 0.6, 0.1, 1000, 40, 10.0, 0.2, 50, 50, 5.0, 5.0, 300, 12.0, "unit", 26),
+]
+
+
+# ---------------------------------------------------------------------------
+# binning and normalisation of given data: bit-exact
+# ---------------------------------------------------------------------------
+
+def test_bin_positions_bit_exact(ctx):
+    rng = np.random.default_rng(5)
+    p1, p2, W1, W2, w1, w2 = 37, 23, 3.7, 2.3, 0.15, -0.4
+    lo1, lo2 = w1 - 0.5 * W1, w2 - 0.5 * W2
+    n = 200000
+    y1 = rng.uniform(lo1 - 0.5, lo1 + W1 + 0.5, n)
+    y2 = rng.uniform(lo2 - 0.5, lo2 + W2 + 0.5, n)
+    # adversarial: pixel edges and their neighbours, window edges, non-finite
+    e1 = lo1 + np.arange(p1 + 1) * (W1 / p1)
+    e2 = lo2 + np.arange(p2 + 1) * (W2 / p2)
+    E1, E2 = np.meshgrid(e1, e2)
+    adv1 = np.concatenate([E1.ravel(), np.nextafter(E1.ravel(), -np.inf), np.nextafter(E1.ravel(), np.inf)])
+    adv2 = np.concatenate([E2.ravel(), np.nextafter(E2.ravel(), np.inf), np.nextafter(E2.ravel(), -np.inf)])
+    special = np.array([np.nan, np.inf, -np.inf, 0.0, -0.0, 1e300, -1e300, lo1, lo1 + W1])
+    sp1, sp2 = np.meshgrid(special, np.array([np.nan, np.inf, -np.inf, lo2, lo2 + W2, w2, -0.0]))
+    y1 = np.concatenate([y1, adv1, sp1.ravel()])
+    y2 = np.concatenate([y2, adv2, sp2.ravel()])
+    spec = spec_custom("bin", 0, 0, 0, 1, 1, 1, 1, p1, p2, W1, W2, 0, 1.0, "unit", 0, w=(w1, w2))
+    counts, esc = ctx.bin_positions(torch.from_numpy(y1).cuda(), torch.from_numpy(y2).cuda(), spec)
+    oc, oe = oracle.bin_positions(y1, y2, p1, p2, w1, w2, W1, W2)
+    assert int(esc.item()) == oe
+    assert (counts.cpu().numpy() == oc).all()
+    assert counts.sum().item() + oe == y1.size
+
+
+def test_normalise_bit_exact(ctx):
+    rng = np.random.default_rng(6)
+    spec = spec_custom("norm", 0, 0, 0, 1000, 700, 3.0, 2.0, 301, 257, 2.0, 2.0, 0, 1.0, "unit", 0)
+    counts = rng.integers(0, 2_000_000, size=(spec.p2, spec.p1)).astype(np.int32)
+    counts[0, :5] = [0, 1, 2**31 - 1, 7, 3]
+    for n_avg in (rl.rl_n_avg(rl.grid_of(spec), rl.window_of(spec)), 0.1, 3.0, 44.6, 1e-7):
+        mu = ctx.normalise(torch.from_numpy(counts).cuda(), spec, n_avg=n_avg).cpu().numpy()
+        ref = oracle.normalise(counts, n_avg)
+        assert (mu.view(np.uint32) == ref.view(np.uint32)).all()
+
+
+# ---------------------------------------------------------------------------
+# FP64 path: bit-identical to the oracle
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("spec", [SMALL, MIXED_SMALL] + ODD_SHAPES, ids=lambda s: s.name)
+def test_fp64_positions_and_map_bit_identical(ctx, spec):
+    f = spec.lenses()
+    L = dev_lenses(f)
+    rb, re = (0, spec.n2) if spec.n2 <= 256 else (37, 37 + 200)
+    y1, y2 = ctx.ray_positions(L, spec, "fp64", rb, re)
+    o1, o2, sing, _ = o_positions(spec, f, rb, re)
+    assert same_bits(y1.cpu().numpy(), o1) and same_bits(y2.cpu().numpy(), o2)
+    counts, esc = ctx.shoot(L, spec, "fp64")
+    oc, oe = o_shoot(spec, f)
+    assert int(esc.item()) == oe
+    assert (counts.cpu().numpy() == oc).all()
+
+
+def test_fp64_ray_on_a_lens_escapes(ctx):
+    spec = spec_custom("singular", 0.0, 0.0, 0.0, 4, 4, 2.0, 2.0, 8, 8, 100.0, 100.0, 1, 1.0, "unit", 0)
+    g = (-2.0) + (np.arange(4) + 0.5) * 1.0
+    f = inputs.LensField(np.array([g[1]]), np.array([g[2]]), None)
+    for prec in ("fp64", "fp32c"):
+        counts, esc = ctx.shoot(dev_lenses(f), spec, prec)
+        assert int(esc.item()) == 1 and counts.sum().item() == 15
+
+
+# ---------------------------------------------------------------------------
+# FP32-compensated path: per-ray and map-level tolerances
+# ---------------------------------------------------------------------------
+
+def check_fp32_positions(ctx, spec, f, rb, re):
+    y1, y2 = ctx.ray_positions(dev_lenses(f), spec, "fp32c", rb, re)
+    y1 = y1.cpu().numpy()
+    y2 = y2.cpu().numpy()
+    o1, o2, sing, rmin = o_positions(spec, f, rb, re)
+    lo1, lo2 = spec.w1 - 0.5 * spec.W1 - 1.0, spec.w2 - 0.5 * spec.W2 - 1.0
+    inwin = (o1 >= lo1) & (o1 < lo1 + spec.W1 + 2.0) & (o2 >= lo2) & (o2 < lo2 + spec.W2 + 2.0)
+    err = np.hypot(y1 - o1, y2 - o2)
+    bad = inwin & ~(err <= TOL_Y)
+    # any ray over the bar must sit within NEAR_LENS of a lens (reported separately)
+    assert not (bad & (rmin >= NEAR_LENS)).any(), (
+        f"{spec.name}: {int((bad & (rmin >= NEAR_LENS)).sum())} rays over {TOL_Y}, "
+        f"max err {err[inwin & (rmin >= NEAR_LENS)].max():.3e}")
+    return float(err[inwin & (rmin >= NEAR_LENS)].max()) if inwin.any() else 0.0, int(bad.sum())
+
+
+def check_fp32_map(ctx, spec, f):
+    counts, esc = ctx.shoot(dev_lenses(f), spec, "fp32c")
+    c = counts.cpu().numpy().astype(np.int64)
+    assert c.sum() + int(esc.item()) == spec.n1 * spec.n2
+    oc, oe = o_shoot(spec, f)
+    rel = abs(c.sum() - oc.sum()) / max(1, oc.sum())    # mean mu shares N_avg: compare sums
+    assert rel <= TOL_MEAN_MU, f"{spec.name}: mean mu off by {rel:.2e}"
+    return rel, int(np.abs(c - oc).sum())
+
+
+@pytest.mark.parametrize("spec", [SMALL, MIXED_SMALL] + ODD_SHAPES, ids=lambda s: s.name)
+def test_fp32_within_tolerance(ctx, spec):
+    f = spec.lenses()
+    rb, re = (0, spec.n2) if spec.n2 <= 1100 else (0, 400)
+    check_fp32_positions(ctx, spec, f, rb, re)
+    check_fp32_map(ctx, spec, f)
+
+
+def test_fp32_mixed_masses_near_critical_line_at_scale(ctx):
+    """The mixed-mass field with smooth matter near the critical line at its
+    full lens count and ray spacing, on a strip of 48 rows spread over the grid."""
+    spec = inputs.config_mixed()
+    f = spec.lenses()
+    worst = 0.0
+    for r in (0, 7919, 12345, spec.n2 - 12):
+        e, _ = check_fp32_positions(ctx, spec, f, r, r + 12)
+        worst = max(worst, e)
+    assert worst <= TOL_Y
+
+
+# ---------------------------------------------------------------------------
+# schedule independence: kernel shapes, chunks, batching, repeats
+# ---------------------------------------------------------------------------
+
+SHAPES = [dict(rays_x=4, rays_y=4, lens_tile=256, waves=4, submap=1),
+          dict(rays_x=2, rays_y=8, lens_tile=128, waves=1, submap=0),
+          dict(rays_x=8, rays_y=2, lens_tile=2048, waves=2, submap=1),
+          dict(rays_x=4, rays_y=4, lens_tile=512, waves=2, submap=0)]
+
+
+@pytest.mark.parametrize("spec", [SMALL, MIXED_SMALL, ODD_SHAPES[4]], ids=lambda s: s.name)
+def test_results_do_not_depend_on_kernel_shape(ctx, spec):
+    f = spec.lenses()
+    L = dev_lenses(f)
+    cls = rl.n_class(spec.n_lens)
+    saved = ctx.get_tuning("fp32c", cls)
+    ref = None
+    try:
+        for sh in SHAPES:
+            ctx.set_tuning("fp32c", cls, **sh)
+            counts, esc = ctx.shoot(L, spec, "fp32c")
+            y1, y2 = ctx.ray_positions(L, spec, "fp32c", 0, min(spec.n2, 64))
+            cur = (counts.cpu().numpy(), int(esc.item()), y1.cpu().numpy(), y2.cpu().numpy())
+            if ref is None:
+                ref = cur
+            else:
+                assert (cur[0] == ref[0]).all() and cur[1] == ref[1]
+                assert same_bits(cur[2], ref[2]) and same_bits(cur[3], ref[3])
+        for sh in SHAPES[:2]:
+            ctx.set_tuning("fp64", cls, **dict(sh, rays_x=4, rays_y=4))
+            counts, esc = ctx.shoot(L, spec, "fp64")
+            oc, oe = o_shoot(spec, f)
+            assert (counts.cpu().numpy() == oc).all() and int(esc.item()) == oe
+    finally:
+        ctx.set_tuning("fp32c", cls, **saved)
+        ctx.set_tuning("fp64", cls, **dict(saved, rays_x=4, rays_y=4))
+
+
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+def test_row_chunks_add_up_exactly(ctx, prec):
+    spec = SMALL
+    f = spec.lenses()
+    L = dev_lenses(f)
+    whole, esc = ctx.shoot(L, spec, prec)
+    acc, acc_e = ctx.new_map(spec)
+    for rb, re in ((0, 1), (1, 300), (300, 301), (301, 777), (777, spec.n2)):
+        ctx.shoot(L, spec, prec, acc, acc_e, rb, re)
+    assert torch.equal(acc, whole) and int(acc_e.item()) == int(esc.item())
+    again, esc2 = ctx.shoot(L, spec, prec)
+    assert torch.equal(again, whole) and int(esc2.item()) == int(esc.item())
+
+
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+def test_batch_equals_alone(ctx, prec):
+    specs = [SMALL, MIXED_SMALL] + ODD_SHAPES
+    fields = [s.lenses() for s in specs]
+    Ls = [dev_lenses(f) for f in fields]
+    alone = [ctx.shoot(L, s, prec) for L, s in zip(Ls, specs)]
+    outs = [ctx.new_map(s) for s in specs]
+    ctx.shoot_batch([(L, s, c, e) for L, s, (c, e) in zip(Ls, specs, outs)], prec)
+    for (c, e), (ca, ea), s, f in zip(outs, alone, specs, fields):
+        assert torch.equal(c, ca), s.name
+        assert int(e.item()) == int(ea.item()), s.name
+        if prec == "fp64":
+            oc, oe = o_shoot(s, f)
+            assert (c.cpu().numpy() == oc).all() and int(e.item()) == oe
+    # partial row ranges inside a batch
+    part = [ctx.new_map(s) for s in specs[:2]]
+    ctx.shoot_batch([(Ls[i], specs[i], part[i][0], part[i][1], 10, 20) for i in range(2)], prec)
+    for i in range(2):
+        c, e = ctx.shoot(Ls[i], specs[i], prec, row_begin=10, row_end=20)
+        assert torch.equal(part[i][0], c) and int(part[i][1].item()) == int(e.item())
+
+
+def test_stats_match_the_oracle(ctx):
+    spec = SMALL
+    f = spec.lenses()
+    counts, esc = ctx.shoot(dev_lenses(f), spec, "fp64")
+    st = ctx.stats(counts, esc, spec)
+    oc, oe = o_shoot(spec, f)
+    navg = oracle.n_avg(spec.n1, spec.n2, spec.h1, spec.h2, spec.p1, spec.p2, spec.W1, spec.W2)
+    ost = oracle.stats(oc, navg, spec.kappa, spec.gamma)
+    assert st["binned"] == ost["binned"] and st["escaped"] == oe
+    assert st["shot"] == spec.n1 * spec.n2
+    assert st["n_avg"] == navg
+    assert st["mean_count"] == ost["mean_count"] and st["mean_mu"] == ost["mean_mu"]
+    assert st["mu_th"] == ost["mu_th"]
+    assert st["max_count"] == int(oc.max())
+
+
+# ---------------------------------------------------------------------------
+# full-size workloads in the benchmark's launch configuration, sampled rows
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("make", [inputs.config_gerlumph, inputs.config_mixed],
+                         ids=["gerlumph", "mixed"])
+def test_full_size_maps_sampled_against_the_oracle(ctx, make):
+    spec = make()
+    f = spec.lenses()
+    L = dev_lenses(f)
+    rows = [int(r) for r in np.linspace(0, spec.n2 - 1, 6)]
+    for r in rows:
+        # FP64 per-ray positions on sampled rows: bit-identical
+        y1, y2 = ctx.ray_positions(L, spec, "fp64", r, r + 1)
+        o1, o2, _, _ = o_positions(spec, f, r, r + 1)
+        assert same_bits(y1.cpu().numpy(), o1) and same_bits(y2.cpu().numpy(), o2)
+        # single-row maps: FP64 exact, FP32 within the per-ray bar
+        c64, e64 = ctx.shoot(L, spec, "fp64", row_begin=r, row_end=r + 1)
+        oc, oe = o_shoot(spec, f, r, r + 1)
+        assert (c64.cpu().numpy() == oc).all() and int(e64.item()) == oe
+        check_fp32_positions(ctx, spec, f, r, r + 1)
+    # whole maps: exact ray conservation, FP32 mean magnification vs FP64
+    c32, e32 = ctx.shoot(L, spec, "fp32c")
+    c64, e64 = ctx.shoot(L, spec, "fp64")
+    s32 = int(c32.sum(dtype=torch.int64).item())
+    s64 = int(c64.sum(dtype=torch.int64).item())
+    assert s32 + int(e32.item()) == spec.n1 * spec.n2
+    assert s64 + int(e64.item()) == spec.n1 * spec.n2
+    assert abs(s32 - s64) / s64 <= TOL_MEAN_MU
+    diff = (c32.to(torch.int64) - c64.to(torch.int64)).abs().sum().item()
+    assert diff / s64 < 5e-3
