@@ -1,0 +1,208 @@
+#!/usr/bin/env python3
+"""Benchmark of the ray-shooting hot path on one MI355X.
+
+Workload (one "step" = one whole magnification map): the GERLUMPH-like map
+of 30000 x 30000 rays through 2624 unit point lenses (kappa = 0.41, s = 0,
+gamma = 0.38) onto a 4096^2 map of 25 x 25 Einstein radii, with synthetic
+seeded lens positions standing in for GERLUMPH's. A step runs the FP32-
+compensated shooter, the normalisation to magnification and the statistics
+reduction, with the lens field already resident in HBM.
+
+Printed: one JSON line with ray-lens evaluations per second (the headline),
+the FP64-plain rate on the same map and the speed-up, maps/hour and per-map
+latency percentiles, the batched 64-map workload's maps/hour, a roofline entry
+for the dominant kernel (timed with events on the stream it runs on) and the
+oracle's rate on a bounded sample on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP32_PEAK_TFLOPS = 157.3          # MI355X FP32 vector peak (AMD published)
+FP64_PEAK_TFLOPS = 78.6           # MI355X FP64 vector peak (AMD published)
+FLOPS_PER_EVAL = 10               # ~10 flops per lens per ray (Section 2.1)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-map batched workload")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target oracle time for the CPU baseline sample")
+    ap.add_argument("--workload", default="gerlumph-30000sq-2624")
+    return ap.parse_args()
+
+
+def percentile(xs, q):
+    return float(np.percentile(np.asarray(xs), q)) if xs else None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the path is a single-GPU "
+                          "kernel and no multi-GPU run is part of it", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_1406_0559_amd import inputs
+    from paper_1406_0559_amd import raylens as rl
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    rl.load()
+    spec = inputs.WORKLOADS[args.workload]()
+    field = spec.lenses()
+    ctx = rl.Context(0)
+    L = rl.DeviceLenses(field.x1, field.x2, field.m)
+    counts, esc = ctx.new_map(spec)
+    mu = torch.empty((spec.p2, spec.p1), dtype=torch.float32, device="cuda")
+    n_avg = rl.rl_n_avg(rl.grid_of(spec), rl.window_of(spec))
+    stream = torch.cuda.current_stream()
+    evals = spec.evals
+
+    def step(prec, ev=None):
+        counts.zero_()
+        esc.zero_()
+        if ev is not None:
+            ev[0].record(stream)
+        ctx.shoot(L, spec, prec, counts, esc, stream=stream)
+        if ev is not None:
+            ev[1].record(stream)
+        ctx.normalise(counts, spec, n_avg=n_avg, mu=mu, stream=stream)
+        return ctx.stats(counts, esc, spec, stream=stream)   # synchronises the stream
+
+    # ---- FP32-compensated: the timed steps -------------------------------------
+    for _ in range(args.warmup):
+        step("fp32c")
+    torch.cuda.synchronize()
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        st = step("fp32c", events[k])
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = [a.elapsed_time(b) for a, b in events]
+    kern_avg_s = float(np.mean(kern_ms)) / 1e3
+    ms_per_step = wall / args.steps * 1e3
+    value = evals * args.steps / wall
+    assert st["binned"] + st["escaped"] == spec.rays, "ray conservation failed"
+
+    # ---- FP64 plain on the same map ---------------------------------------------
+    fp64 = None
+    if args.fp64_steps > 0:
+        step("fp64")
+        ev64 = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                for _ in range(args.fp64_steps)]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for k in range(args.fp64_steps):
+            st64 = step("fp64", ev64[k])
+        torch.cuda.synchronize()
+        w64 = time.perf_counter() - t1
+        k64 = float(np.mean([a.elapsed_time(b) for a, b in ev64])) / 1e3
+        fp64 = {"evals_per_s": evals * args.fp64_steps / w64,
+                "kernel_ms": k64 * 1e3,
+                "tflops_alg": FLOPS_PER_EVAL * evals / k64 / 1e12,
+                "frac_fp64_peak": FLOPS_PER_EVAL * evals / k64 / 1e12 / FP64_PEAK_TFLOPS,
+                "mean_mu": st64["mean_mu"],
+                "mean_mu_rel_diff_fp32c": abs(st["mean_mu"] - st64["mean_mu"]) / st64["mean_mu"]}
+
+    # ---- 64-map batched persistent launch ---------------------------------------
+    batch = None
+    if not args.no_batch:
+        maps = inputs.config_batch()
+        Ls = [rl.DeviceLenses(*(lambda f: (f.x1, f.x2, f.m))(m.lenses())) for m in maps]
+        outs = [ctx.new_map(m) for m in maps]
+        items = [(Lb, m, c, e) for Lb, m, (c, e) in zip(Ls, maps, outs)]
+
+        def run_batch():
+            for c, e in outs:
+                c.zero_()
+                e.zero_()
+            ctx.shoot_batch(items, "fp32c", stream=stream)
+            torch.cuda.synchronize()
+
+        run_batch()
+        tb = time.perf_counter()
+        run_batch()
+        wb = time.perf_counter() - tb
+        bevals = sum(m.evals for m in maps)
+        batch = {"workload": "batch-64x1024sq", "maps": len(maps), "seconds": wb,
+                 "maps_per_hour": len(maps) * 3600.0 / wb, "evals_per_s": bevals / wb}
+
+    # ---- CPU baseline: the oracle on a bounded row sample of the same map ---------
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        nthreads = oracle.max_threads()
+        r0 = spec.n2 // 2
+        probe_rows = max(2, nthreads)
+        tp = time.perf_counter()
+        oracle.shoot(field.x1, field.x2, field.m, spec.kappa, spec.gamma, spec.s, spec.n1, spec.n2,
+                     spec.c1, spec.c2, spec.h1, spec.h2, spec.p1, spec.p2, spec.w1, spec.w2,
+                     spec.W1, spec.W2, r0, r0 + probe_rows)
+        per_row = (time.perf_counter() - tp) / probe_rows
+        rows = int(max(probe_rows, min(spec.n2 - r0, args.cpu_seconds / max(per_row, 1e-9))))
+        tc = time.perf_counter()
+        oracle.shoot(field.x1, field.x2, field.m, spec.kappa, spec.gamma, spec.s, spec.n1, spec.n2,
+                     spec.c1, spec.c2, spec.h1, spec.h2, spec.p1, spec.p2, spec.w1, spec.w2,
+                     spec.W1, spec.W2, r0, r0 + rows)
+        tcpu = time.perf_counter() - tc
+        cpu = {"value": rows * spec.n1 * spec.n_lens / tcpu, "unit": "evals/s", "cores": nthreads,
+               "kind": "oracle",
+               "sample": f"ray rows [{r0}, {r0 + rows}) of the {spec.n1}x{spec.n2} grid "
+                         f"({rows * spec.n1} rays x {spec.n_lens} lenses, FP64, OpenMP), "
+                         f"{tcpu:.1f} s"}
+
+    achieved = FLOPS_PER_EVAL * evals / kern_avg_s / 1e12
+    out = {
+        "metric": "ray-lens evals/s FP32-comp vs FP64 plain; maps/hour + p50/p99 map latency",
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": spec.name, "rays": f"{spec.n1}x{spec.n2}", "lenses": spec.n_lens,
+                   "map": f"{spec.p1}x{spec.p2}", "width_RE": spec.W1, "kappa": spec.kappa,
+                   "gamma": spec.gamma, "s": spec.s, "evals_per_map": evals},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "shoot_kernel (FP32-compensated)",
+                     "kernel_ms": kern_avg_s * 1e3,
+                     "algorithmic_flops_per_launch": FLOPS_PER_EVAL * evals},
+        "cpu_baseline": cpu,
+        "fp64_plain": fp64,
+        "speedup_fp32c_over_fp64": (value / fp64["evals_per_s"]) if fp64 else None,
+        "maps_per_hour": 3600.0 / (ms_per_step / 1e3),
+        "map_latency_ms": {"p50": percentile(lat, 50) * 1e3, "p99": percentile(lat, 99) * 1e3},
+        "mean_mu": st["mean_mu"],
+        "mu_th": st["mu_th"],
+        "batch": batch,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
