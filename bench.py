@@ -41,6 +41,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target oracle time for the CPU baseline sample")
     ap.add_argument("--workload", default="gerlumph-30000sq-2624")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-scale", type=float, default=0.25,
+                    help="map-size scale of the served requests (1.0 = 1024^2-4096^2 maps)")
+    ap.add_argument("--no-tuning-cache", action="store_true")
     return ap.parse_args()
 
 
@@ -56,6 +61,7 @@ def main():
         sys.exit(2)
 
     import torch
+    from paper_1406_0559_amd import autotune
     from paper_1406_0559_amd import inputs
     from paper_1406_0559_amd import raylens as rl
 
@@ -64,6 +70,7 @@ def main():
     spec = inputs.WORKLOADS[args.workload]()
     field = spec.lenses()
     ctx = rl.Context(0)
+    tuned = False if args.no_tuning_cache else autotune.apply(ctx, autotune.load())
     L = rl.DeviceLenses(field.x1, field.x2, field.m)
     counts, esc = ctx.new_map(spec)
     mu = torch.empty((spec.p2, spec.p1), dtype=torch.float32, device="cuda")
@@ -146,6 +153,34 @@ def main():
         batch = {"workload": "batch-64x1024sq", "maps": len(maps), "seconds": wb,
                  "maps_per_hour": len(maps) * 3600.0 / wb, "evals_per_s": bevals / wb}
 
+    # ---- serving: Poisson stream of map requests, continuous batching -------------
+    serving = None
+    if not args.no_serve:
+        from paper_1406_0559_amd import serve
+        probe = inputs.serve_requests(args.serve_requests, rate=1.0, seed=5,
+                                      size_scale=args.serve_scale)
+        mean_evals = float(np.mean([r.spec.evals for r in probe]))
+        lam = 0.7 * value / mean_evals          # 70 % of the saturated request rate
+        reqs = inputs.serve_requests(args.serve_requests, rate=lam, seed=5,
+                                     size_scale=args.serve_scale)
+        mreqs = [serve.MapRequest(r.rid, r.spec, r.spec.lenses(), r.arrival) for r in reqs]
+        be = serve.GpuBackend(ctx=ctx)
+        sch = serve.Scheduler(be, budget_bytes=serve.gpu_budget_bytes(0.5), max_active=16,
+                              chunk_evals=2e11, max_inflight=2)
+        ts = time.perf_counter()
+        res = sch.run(mreqs)
+        tserve = time.perf_counter() - ts
+        summ = serve.latency_summary(res)
+        sizes = sorted({r.spec.p1 for r in reqs})
+        serving = {"workload": f"serve-{args.serve_requests}req-maps{sizes[0]}-{sizes[-1]}",
+                   "arrival_rate_per_s": lam, "mean_evals_per_request": mean_evals,
+                   "launches": sch.launches, "peak_active": sch.peak_active,
+                   "wall_s": tserve, **summ,
+                   "p50_ms": summ["p50_s"] * 1e3 if summ["p50_s"] is not None else None,
+                   "p99_ms": summ["p99_s"] * 1e3 if summ["p99_s"] is not None else None,
+                   "evals_per_s": sum(r.spec.evals for r in reqs) / summ["makespan_s"]
+                   if summ["makespan_s"] else None}
+
     # ---- CPU baseline: the oracle on a bounded row sample of the same map ---------
     cpu = None
     if not args.no_cpu_baseline:
@@ -200,6 +235,8 @@ def main():
         "mean_mu": st["mean_mu"],
         "mu_th": st["mu_th"],
         "batch": batch,
+        "serving": serving,
+        "tuning": "autotuned cache" if tuned else "defaults",
     }
     print(json.dumps(out), flush=True)
 

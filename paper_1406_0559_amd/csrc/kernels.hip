@@ -89,14 +89,23 @@ __device__ __forceinline__ void lens_step_f32(const float* __restrict__ wl, int 
         dy2[b] = dy[b] * dy[b];
         wy[b] = MASS ? lm * dy[b] : dy[b];
     }
+    // Phase-ordered: all r^2, then all reciprocals, then all accumulations, so
+    // no v_rcp_f32 result is consumed right after it issues.
+    float inv[KX * KY];
+#pragma unroll
+    for (int a = 0; a < KX; ++a)
+#pragma unroll
+        for (int b = 0; b < KY; ++b) inv[a * KY + b] = __builtin_fmaf(dx[a], dx[a], dy2[b]);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int r = 0; r < KX * KY; ++r) inv[r] = __builtin_amdgcn_rcpf(inv[r]);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int a = 0; a < KX; ++a) {
 #pragma unroll
         for (int b = 0; b < KY; ++b) {
-            const float r2 = __builtin_fmaf(dx[a], dx[a], dy2[b]);
-            const float inv = __builtin_amdgcn_rcpf(r2);
-            p1[a * KY + b] = __builtin_fmaf(wx[a], inv, p1[a * KY + b]);
-            p2[a * KY + b] = __builtin_fmaf(wy[b], inv, p2[a * KY + b]);
+            p1[a * KY + b] = __builtin_fmaf(wx[a], inv[a * KY + b], p1[a * KY + b]);
+            p2[a * KY + b] = __builtin_fmaf(wy[b], inv[a * KY + b], p2[a * KY + b]);
         }
     }
 }

@@ -74,6 +74,12 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1406_0559_amd/build.py "
                            "(or __graft_entry__.build()); there is no fallback")
+    # PyTorch ships its own HIP runtime and asks for it as "libamdhip64.so";
+    # the library asks for "libamdhip64.so.7". Loading torch first makes the
+    # library bind to torch's runtime (same soname), so one runtime owns the
+    # streams and device memory that torch hands to the library. Loaded the
+    # other way round, the process would hold two runtimes.
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     P = C.POINTER
     vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double

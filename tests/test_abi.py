@@ -145,3 +145,20 @@ def test_header_documents_every_entry_point():
         assert decl, f"{sym}: declaration not found"
         before = text[:decl.start()].rstrip()
         assert "*/" in before[-400:], f"{sym} has no comment"
+
+
+def test_one_hip_runtime_per_process():
+    """Loading the library before torch must not leave two HIP runtimes in the
+    process (torch's bundled one and the system one): the binding loads torch
+    first so the library binds to torch's runtime."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1406_0559_amd import raylens as rl\n"
+            "rl.load()\n"
+            "import torch\n"
+            "paths = {l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}\n"
+            "print(len(paths), sorted(paths))\n") % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert out.stdout.split()[0] == "1", out.stdout
