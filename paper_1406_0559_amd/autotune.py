@@ -36,11 +36,18 @@ def candidates(precision: str):
         yield dict(rays_x=rx, rays_y=ry, lens_tile=tile, waves=waves, submap=sub)
 
 
-def probe_spec(n_lens: int, precision: str, target_evals: float) -> inputs.MapSpec:
+# a probe must keep every SIMD busy for many rounds of waves, or the tail of
+# the launch decides the ranking: >= 16 rounds of 256 CUs x 4 SIMDs x 3 waves
+MIN_PROBE_RAYS = 16 * 256 * 4 * 3 * 1024
+
+
+def probe_spec(n_lens: int, precision: str, target_evals: float,
+               min_rays: int = MIN_PROBE_RAYS) -> inputs.MapSpec:
     """A GERLUMPH-like probe (kappa = 0.41, gamma = 0.38, 25 R_E window) with
-    n_lens unit lenses and enough rays for ~target_evals evaluations."""
+    n_lens unit lenses and enough rays for ~target_evals evaluations (at
+    least min_rays)."""
     base = inputs.config_gerlumph()
-    rays = max(64 * 64, int(target_evals / max(n_lens, 1)))
+    rays = max(min_rays, int(target_evals / max(n_lens, 1)))
     n2 = int(math.sqrt(rays * base.h2 / base.h1))
     n1 = max(64, rays // max(n2, 1))
     R = math.sqrt(n_lens / base.kappa_star)
@@ -65,7 +72,8 @@ def _time(fn, reps, torch, stream):
 
 
 def tune(ctx: "rl.Context", precisions=("fp32c", "fp64"), classes=(0, 1, 2), reps: int = 2,
-         target_evals: float = 2e11, verbose: bool = False) -> Dict:
+         target_evals: float = 2e11, verbose: bool = False,
+         min_rays: int = MIN_PROBE_RAYS) -> Dict:
     """Times every candidate shape; returns the table (and leaves it applied)."""
     import torch
 
@@ -77,7 +85,7 @@ def tune(ctx: "rl.Context", precisions=("fp32c", "fp64"), classes=(0, 1, 2), rep
         for cls in classes:
             n = CLASS_PROBE_LENSES[cls]
             te = target_evals if prec == "fp32c" else target_evals / 4
-            spec = probe_spec(n, prec, te)
+            spec = probe_spec(n, prec, te, min_rays)
             f = spec.lenses()
             L = rl.DeviceLenses(f.x1, f.x2, f.m)
             counts, esc = ctx.new_map(spec)
@@ -104,8 +112,9 @@ def tune(ctx: "rl.Context", precisions=("fp32c", "fp64"), classes=(0, 1, 2), rep
             best_ms, best = results[0]
             # work-item size for the batched launch, with the best shape
             item_best, item_ms = 16, None
-            maps = [probe_spec(max(200, n // 4), prec, te / 4), probe_spec(n, prec, te / 4),
-                    probe_spec(min(20000, n * 3), prec, te / 4)]
+            maps = [probe_spec(max(200, n // 4), prec, te / 4, min_rays // 4),
+                    probe_spec(n, prec, te / 4, min_rays // 4),
+                    probe_spec(min(20000, n * 3), prec, te / 4, min_rays // 4)]
             fields = [m.lenses() for m in maps]
             Ls = [rl.DeviceLenses(x.x1, x.x2, x.m) for x in fields]
             outs = [ctx.new_map(m) for m in maps]

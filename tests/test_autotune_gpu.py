@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 def test_tune_save_load_apply(tmp_path):
     ctx = rl.Context(0)
     table = autotune.tune(ctx, precisions=("fp32c", "fp64"), classes=(0,), reps=1,
-                          target_evals=2e9)
+                          target_evals=2e9, min_rays=1 << 20)
     for key in ("fp32c/0", "fp64/0"):
         ent = table["entries"][key]
         assert ent["candidates"] >= 24 and ent["best_ms"] <= ent["worst_ms"]
