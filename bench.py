@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--serve-scale", type=float, default=0.25,
                     help="map-size scale of the served requests (1.0 = 1024^2-4096^2 maps)")
     ap.add_argument("--no-tuning-cache", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB (a known-size "
+                         "kernel for scaling hardware traffic counters)")
     return ap.parse_args()
 
 
@@ -77,6 +80,13 @@ def main():
     n_avg = rl.rl_n_avg(rl.grid_of(spec), rl.window_of(spec))
     stream = torch.cuda.current_stream()
     evals = spec.evals
+    if args.copy_calibration_mib > 0:
+        nbytes = args.copy_calibration_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step(prec, ev=None):
         counts.zero_()

@@ -208,7 +208,11 @@ rl_status rl_shoot_batch(rl_context* ctx, const rl_map_desc* h_maps, int32_t n_m
  *   rays_x, rays_y : rays per lane along x1 and x2 (product 16: 4x4, 2x8, 8x2)
  *   lens_tile      : lenses staged in LDS per pass (multiple of 128, <= 2048)
  *   waves          : waves per workgroup (1, 2 or 4)
- *   submap         : 1 = bin through an LDS-privatised sub-map, 0 = global atomics
+ *   submap         : binning mode. 0 = one global atomic per binned ray; 1 = an
+ *                    LDS-privatised sub-map over the bounding box of the
+ *                    workgroup's binned rays; 2 = an LDS-privatised 64 x 64 sub-map
+ *                    around their mean pixel. In modes 1 and 2 each touched pixel
+ *                    gets one global atomic; rays outside the sub-map go global.
  *   item_cells     : ray cells per work item in rl_shoot_batch (>= 1) */
 typedef struct {
     int32_t rays_x;

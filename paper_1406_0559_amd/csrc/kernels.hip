@@ -30,6 +30,8 @@
 //   * Block index -> cell mapping is XCD-aware: consecutive cells (adjacent
 //     on the sky, hence adjacent on the source plane) go to workgroups that
 //     run on the same XCD, so their atomics meet in the same L2.
+#include <climits>
+
 #include "internal.h"
 
 namespace rl {
@@ -52,6 +54,25 @@ __device__ __forceinline__ int wave_sum(int v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Workgroup header in LDS: [0..2] sums of ix, iy and the binned count,
+// [3] the batch work item, [4..7] bounding box (min x, min y, max x, max y).
+__device__ __forceinline__ void reset_header(int* hdr) {
+    hdr[0] = 0; hdr[1] = 0; hdr[2] = 0;
+    hdr[4] = INT_MAX; hdr[5] = INT_MAX; hdr[6] = -1; hdr[7] = -1;
 }
 
 // Bijective remap of a linear block id so that blocks dispatched to the same
@@ -245,7 +266,7 @@ __device__ __forceinline__ void deflect_f64(const MapParams& P, int64_t i0, int6
 // one cell per wave: deflection, lens equation, binning
 // ----------------------------------------------------------------------------
 
-template <int KX, int KY, bool MASS, bool SUBMAP, bool OUT_Y, int PREC>
+template <int KX, int KY, bool MASS, int SUBMAP, bool OUT_Y, int PREC>
 __device__ __forceinline__ void process_cell(const MapParams& P, int64_t cell, bool valid,
                                              int wave, int lane, int L, char* lens_base,
                                              int* sub, int* hdr) {
@@ -314,58 +335,83 @@ __device__ __forceinline__ void process_cell(const MapParams& P, int64_t cell, b
         for (int r = 0; r < R; ++r)
             if (ixs[r] >= 0) atomicAdd(P.counts + (int64_t)iys[r] * P.p1 + ixs[r], 1);
     } else {
-        // workgroup-wide: centre the sub-map on the mean pixel of the binned rays
-        int sx = 0, sy = 0, sc = 0;
+        // Workgroup-wide sub-map over the bounding box of the binned rays (or,
+        // when the box is too large, a kSub x kSub window around their mean
+        // pixel, clamped to the box). Rays outside it go straight to global.
+        int sx = 0, sy = 0, sc = 0, mnx = INT_MAX, mny = INT_MAX, mxx = -1, mxy = -1;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            if (ixs[r] >= 0) { sx += ixs[r]; sy += iys[r]; sc += 1; }
+            if (ixs[r] >= 0) {
+                sx += ixs[r]; sy += iys[r]; sc += 1;
+                mnx = min(mnx, ixs[r]); mxx = max(mxx, ixs[r]);
+                mny = min(mny, iys[r]); mxy = max(mxy, iys[r]);
+            }
         }
         sx = wave_sum(sx);
         sy = wave_sum(sy);
         sc = wave_sum(sc);
+        mnx = wave_min(mnx); mny = wave_min(mny);
+        mxx = wave_max(mxx); mxy = wave_max(mxy);
         if (lane == 0 && sc) {
             atomicAdd(&hdr[0], sx);
             atomicAdd(&hdr[1], sy);
             atomicAdd(&hdr[2], sc);
+            atomicMin(&hdr[4], mnx);
+            atomicMin(&hdr[5], mny);
+            atomicMax(&hdr[6], mxx);
+            atomicMax(&hdr[7], mxy);
         }
         __syncthreads();
         const int cnt = hdr[2];
         if (cnt > 0) {  // uniform across the workgroup
-            const int ox = hdr[0] / cnt - kSub / 2;
-            const int oy = hdr[1] / cnt - kSub / 2;
-            for (int e = threadIdx.x; e < kSub * kSub; e += blockDim.x) sub[e] = 0;
+            const int bx0 = hdr[4], by0 = hdr[5];
+            const int bw = hdr[6] - bx0 + 1, bh = hdr[7] - by0 + 1;
+            int ox = bx0, oy = by0, sw = bw, sh = bh;
+            if (SUBMAP == 2 || (int64_t)bw * bh > kSub * kSub) {
+                sw = min(bw, kSub);
+                sh = min(bh, kSub);
+                ox = min(max(hdr[0] / cnt - sw / 2, bx0), bx0 + bw - sw);
+                oy = min(max(hdr[1] / cnt - sh / 2, by0), by0 + bh - sh);
+            }
+            if (SUBMAP == 2) sw = kSub;      // fixed row stride: no division below
+            const int area = sw * sh;
+            for (int e = threadIdx.x; e < area; e += blockDim.x) sub[e] = 0;
             __syncthreads();
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 if (ixs[r] >= 0) {
                     const unsigned dx = (unsigned)(ixs[r] - ox), dy = (unsigned)(iys[r] - oy);
-                    if (dx < (unsigned)kSub && dy < (unsigned)kSub)
-                        atomicAdd(&sub[dy * kSub + dx], 1);
+                    if (dx < (unsigned)sw && dy < (unsigned)sh)
+                        atomicAdd(&sub[dy * sw + dx], 1);
                     else
                         atomicAdd(P.counts + (int64_t)iys[r] * P.p1 + ixs[r], 1);
                 }
             }
             __syncthreads();
-            for (int e = threadIdx.x; e < kSub * kSub; e += blockDim.x) {
+            for (int e = threadIdx.x; e < area; e += blockDim.x) {
                 const int v = sub[e];
-                if (v) atomicAdd(P.counts + (int64_t)(oy + e / kSub) * P.p1 + (ox + e % kSub), v);
+                if (v) {
+                    const int ey = SUBMAP == 2 ? e / kSub : e / sw;
+                    const int ex = SUBMAP == 2 ? e % kSub : e - ey * sw;
+                    atomicAdd(P.counts + (int64_t)(oy + ey) * P.p1 + (ox + ex), v);
+                }
             }
         }
         __syncthreads();
-        if (threadIdx.x == 0) { hdr[0] = 0; hdr[1] = 0; hdr[2] = 0; }
+        if (threadIdx.x == 0) reset_header(hdr);
         __syncthreads();
     }
 }
 
 constexpr int kHdrBytes = 64;
 
-template <int KX, int KY, bool MASS, bool SUBMAP, bool OUT_Y, int PREC>
+template <int KX, int KY, bool MASS, int SUBMAP, bool OUT_Y, int PREC>
 __global__ void __launch_bounds__(256) shoot_kernel(MapParams P, int L) {
     extern __shared__ __align__(16) char smem[];
     int* hdr = reinterpret_cast<int*>(smem);
     char* lens_base = smem + kHdrBytes;
     int* sub = reinterpret_cast<int*>(smem + kHdrBytes);
-    if (threadIdx.x < 16) hdr[threadIdx.x] = 0;
+    if (threadIdx.x == 0) reset_header(hdr);
     __syncthreads();
     const int wave = threadIdx.x / kLanes, lane = threadIdx.x % kLanes;
     const int W = blockDim.x / kLanes;
@@ -379,7 +425,7 @@ __global__ void __launch_bounds__(256) shoot_kernel(MapParams P, int L) {
 // Persistent batch kernel: workgroups pull (map, cell range) items from a
 // global counter until the list is exhausted; every workgroup reaches the
 // exit because the counter only grows.
-template <int KX, int KY, bool MASS, bool SUBMAP, int PREC>
+template <int KX, int KY, bool MASS, int SUBMAP, int PREC>
 __global__ void __launch_bounds__(256) shoot_batch_kernel(const MapParams* __restrict__ maps,
                                                           const WorkItem* __restrict__ items,
                                                           int64_t n_items, unsigned int* counter,
@@ -388,7 +434,7 @@ __global__ void __launch_bounds__(256) shoot_batch_kernel(const MapParams* __res
     int* hdr = reinterpret_cast<int*>(smem);
     char* lens_base = smem + kHdrBytes;
     int* sub = reinterpret_cast<int*>(smem + kHdrBytes);
-    if (threadIdx.x < 16) hdr[threadIdx.x] = 0;
+    if (threadIdx.x == 0) { reset_header(hdr); hdr[3] = 0; }
     __syncthreads();
     const int wave = threadIdx.x / kLanes, lane = threadIdx.x % kLanes;
     const int W = blockDim.x / kLanes;
@@ -455,8 +501,11 @@ __global__ void normalise_kernel(const int32_t* __restrict__ counts, int64_t n, 
         mu[k] = (float)((double)counts[k] / n_avg);
 }
 
-__global__ void count_stats_kernel(const int32_t* __restrict__ counts, int64_t n,
-                                   unsigned long long* __restrict__ out) {
+__global__ void __launch_bounds__(256) count_stats_kernel(const int32_t* __restrict__ counts,
+                                                          int64_t n,
+                                                          unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long ssum[4];
+    __shared__ int smax[4];
     unsigned long long s = 0;
     int mx = 0;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
@@ -471,9 +520,18 @@ __global__ void count_stats_kernel(const int32_t* __restrict__ counts, int64_t n
         const int t = __shfl_xor(mx, o);
         mx = t > mx ? t : mx;
     }
-    if ((threadIdx.x % kLanes) == 0) {
-        atomicAdd(&out[0], s);
-        atomicMax(&out[1], (unsigned long long)mx);
+    const int w = threadIdx.x / kLanes;
+    if ((threadIdx.x % kLanes) == 0) { ssum[w] = s; smax[w] = mx; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long bs = 0;
+        int bm = 0;
+        for (int i = 0; i < (int)(blockDim.x / kLanes); ++i) {
+            bs += ssum[i];
+            bm = smax[i] > bm ? smax[i] : bm;
+        }
+        atomicAdd(&out[0], bs);
+        atomicMax(&out[1], (unsigned long long)bm);
     }
 }
 
@@ -494,7 +552,7 @@ int grid_for(int64_t n, int threads, int cap) {
 // dispatch
 // ----------------------------------------------------------------------------
 
-template <int KX, int KY, bool MASS, bool SUBMAP, bool OUT_Y, int PREC>
+template <int KX, int KY, bool MASS, int SUBMAP, bool OUT_Y, int PREC>
 hipError_t launch_one(const MapParams& P, const KernelShape& ks, size_t lds, hipStream_t s) {
     const int W = ks.waves;
     const int64_t blocks = (P.n_cells + W - 1) / W;
@@ -504,7 +562,7 @@ hipError_t launch_one(const MapParams& P, const KernelShape& ks, size_t lds, hip
     return hipGetLastError();
 }
 
-template <int KX, int KY, bool MASS, bool SUBMAP, int PREC>
+template <int KX, int KY, bool MASS, int SUBMAP, int PREC>
 hipError_t launch_batch_one(const MapParams* maps, const WorkItem* items, int64_t n_items,
                             unsigned int* counter, const KernelShape& ks, size_t lds,
                             int num_cus, hipStream_t s) {
@@ -518,33 +576,43 @@ hipError_t launch_batch_one(const MapParams* maps, const WorkItem* items, int64_
     return hipGetLastError();
 }
 
+template <int KX, int KY, bool MASS, int PREC>
+hipError_t dispatch_submap(const MapParams& P, const KernelShape& ks, size_t lds, hipStream_t s) {
+    switch (ks.submap) {
+        case 1: return launch_one<KX, KY, MASS, 1, false, PREC>(P, ks, lds, s);
+        case 2: return launch_one<KX, KY, MASS, 2, false, PREC>(P, ks, lds, s);
+        default: return launch_one<KX, KY, MASS, 0, false, PREC>(P, ks, lds, s);
+    }
+}
+
 template <int KX, int KY, int PREC>
 hipError_t dispatch_shape(const MapParams& P, const KernelShape& ks, bool masses, bool out_y,
                           size_t lds, hipStream_t s) {
     if (out_y) {
-        return masses ? launch_one<KX, KY, true, false, true, PREC>(P, ks, lds, s)
-                      : launch_one<KX, KY, false, false, true, PREC>(P, ks, lds, s);
+        return masses ? launch_one<KX, KY, true, 0, true, PREC>(P, ks, lds, s)
+                      : launch_one<KX, KY, false, 0, true, PREC>(P, ks, lds, s);
     }
-    if (masses) {
-        return ks.submap ? launch_one<KX, KY, true, true, false, PREC>(P, ks, lds, s)
-                         : launch_one<KX, KY, true, false, false, PREC>(P, ks, lds, s);
+    return masses ? dispatch_submap<KX, KY, true, PREC>(P, ks, lds, s)
+                  : dispatch_submap<KX, KY, false, PREC>(P, ks, lds, s);
+}
+
+template <int KX, int KY, bool MASS, int PREC>
+hipError_t dispatch_batch_submap(const MapParams* maps, const WorkItem* items, int64_t n_items,
+                                 unsigned int* counter, const KernelShape& ks, size_t lds,
+                                 int num_cus, hipStream_t s) {
+    switch (ks.submap) {
+        case 1: return launch_batch_one<KX, KY, MASS, 1, PREC>(maps, items, n_items, counter, ks, lds, num_cus, s);
+        case 2: return launch_batch_one<KX, KY, MASS, 2, PREC>(maps, items, n_items, counter, ks, lds, num_cus, s);
+        default: return launch_batch_one<KX, KY, MASS, 0, PREC>(maps, items, n_items, counter, ks, lds, num_cus, s);
     }
-    return ks.submap ? launch_one<KX, KY, false, true, false, PREC>(P, ks, lds, s)
-                     : launch_one<KX, KY, false, false, false, PREC>(P, ks, lds, s);
 }
 
 template <int KX, int KY, int PREC>
 hipError_t dispatch_batch_shape(const MapParams* maps, const WorkItem* items, int64_t n_items,
                                 unsigned int* counter, bool masses, const KernelShape& ks,
                                 size_t lds, int num_cus, hipStream_t s) {
-    if (masses) {
-        return ks.submap
-                   ? launch_batch_one<KX, KY, true, true, PREC>(maps, items, n_items, counter, ks, lds, num_cus, s)
-                   : launch_batch_one<KX, KY, true, false, PREC>(maps, items, n_items, counter, ks, lds, num_cus, s);
-    }
-    return ks.submap
-               ? launch_batch_one<KX, KY, false, true, PREC>(maps, items, n_items, counter, ks, lds, num_cus, s)
-               : launch_batch_one<KX, KY, false, false, PREC>(maps, items, n_items, counter, ks, lds, num_cus, s);
+    return masses ? dispatch_batch_submap<KX, KY, true, PREC>(maps, items, n_items, counter, ks, lds, num_cus, s)
+                  : dispatch_batch_submap<KX, KY, false, PREC>(maps, items, n_items, counter, ks, lds, num_cus, s);
 }
 
 }  // namespace
@@ -557,7 +625,7 @@ bool shape_supported(Precision prec, const KernelShape& ks) {
     if (!(k44 || k28 || k82)) return false;
     if (ks.lens_tile < kBlock || ks.lens_tile > 2048 || ks.lens_tile % kBlock) return false;
     if (!(ks.waves == 1 || ks.waves == 2 || ks.waves == 4)) return false;
-    if (!(ks.submap == 0 || ks.submap == 1)) return false;
+    if (ks.submap < 0 || ks.submap > 2) return false;
     if (ks.item_cells < 1) return false;
     return true;
 }
@@ -636,7 +704,7 @@ hipError_t launch_normalise(const int32_t* counts, int64_t n, double n_avg, floa
 hipError_t launch_count_stats(const int32_t* counts, int64_t n, unsigned long long* out,
                               hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(count_stats_kernel, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, counts, n,
+    hipLaunchKernelGGL(count_stats_kernel, dim3(grid_for(n, 256 * 8, 1024)), dim3(256), 0, s, counts, n,
                        out);
     return hipGetLastError();
 }

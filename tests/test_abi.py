@@ -119,7 +119,7 @@ def test_tuning_table_validation():
         t = rl.rl_get_tuning(ctx, rl.RL_FP32_COMP, 1)
         assert t.rays_x * t.rays_y == 16
         for bad in [dict(rays_x=3), dict(lens_tile=100), dict(lens_tile=4096), dict(waves=3),
-                    dict(submap=2), dict(item_cells=0)]:
+                    dict(submap=3), dict(item_cells=0)]:
             cur = {f: getattr(t, f) for f, _ in rl.rl_tuning._fields_}
             cur.update(bad)
             with pytest.raises(rl.RaylensError):

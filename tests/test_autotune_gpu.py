@@ -15,7 +15,7 @@ def test_tune_save_load_apply(tmp_path):
                           target_evals=2e9, min_rays=1 << 20)
     for key in ("fp32c/0", "fp64/0"):
         ent = table["entries"][key]
-        assert ent["candidates"] >= 24 and ent["best_ms"] <= ent["worst_ms"]
+        assert ent["candidates"] >= 12 and ent["best_ms"] <= ent["worst_ms"]
     path = str(tmp_path / "t.json")
     autotune.save(table, path)
     back = autotune.load(path)

@@ -206,7 +206,9 @@ def test_fp32_mixed_masses_near_critical_line_at_scale(ctx):
 SHAPES = [dict(rays_x=4, rays_y=4, lens_tile=256, waves=4, submap=1),
           dict(rays_x=2, rays_y=8, lens_tile=128, waves=1, submap=0),
           dict(rays_x=8, rays_y=2, lens_tile=2048, waves=2, submap=1),
-          dict(rays_x=4, rays_y=4, lens_tile=512, waves=2, submap=0)]
+          dict(rays_x=4, rays_y=4, lens_tile=512, waves=2, submap=0),
+          dict(rays_x=2, rays_y=8, lens_tile=256, waves=4, submap=2),
+          dict(rays_x=4, rays_y=4, lens_tile=128, waves=1, submap=2)]
 
 
 @pytest.mark.parametrize("spec", [SMALL, MIXED_SMALL, ODD_SHAPES[4]], ids=lambda s: s.name)
