@@ -52,6 +52,33 @@ def parse():
     return ap.parse_args()
 
 
+def kernel_source_hash():
+    import hashlib
+    path = os.path.join(ROOT, "paper_1406_0559_amd", "csrc", "kernels.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch of the FP32 shoot kernel from the rocprofv3 --pmc
+    summary in profiles/ (FETCH_SIZE and WRITE_SIZE, scaled by a known-size
+    copy), or None if none exists or the kernel source changed since."""
+    path = os.path.join(ROOT, "profiles", f"traffic_shoot_fp32c_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        line = line.strip()
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernels.hip sha256") != kernel_source_hash():
+        return None
+    fetch = float(vals["fetch bytes per launch"])
+    write = float(vals["write bytes per launch"])
+    return {"bytes": fetch + write, "fetch_bytes": fetch, "write_bytes": write,
+            "binning_mode": vals.get("binning mode"), "source": os.path.relpath(path, ROOT)}
+
+
 def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if xs else None
 
@@ -214,8 +241,28 @@ def main():
                "sample": f"ray rows [{r0}, {r0 + rows}) of the {spec.n1}x{spec.n2} grid "
                          f"({rows * spec.n1} rays x {spec.n_lens} lenses, FP64, OpenMP), "
                          f"{tcpu:.1f} s"}
+        # accuracy of the GPU positions on two sampled rows against the oracle
+        o1, o2, _, rmin = oracle.ray_positions(field.x1, field.x2, field.m, spec.kappa, spec.gamma,
+                                               spec.s, spec.n1, spec.n2, spec.c1, spec.c2, spec.h1,
+                                               spec.h2, r0, r0 + 2)
+        lo1, lo2 = spec.w1 - 0.5 * spec.W1 - 1.0, spec.w2 - 0.5 * spec.W2 - 1.0
+        inwin = (o1 >= lo1) & (o1 < lo1 + spec.W1 + 2.0) & (o2 >= lo2) & (o2 < lo2 + spec.W2 + 2.0)
+        far = inwin & (rmin >= 0.015)
+        acc = {"rows": [r0, r0 + 2], "rays_in_window": int(inwin.sum()),
+               "near_lens_rays": int((inwin & ~far).sum())}
+        for prec in ("fp32c", "fp64"):
+            g1, g2 = ctx.ray_positions(L, spec, prec, r0, r0 + 2)
+            g1 = g1.cpu().numpy()
+            g2 = g2.cpu().numpy()
+            err = np.hypot(g1 - o1, g2 - o2)
+            acc[prec] = {"max_abs_dy": float(err[far].max()) if far.any() else None,
+                         "rms_dy": float(np.sqrt(np.mean(err[far] ** 2))) if far.any() else None,
+                         "bit_identical": bool((g1.view(np.int64) == o1.view(np.int64)).all() and
+                                               (g2.view(np.int64) == o2.view(np.int64)).all())}
+        cpu["accuracy_vs_oracle"] = acc
 
     achieved = FLOPS_PER_EVAL * evals / kern_avg_s / 1e12
+    traffic = measured_traffic(spec.name)
     out = {
         "metric": "ray-lens evals/s FP32-comp vs FP64 plain; maps/hour + p50/p99 map latency",
         "value": value,
@@ -233,7 +280,9 @@ def main():
                    "map": f"{spec.p1}x{spec.p2}", "width_RE": spec.W1, "kappa": spec.kappa,
                    "gamma": spec.gamma, "s": spec.s, "evals_per_map": evals},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
+                     "traffic": traffic["bytes"] if traffic else None,
+                     "traffic_detail": traffic,
                      "kernel": "shoot_kernel (FP32-compensated)",
                      "kernel_ms": kern_avg_s * 1e3,
                      "algorithmic_flops_per_launch": FLOPS_PER_EVAL * evals},
