@@ -37,8 +37,13 @@ def lib():
         L.oracle_n_avg.restype = dbl
         L.oracle_normalise.argtypes = [vp, i64, dbl, vp]
         L.oracle_stats.argtypes = [vp, i64, dbl, dbl, dbl, vp]
+        L.oracle_count_histogram.argtypes = [vp, i64, i64, vp]
+        L.oracle_mpd_thresholds.argtypes = [dbl, dbl, dbl, dbl, i32, vp]
+        L.oracle_mpd.argtypes = [vp, i64, vp, i32, vp]
+        L.oracle_probability_sums.argtypes = [vp, i64, dbl, dbl, vp, vp]
         for f in ("oracle_ray_positions", "oracle_bin", "oracle_shoot", "oracle_normalise",
-                  "oracle_stats", "oracle_max_threads"):
+                  "oracle_stats", "oracle_max_threads", "oracle_count_histogram",
+                  "oracle_mpd_thresholds", "oracle_mpd", "oracle_probability_sums"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -139,3 +144,40 @@ def stats(counts, n_avg_value, kappa, gamma):
     if rc != 0:
         raise ValueError("oracle_stats: invalid arguments")
     return {"binned": int(out[0]), "mean_count": out[1], "mean_mu": out[2], "mu_th": out[3]}
+
+
+def count_histogram(counts, n_values):
+    """Frequency of each count value (Section 3.2.1's MPD before division by
+    the pixel count); values >= n_values - 1 land in the last entry."""
+    counts = np.ascontiguousarray(counts, dtype=np.int32)
+    hist = np.zeros(int(n_values), np.int64)
+    if lib().oracle_count_histogram(_p(counts), counts.size, int(n_values), _p(hist)) != 0:
+        raise ValueError("oracle_count_histogram: invalid arguments")
+    return hist
+
+
+def mpd_thresholds(n_avg_value, mu_ref, log_lo, log_hi, nbins):
+    thr = np.zeros(int(nbins) + 1, np.float64)
+    if lib().oracle_mpd_thresholds(n_avg_value, mu_ref, log_lo, log_hi, int(nbins), _p(thr)) != 0:
+        raise ValueError("oracle_mpd_thresholds: invalid arguments")
+    return thr
+
+
+def mpd(counts, n_avg_value, mu_ref, log_lo, log_hi, nbins):
+    """Binned MPD in log10(mu / mu_ref): [underflow, nbins bins, overflow]
+    pixel counts (divide by the pixel count for probabilities)."""
+    counts = np.ascontiguousarray(counts, dtype=np.int32)
+    thr = mpd_thresholds(n_avg_value, mu_ref, log_lo, log_hi, nbins)
+    bins = np.zeros(int(nbins) + 2, np.int64)
+    if lib().oracle_mpd(_p(counts), counts.size, _p(thr), int(nbins), _p(bins)) != 0:
+        raise ValueError("oracle_mpd: invalid arguments")
+    return bins
+
+
+def probability_sums(counts, n_avg_value, mu_lim):
+    counts = np.ascontiguousarray(counts, dtype=np.int32)
+    lo = np.zeros(1, np.int64)
+    hi = np.zeros(1, np.int64)
+    if lib().oracle_probability_sums(_p(counts), counts.size, n_avg_value, mu_lim, _p(lo), _p(hi)) != 0:
+        raise ValueError("oracle_probability_sums: invalid arguments")
+    return int(lo[0]), int(hi[0])

@@ -217,3 +217,53 @@ int oracle_stats(const int32_t* counts, int64_t n_pix, double n_avg, double kapp
     out[3] = 1.0 / ((1.0 - kappa) * (1.0 - kappa) - gamma * gamma);
     return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Magnification probability distributions (Section 3.2.1 and Section 4)
+ * ------------------------------------------------------------------------ */
+
+int oracle_count_histogram(const int32_t* counts, int64_t n_pix, int64_t n_values, int64_t* hist) {
+    if (n_pix < 0 || n_values < 1 || !hist || (n_pix > 0 && !counts)) return -1;
+    for (int64_t v = 0; v < n_values; ++v) hist[v] = 0;
+    for (int64_t k = 0; k < n_pix; ++k) {
+        const int64_t c = counts[k];
+        if (c < 0) return -1;
+        hist[c < n_values - 1 ? c : n_values - 1] += 1;
+    }
+    return 0;
+}
+
+int oracle_mpd_thresholds(double n_avg, double mu_ref, double log_lo, double log_hi, int32_t nbins,
+                          double* thr) {
+    if (!(n_avg > 0.0) || !(mu_ref > 0.0) || !isfinite(n_avg) || !isfinite(mu_ref)) return -1;
+    if (!isfinite(log_lo) || !isfinite(log_hi) || !(log_hi > log_lo) || nbins < 1 || !thr) return -1;
+    const double step = (log_hi - log_lo) / (double)nbins;
+    const double scale = n_avg * mu_ref;
+    for (int32_t k = 0; k <= nbins; ++k) thr[k] = scale * pow(10.0, log_lo + (double)k * step);
+    return 0;
+}
+
+int oracle_mpd(const int32_t* counts, int64_t n_pix, const double* thr, int32_t nbins, int64_t* bins) {
+    if (n_pix < 0 || nbins < 1 || !thr || !bins || (n_pix > 0 && !counts)) return -1;
+    for (int32_t b = 0; b < nbins + 2; ++b) bins[b] = 0;
+    for (int64_t k = 0; k < n_pix; ++k) {
+        const double c = (double)counts[k];
+        /* the number of thresholds at or below c picks the bin */
+        int32_t b = 0;
+        while (b <= nbins && thr[b] <= c) ++b;
+        bins[b] += 1;
+    }
+    return 0;
+}
+
+int oracle_probability_sums(const int32_t* counts, int64_t n_pix, double n_avg, double mu_lim,
+                            int64_t* below, int64_t* above) {
+    if (n_pix < 0 || !(n_avg > 0.0) || !isfinite(n_avg) || isnan(mu_lim) || !below || !above) return -1;
+    if (n_pix > 0 && !counts) return -1;
+    int64_t lo = 0;
+    for (int64_t k = 0; k < n_pix; ++k)
+        if ((double)counts[k] / n_avg < mu_lim) lo += 1;
+    *below = lo;
+    *above = n_pix - lo;
+    return 0;
+}

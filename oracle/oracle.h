@@ -59,6 +59,29 @@ int oracle_normalise(const int32_t* counts, int64_t n_pix, double n_avg, float* 
 int oracle_stats(const int32_t* counts, int64_t n_pix, double n_avg, double kappa, double gamma,
                  double* out);
 
+/* Magnification probability distribution (Section 3.2.1, mpd.dat: the
+ * frequency of each value in the map divided by the number of pixels).
+ * hist[v] counts the pixels holding v for v < n_values - 1; pixels holding
+ * n_values - 1 or more are counted in hist[n_values - 1]. hist is overwritten. */
+int oracle_count_histogram(const int32_t* counts, int64_t n_pix, int64_t n_values, int64_t* hist);
+
+/* Bin edges of a histogram in log10(mu / mu_ref) over [log_lo, log_hi) with
+ * nbins equal bins (Section 4: MPDs binned into 100-400 bins, magnification
+ * measured against mu_th), expressed as count thresholds:
+ * thr[k] = (n_avg * mu_ref) * 10^(log_lo + k (log_hi - log_lo) / nbins), k = 0..nbins. */
+int oracle_mpd_thresholds(double n_avg, double mu_ref, double log_lo, double log_hi, int32_t nbins,
+                          double* thr);
+
+/* Binned MPD: bins[0] counts pixels below thr[0] (zero counts included),
+ * bins[1 + k] those with thr[k] <= N < thr[k + 1], bins[nbins + 1] those at
+ * or above thr[nbins]. bins (nbins + 2 entries) is overwritten. */
+int oracle_mpd(const int32_t* counts, int64_t n_pix, const double* thr, int32_t nbins, int64_t* bins);
+
+/* Probability sums (Section 4: P(mu < mu_lim) and P(mu > mu_lim), which add
+ * to one): *below counts pixels with N / N_avg < mu_lim, *above the rest. */
+int oracle_probability_sums(const int32_t* counts, int64_t n_pix, double n_avg, double mu_lim,
+                            int64_t* below, int64_t* above);
+
 int oracle_max_threads(void);
 
 #ifdef __cplusplus

@@ -32,6 +32,12 @@ MUTANTS = {
                           "if (!(u1 >= 0.0 && u1 <= (double)p1)) return -1;"),
     "n-avg-factor": ("const double ray_density = ((double)n1 * (double)n2) / (4.0 * h1 * h2);",
                      "const double ray_density = ((double)n1 * (double)n2) / (2.0 * h1 * h2);"),
+    "mpd-scale-without-mu-ref": ("const double scale = n_avg * mu_ref;", "const double scale = n_avg;"),
+    "mpd-edge-closed": ("while (b <= nbins && thr[b] <= c) ++b;", "while (b <= nbins && thr[b] < c) ++b;"),
+    "probability-sum-closed": ("if ((double)counts[k] / n_avg < mu_lim) lo += 1;",
+                               "if ((double)counts[k] / n_avg <= mu_lim) lo += 1;"),
+    "histogram-overflow-dropped": ("hist[c < n_values - 1 ? c : n_values - 1] += 1;",
+                                   "if (c < n_values - 1) hist[c] += 1;"),
     "row-offset": ("const double x2 = base2 + ((double)j + 0.5) * d2;\n        for (int64_t i = 0; i < n1; ++i) {\n            const double x1 = base1 + ((double)i + 0.5) * d1;\n            double y1, y2;",
                    "const double x2 = base2 + ((double)(j - row_begin) + 0.5) * d2;\n        for (int64_t i = 0; i < n1; ++i) {\n            const double x1 = base1 + ((double)i + 0.5) * d1;\n            double y1, y2;"),
 }
@@ -54,6 +60,7 @@ def test_planted_mistake_is_caught(name, tmp_path):
                     "-o", str(lib), str(c_path), "-lm"], check=True)
     env = dict(os.environ, ORACLE_LIB=str(lib), OMP_NUM_THREADS=os.environ.get("OMP_NUM_THREADS", "4"))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_mpd.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutant {name} passed every pin:\n{r.stdout[-2000:]}"
