@@ -230,6 +230,50 @@ rl_status rl_get_tuning(rl_context* ctx, rl_precision precision, int32_t n_class
 rl_status rl_set_tuning(rl_context* ctx, rl_precision precision, int32_t n_class,
                         const rl_tuning* h_tuning);
 
+/* ------------------------------------------------------------------------
+ * Magnification probability distributions (MPDs)
+ * ------------------------------------------------------------------------ */
+
+/* The full MPD of a count map before division by the pixel count (Section
+ * 3.2.1, mpd.dat: the frequency of each magnification value, i.e. of each
+ * count N = mu N_avg): d_hist[v] += number of pixels holding v, for
+ * v < n_values - 1; pixels holding n_values - 1 or more are added to
+ * d_hist[n_values - 1]. Counts must be >= 0 (as rl_shoot produces them).
+ * d_hist is int64[n_values], caller-zeroed, accumulated. 1 <= n_values <= 2^31.
+ * Asynchronous. */
+rl_status rl_count_histogram(rl_context* ctx, const int32_t* d_counts, const rl_window* win,
+                             int64_t n_values, int64_t* d_hist, hipStream_t stream);
+
+/* Binned MPD in log10(mu / mu_ref) (Section 4: the MPD tools bin the
+ * distribution into 100 to 400 bins and measure magnification against the
+ * macro-magnification mu_th = 1 / ((1 - kappa)^2 - gamma^2)). The nbins equal
+ * bins of [log_lo, log_hi) are turned into count thresholds in FP64,
+ * T_k = (n_avg mu_ref) 10^(log_lo + k (log_hi - log_lo) / nbins), k = 0..nbins,
+ * and a pixel with count N goes to bin b = #{k : T_k <= N}: d_bins[0] is the
+ * underflow (zero counts included), d_bins[1 + k] holds T_k <= N < T_(k+1),
+ * d_bins[nbins + 1] the overflow. d_bins is int64[nbins + 2], caller-zeroed,
+ * accumulated; probabilities are d_bins / (p1 p2). n_avg, mu_ref finite > 0;
+ * log_lo < log_hi finite; 1 <= nbins <= 4096. Asynchronous. */
+rl_status rl_mpd(rl_context* ctx, const int32_t* d_counts, const rl_window* win, double n_avg,
+                 double mu_ref, double log_lo, double log_hi, int32_t nbins, int64_t* d_bins,
+                 hipStream_t stream);
+
+/* Probability sums for mu < mu_lim and mu > mu_lim (Section 4, MPDs tool;
+ * the two add up to one): *h_below = number of pixels with N / N_avg < mu_lim
+ * (one FP64 division per pixel), *h_above = p1 p2 - *h_below. mu_lim not NaN.
+ * Synchronises the stream. */
+rl_status rl_probability_sums(rl_context* ctx, const int32_t* d_counts, const rl_window* win,
+                              double n_avg, double mu_lim, int64_t* h_below, int64_t* h_above,
+                              hipStream_t stream);
+
+/* Mean MPD and its spread over realisations (Section 4, meanMPD tool: the MPDs
+ * of maps with the same kappa, gamma, s but different lens positions): for
+ * each of n_bins bins, d_mean[b] = mean over the n_maps rows of d_bins (int64,
+ * row-major n_maps x n_bins) of d_bins[r][b] / n_pix, and d_std[b] the sample
+ * standard deviation (0 for one map). Asynchronous. */
+rl_status rl_mpd_moments(rl_context* ctx, const int64_t* d_bins, int32_t n_maps, int32_t n_bins,
+                         int64_t n_pix, double* d_mean, double* d_std, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

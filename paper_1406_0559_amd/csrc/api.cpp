@@ -225,6 +225,7 @@ struct rl_context {
     Scratch lens;        // FP32 lens copies
     Scratch batch;       // map records + work items + counter
     Scratch stats;       // reduction outputs
+    Scratch aux;         // MPD thresholds
     void* host_stage = nullptr;  // pinned staging for batch records
     size_t host_cap = 0;
     hipEvent_t stage_done = nullptr;
@@ -268,6 +269,42 @@ rl_status prepare_lenses_f32(rl_context* ctx, const rl_lenses* L, bool force_mas
     return RL_OK;
 }
 
+// Pinned host staging shared by the calls of one context: a caller writes the
+// returned buffer, then stage_send copies it to device memory in stream order.
+// The previous copy out of the buffer is waited for before it is reused.
+rl_status stage_reserve(rl_context* ctx, size_t bytes, char** host) {
+    hipError_t e;
+    if (ctx->stage_used) {
+        e = hipEventSynchronize(ctx->stage_done);
+        if (e != hipSuccess) return hip_fail(e, "staging wait");
+    }
+    if (ctx->host_cap < bytes) {
+        if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
+        ctx->host_stage = nullptr;
+        ctx->host_cap = 0;
+        e = hipHostMalloc(&ctx->host_stage, bytes, hipHostMallocDefault);
+        if (e != hipSuccess) { ctx->host_stage = nullptr; return hip_fail(e, "pinned staging"); }
+        ctx->host_cap = bytes;
+    }
+    *host = static_cast<char*>(ctx->host_stage);
+    return RL_OK;
+}
+
+rl_status stage_send(rl_context* ctx, void* dst, size_t bytes, hipStream_t s) {
+    hipError_t e = hipMemcpyAsync(dst, ctx->host_stage, bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "staging copy");
+    e = hipEventRecord(ctx->stage_done, s);
+    if (e != hipSuccess) return hip_fail(e, "staging event");
+    ctx->stage_used = true;
+    return RL_OK;
+}
+
+rl_status check_counts(const int32_t* d_counts, const rl_window* win) {
+    RL_TRY(check_window(win));
+    if (!d_counts) return fail(RL_E_INVALID, "counts pointer is NULL");
+    return RL_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -299,6 +336,7 @@ rl_status rl_destroy(rl_context* ctx) {
         ctx->lens.destroy();
         ctx->batch.destroy();
         ctx->stats.destroy();
+        ctx->aux.destroy();
         if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
         if (ctx->stage_done) (void)hipEventDestroy(ctx->stage_done);
     }
@@ -599,30 +637,15 @@ rl_status rl_shoot_batch(rl_context* ctx, const rl_map_desc* h_maps, int32_t n_m
     const size_t ibytes = sizeof(rl::WorkItem) * sorted.size();
     const size_t coff = (ioff + ibytes + 255) & ~(size_t)255;
     const size_t total = coff + 256;
-    if (ctx->stage_used) {
-        e = hipEventSynchronize(ctx->stage_done);
-        if (e != hipSuccess) return hip_fail(e, "staging wait");
-    }
-    if (ctx->host_cap < total) {
-        if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
-        ctx->host_stage = nullptr;
-        ctx->host_cap = 0;
-        e = hipHostMalloc(&ctx->host_stage, total, hipHostMallocDefault);
-        if (e != hipSuccess) { ctx->host_stage = nullptr; return hip_fail(e, "pinned staging"); }
-        ctx->host_cap = total;
-    }
-    char* hs = static_cast<char*>(ctx->host_stage);
+    char* hs = nullptr;
+    RL_TRY(stage_reserve(ctx, total, &hs));
     std::memset(hs, 0, total);
     std::memcpy(hs, params.data(), pbytes);
     std::memcpy(hs + ioff, sorted.data(), ibytes);
     e = ctx->batch.acquire(total, stream);
     if (e != hipSuccess) return hip_fail(e, "batch scratch");
     char* ds = static_cast<char*>(ctx->batch.ptr);
-    e = hipMemcpyAsync(ds, hs, total, hipMemcpyHostToDevice, stream);
-    if (e != hipSuccess) return hip_fail(e, "batch records copy");
-    e = hipEventRecord(ctx->stage_done, stream);
-    if (e != hipSuccess) return hip_fail(e, "staging event");
-    ctx->stage_used = true;
+    RL_TRY(stage_send(ctx, ds, total, stream));
 
     e = rl::launch_shoot_batch(reinterpret_cast<const rl::MapParams*>(ds),
                                reinterpret_cast<const rl::WorkItem*>(ds + ioff),
@@ -633,6 +656,101 @@ rl_status rl_shoot_batch(rl_context* ctx, const rl_map_desc* h_maps, int32_t n_m
     if (e == hipSuccess) e = e2;
     if (e == hipSuccess) e = e3;
     if (e != hipSuccess) return hip_fail(e, "batch launch");
+    return RL_OK;
+}
+
+rl_status rl_count_histogram(rl_context* ctx, const int32_t* d_counts, const rl_window* win,
+                             int64_t n_values, int64_t* d_hist, hipStream_t stream) {
+    g_error.clear();
+    if (!ctx) return fail(RL_E_INVALID, "context is NULL");
+    RL_TRY(check_counts(d_counts, win));
+    if (n_values < 1 || n_values > ((int64_t)1 << 31)) return fail(RL_E_INVALID, "n_values must be in [1, 2^31]");
+    if (!d_hist) return fail(RL_E_INVALID, "histogram pointer is NULL");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return hip_fail(dg.err, "hipSetDevice");
+    RL_TRY(ensure_ready(ctx));
+    hipError_t e = rl::launch_count_hist(d_counts, (int64_t)win->p1 * win->p2, n_values,
+                                         reinterpret_cast<unsigned long long*>(d_hist), stream);
+    if (e != hipSuccess) return hip_fail(e, "count histogram launch");
+    return RL_OK;
+}
+
+rl_status rl_mpd(rl_context* ctx, const int32_t* d_counts, const rl_window* win, double n_avg,
+                 double mu_ref, double log_lo, double log_hi, int32_t nbins, int64_t* d_bins,
+                 hipStream_t stream) {
+    g_error.clear();
+    if (!ctx) return fail(RL_E_INVALID, "context is NULL");
+    RL_TRY(check_counts(d_counts, win));
+    if (!is_finite(n_avg) || !(n_avg > 0.0)) return fail(RL_E_INVALID, "n_avg must be finite and > 0");
+    if (!is_finite(mu_ref) || !(mu_ref > 0.0)) return fail(RL_E_INVALID, "mu_ref must be finite and > 0");
+    if (!is_finite(log_lo) || !is_finite(log_hi) || !(log_hi > log_lo))
+        return fail(RL_E_INVALID, "need finite log_lo < log_hi");
+    if (nbins < 1 || nbins > rl::kMaxMpdBins) return fail(RL_E_INVALID, "nbins must be in [1, %d]", rl::kMaxMpdBins);
+    if (!d_bins) return fail(RL_E_INVALID, "bins pointer is NULL");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return hip_fail(dg.err, "hipSetDevice");
+    RL_TRY(ensure_ready(ctx));
+    // count thresholds of the log10(mu / mu_ref) bin edges, in FP64 on the host
+    const int nthr = nbins + 1;
+    const size_t bytes = (size_t)nthr * sizeof(double);
+    char* hs = nullptr;
+    RL_TRY(stage_reserve(ctx, bytes, &hs));
+    double* thr = reinterpret_cast<double*>(hs);
+    const double step = (log_hi - log_lo) / (double)nbins;
+    const double scale = n_avg * mu_ref;
+    for (int k = 0; k < nthr; ++k) thr[k] = scale * std::pow(10.0, log_lo + (double)k * step);
+    hipError_t e = ctx->aux.acquire(bytes, stream);
+    if (e != hipSuccess) return hip_fail(e, "threshold scratch");
+    RL_TRY(stage_send(ctx, ctx->aux.ptr, bytes, stream));
+    e = rl::launch_mpd(d_counts, (int64_t)win->p1 * win->p2, static_cast<const double*>(ctx->aux.ptr),
+                       nthr, reinterpret_cast<unsigned long long*>(d_bins), stream);
+    hipError_t e2 = ctx->aux.release(stream);
+    if (e == hipSuccess) e = e2;
+    if (e != hipSuccess) return hip_fail(e, "mpd launch");
+    return RL_OK;
+}
+
+rl_status rl_probability_sums(rl_context* ctx, const int32_t* d_counts, const rl_window* win,
+                              double n_avg, double mu_lim, int64_t* h_below, int64_t* h_above,
+                              hipStream_t stream) {
+    g_error.clear();
+    if (!ctx) return fail(RL_E_INVALID, "context is NULL");
+    RL_TRY(check_counts(d_counts, win));
+    if (!is_finite(n_avg) || !(n_avg > 0.0)) return fail(RL_E_INVALID, "n_avg must be finite and > 0");
+    if (std::isnan(mu_lim)) return fail(RL_E_INVALID, "mu_lim is NaN");
+    if (!h_below || !h_above) return fail(RL_E_INVALID, "output pointers are NULL");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return hip_fail(dg.err, "hipSetDevice");
+    RL_TRY(ensure_ready(ctx));
+    hipError_t e = ctx->stats.acquire(4 * sizeof(unsigned long long), stream);
+    if (e != hipSuccess) return hip_fail(e, "stats scratch");
+    unsigned long long* acc = static_cast<unsigned long long*>(ctx->stats.ptr);
+    const int64_t n = (int64_t)win->p1 * win->p2;
+    e = rl::launch_fill_u32(reinterpret_cast<unsigned int*>(acc), 2, 0u, stream);
+    if (e == hipSuccess) e = rl::launch_prob_sum(d_counts, n, n_avg, mu_lim, acc, stream);
+    unsigned long long below = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&below, acc, sizeof(below), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    hipError_t e2 = ctx->stats.release(stream);
+    if (e == hipSuccess) e = e2;
+    if (e != hipSuccess) return hip_fail(e, "probability sums");
+    *h_below = (int64_t)below;
+    *h_above = n - (int64_t)below;
+    return RL_OK;
+}
+
+rl_status rl_mpd_moments(rl_context* ctx, const int64_t* d_bins, int32_t n_maps, int32_t n_bins,
+                         int64_t n_pix, double* d_mean, double* d_std, hipStream_t stream) {
+    g_error.clear();
+    if (!ctx) return fail(RL_E_INVALID, "context is NULL");
+    if (!d_bins || !d_mean || !d_std) return fail(RL_E_INVALID, "pointers are NULL");
+    if (n_maps < 1 || n_bins < 1 || n_pix < 1) return fail(RL_E_INVALID, "n_maps, n_bins, n_pix must be >= 1");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return hip_fail(dg.err, "hipSetDevice");
+    RL_TRY(ensure_ready(ctx));
+    hipError_t e = rl::launch_mpd_moments(reinterpret_cast<const unsigned long long*>(d_bins), n_maps,
+                                          n_bins, (double)n_pix, d_mean, d_std, stream);
+    if (e != hipSuccess) return hip_fail(e, "mpd moments launch");
     return RL_OK;
 }
 

@@ -66,7 +66,7 @@ struct KernelShape {
     int32_t rays_x, rays_y;    // rays per lane along x1 / x2 (product 16)
     int32_t lens_tile;         // lenses per LDS pass (multiple of kBlock)
     int32_t waves;             // waves per workgroup
-    int32_t submap;            // 1 = LDS-privatised binning
+    int32_t submap;            // 0 global atomics, 1 bounding-box LDS sub-map, 2 64x64 LDS window
     int32_t item_cells;        // cells per batch work item
 };
 
@@ -88,6 +88,16 @@ hipError_t launch_normalise(const int32_t* counts, int64_t n, double n_avg, floa
 hipError_t launch_count_stats(const int32_t* counts, int64_t n, unsigned long long* out,
                               hipStream_t stream);
 hipError_t launch_fill_u32(unsigned int* p, int64_t n, unsigned int v, hipStream_t stream);
+hipError_t launch_count_hist(const int32_t* counts, int64_t n, int64_t n_values,
+                             unsigned long long* hist, hipStream_t stream);
+hipError_t launch_mpd(const int32_t* counts, int64_t n, const double* thr, int nthr,
+                      unsigned long long* bins, hipStream_t stream);
+hipError_t launch_prob_sum(const int32_t* counts, int64_t n, double n_avg, double mu_lim,
+                           unsigned long long* out, hipStream_t stream);
+hipError_t launch_mpd_moments(const unsigned long long* bins, int n_maps, int n_bins, double n_pix,
+                              double* mean, double* stdev, hipStream_t stream);
+
+constexpr int kMaxMpdBins = 4096;
 
 bool shape_supported(Precision prec, const KernelShape& ks);
 size_t shoot_lds_bytes(Precision prec, bool masses, const KernelShape& ks);

@@ -541,6 +541,101 @@ __global__ void fill_u32_kernel(unsigned int* p, int64_t n, unsigned int v) {
         p[k] = v;
 }
 
+// ----------------------------------------------------------------------------
+// magnification probability distributions (Section 3.2.1 and Section 4)
+// ----------------------------------------------------------------------------
+
+constexpr int kHistLds = 8192;   // count values histogrammed in LDS per workgroup
+
+// Frequency of each count value; values >= n_values - 1 share the last entry.
+// Low values (where almost every pixel lies) go to an LDS copy first.
+__global__ void __launch_bounds__(256) count_hist_kernel(const int32_t* __restrict__ counts,
+                                                         int64_t n, int64_t n_values,
+                                                         unsigned long long* __restrict__ hist) {
+    __shared__ unsigned int sh[kHistLds];
+    const int nl = (int)(n_values < kHistLds ? n_values : kHistLds);
+    for (int e = threadIdx.x; e < nl; e += blockDim.x) sh[e] = 0;
+    __syncthreads();
+    const int64_t last = n_values - 1;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        int64_t c = counts[k];
+        c = c < 0 ? 0 : c;
+        const int64_t v = c < last ? c : last;
+        if (v < nl) atomicAdd(&sh[v], 1u);
+        else atomicAdd(&hist[v], 1ull);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nl; e += blockDim.x)
+        if (sh[e]) atomicAdd(&hist[e], (unsigned long long)sh[e]);
+}
+
+// Binned MPD: bin = number of count thresholds <= N (thresholds ascending), so
+// bin 0 is the underflow and bin nthr the overflow. Thresholds and bins in LDS.
+__global__ void __launch_bounds__(256) mpd_kernel(const int32_t* __restrict__ counts, int64_t n,
+                                                  const double* __restrict__ thr, int nthr,
+                                                  unsigned long long* __restrict__ bins) {
+    extern __shared__ __align__(16) char smem[];
+    double* st = reinterpret_cast<double*>(smem);
+    unsigned int* sb = reinterpret_cast<unsigned int*>(st + nthr);
+    for (int e = threadIdx.x; e < nthr; e += blockDim.x) st[e] = thr[e];
+    for (int e = threadIdx.x; e <= nthr; e += blockDim.x) sb[e] = 0;
+    __syncthreads();
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const double c = (double)counts[k];
+        int lo = 0, hi = nthr;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (st[mid] <= c) lo = mid + 1;
+            else hi = mid;
+        }
+        atomicAdd(&sb[lo], 1u);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e <= nthr; e += blockDim.x)
+        if (sb[e]) atomicAdd(&bins[e], (unsigned long long)sb[e]);
+}
+
+// Pixels with N / N_avg < mu_lim (one FP64 division each, as the definition).
+__global__ void __launch_bounds__(256) prob_sum_kernel(const int32_t* __restrict__ counts, int64_t n,
+                                                       double n_avg, double mu_lim,
+                                                       unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long part[4];
+    unsigned long long below = 0;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x)
+        below += ((double)counts[k] / n_avg < mu_lim) ? 1ull : 0ull;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) below += __shfl_xor(below, o);
+    if ((threadIdx.x % kLanes) == 0) part[threadIdx.x / kLanes] = below;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int i = 0; i < (int)(blockDim.x / kLanes); ++i) t += part[i];
+        atomicAdd(out, t);
+    }
+}
+
+// Mean and sample standard deviation over n_maps MPDs of one bin per thread,
+// in probabilities (bin count / n_pix).
+__global__ void mpd_moments_kernel(const unsigned long long* __restrict__ bins, int n_maps,
+                                   int n_bins, double n_pix, double* __restrict__ mean,
+                                   double* __restrict__ stdev) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n_bins) return;
+    double s = 0.0;
+    for (int r = 0; r < n_maps; ++r) s += (double)bins[(int64_t)r * n_bins + b] / n_pix;
+    const double m = s / (double)n_maps;
+    double v = 0.0;
+    for (int r = 0; r < n_maps; ++r) {
+        const double d = (double)bins[(int64_t)r * n_bins + b] / n_pix - m;
+        v += d * d;
+    }
+    mean[b] = m;
+    stdev[b] = n_maps > 1 ? sqrt(v / (double)(n_maps - 1)) : 0.0;
+}
+
 int grid_for(int64_t n, int threads, int cap) {
     int64_t g = (n + threads - 1) / threads;
     if (g < 1) g = 1;
@@ -706,6 +801,39 @@ hipError_t launch_count_stats(const int32_t* counts, int64_t n, unsigned long lo
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(count_stats_kernel, dim3(grid_for(n, 256 * 8, 1024)), dim3(256), 0, s, counts, n,
                        out);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_hist(const int32_t* counts, int64_t n, int64_t n_values,
+                             unsigned long long* hist, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(count_hist_kernel, dim3(grid_for(n, 256 * 16, 2048)), dim3(256), 0, s, counts,
+                       n, n_values, hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_mpd(const int32_t* counts, int64_t n, const double* thr, int nthr,
+                      unsigned long long* bins, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const size_t lds = (size_t)nthr * sizeof(double) + (size_t)(nthr + 1) * sizeof(unsigned int);
+    hipLaunchKernelGGL(mpd_kernel, dim3(grid_for(n, 256 * 16, 2048)), dim3(256), lds, s, counts, n,
+                       thr, nthr, bins);
+    return hipGetLastError();
+}
+
+hipError_t launch_prob_sum(const int32_t* counts, int64_t n, double n_avg, double mu_lim,
+                           unsigned long long* out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(prob_sum_kernel, dim3(grid_for(n, 256 * 16, 2048)), dim3(256), 0, s, counts, n,
+                       n_avg, mu_lim, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_mpd_moments(const unsigned long long* bins, int n_maps, int n_bins, double n_pix,
+                              double* mean, double* stdev, hipStream_t s) {
+    if (n_bins <= 0) return hipSuccess;
+    hipLaunchKernelGGL(mpd_moments_kernel, dim3((n_bins + 255) / 256), dim3(256), 0, s, bins, n_maps,
+                       n_bins, n_pix, mean, stdev);
     return hipGetLastError();
 }
 

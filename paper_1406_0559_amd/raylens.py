@@ -95,6 +95,10 @@ def load():
         "rl_ray_positions": [vp, P(rl_lenses), P(rl_macro), P(rl_raygrid), C.c_int, i64, i64, vp,
                              vp, vp],
         "rl_shoot_batch": [vp, P(rl_map_desc), i32, C.c_int, vp],
+        "rl_count_histogram": [vp, vp, P(rl_window), i64, vp, vp],
+        "rl_mpd": [vp, vp, P(rl_window), dbl, dbl, dbl, dbl, i32, vp, vp],
+        "rl_probability_sums": [vp, vp, P(rl_window), dbl, dbl, P(i64), P(i64), vp],
+        "rl_mpd_moments": [vp, vp, i32, i32, i64, vp, vp, vp],
         "rl_get_tuning": [vp, C.c_int, i32, P(rl_tuning)],
         "rl_set_tuning": [vp, C.c_int, i32, P(rl_tuning)],
     }
@@ -175,6 +179,27 @@ def rl_ray_positions(ctx, lenses, macro, grid, precision, row_begin, row_end, d_
 def rl_shoot_batch(ctx, descs: Sequence[rl_map_desc], precision, stream=None):
     arr = (rl_map_desc * len(descs))(*descs)
     _check(load().rl_shoot_batch(ctx, arr, len(descs), precision, stream))
+
+
+def rl_count_histogram(ctx, d_counts, win, n_values, d_hist, stream=None):
+    _check(load().rl_count_histogram(ctx, d_counts, C.byref(win), n_values, d_hist, stream))
+
+
+def rl_mpd(ctx, d_counts, win, n_avg, mu_ref, log_lo, log_hi, nbins, d_bins, stream=None):
+    _check(load().rl_mpd(ctx, d_counts, C.byref(win), n_avg, mu_ref, log_lo, log_hi, nbins, d_bins,
+                         stream))
+
+
+def rl_probability_sums(ctx, d_counts, win, n_avg, mu_lim, stream=None):
+    below = C.c_int64()
+    above = C.c_int64()
+    _check(load().rl_probability_sums(ctx, d_counts, C.byref(win), n_avg, mu_lim, C.byref(below),
+                                      C.byref(above), stream))
+    return below.value, above.value
+
+
+def rl_mpd_moments(ctx, d_bins, n_maps, n_bins, n_pix, d_mean, d_std, stream=None):
+    _check(load().rl_mpd_moments(ctx, d_bins, n_maps, n_bins, n_pix, d_mean, d_std, stream))
 
 
 def rl_get_tuning(ctx, precision, n_class) -> rl_tuning:
@@ -332,6 +357,47 @@ class Context:
                                      rb, re, counts.data_ptr(), escaped.data_ptr()))
         rl_shoot_batch(self.handle, descs, PRECISIONS[precision], _stream_ptr(stream))
 
+    # ---- magnification probability distributions ----------------------------
+    def count_histogram(self, counts, spec, n_values, hist=None, stream=None):
+        torch = _torch()
+        _check_counts(counts, spec)
+        if hist is None:
+            hist = torch.zeros(int(n_values), dtype=torch.int64, device=counts.device)
+        rl_count_histogram(self.handle, counts.data_ptr(), window_of(spec), int(n_values),
+                           hist.data_ptr(), _stream_ptr(stream))
+        return hist
+
+    def mpd(self, counts, spec, mu_ref, log_lo, log_hi, nbins, n_avg=None, bins=None, stream=None):
+        """[underflow, nbins bins of log10(mu / mu_ref) over [log_lo, log_hi), overflow]."""
+        torch = _torch()
+        _check_counts(counts, spec)
+        if n_avg is None:
+            n_avg = rl_n_avg(grid_of(spec), window_of(spec))
+        if bins is None:
+            bins = torch.zeros(int(nbins) + 2, dtype=torch.int64, device=counts.device)
+        rl_mpd(self.handle, counts.data_ptr(), window_of(spec), n_avg, mu_ref, log_lo, log_hi,
+               int(nbins), bins.data_ptr(), _stream_ptr(stream))
+        return bins
+
+    def probability_sums(self, counts, spec, mu_lim, n_avg=None, stream=None):
+        _check_counts(counts, spec)
+        if n_avg is None:
+            n_avg = rl_n_avg(grid_of(spec), window_of(spec))
+        return rl_probability_sums(self.handle, counts.data_ptr(), window_of(spec), n_avg, mu_lim,
+                                   _stream_ptr(stream))
+
+    def mpd_moments(self, bins, n_pix, stream=None):
+        """bins: int64 tensor (n_maps, n_bins). Returns (mean, std) float64 tensors."""
+        torch = _torch()
+        bins = bins.contiguous()
+        if bins.dtype != torch.int64 or bins.dim() != 2:
+            raise ValueError("bins must be a 2-D int64 tensor")
+        mean = torch.empty(bins.shape[1], dtype=torch.float64, device=bins.device)
+        std = torch.empty_like(mean)
+        rl_mpd_moments(self.handle, bins.data_ptr(), bins.shape[0], bins.shape[1], int(n_pix),
+                       mean.data_ptr(), std.data_ptr(), _stream_ptr(stream))
+        return mean, std
+
     def get_tuning(self, precision, n_class):
         t = rl_get_tuning(self.handle, PRECISIONS[precision], n_class)
         return {f: getattr(t, f) for f, _ in rl_tuning._fields_}
@@ -350,6 +416,14 @@ def _check_map_tensors(counts, escaped, spec):
         raise ValueError("escaped must be an int64 tensor")
     if not counts.is_cuda or not escaped.is_cuda:
         raise ValueError("counts and escaped must be device tensors")
+
+
+def _check_counts(counts, spec):
+    torch = _torch()
+    if counts.dtype != torch.int32 or counts.numel() != spec.p1 * spec.p2 or not counts.is_contiguous():
+        raise ValueError("counts must be a contiguous int32 tensor of p2 x p1 elements")
+    if not counts.is_cuda:
+        raise ValueError("counts must be a device tensor")
 
 
 def n_class(n: int) -> int:

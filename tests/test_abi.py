@@ -162,3 +162,28 @@ def test_one_hip_runtime_per_process():
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr[-2000:]
     assert out.stdout.split()[0] == "1", out.stdout
+
+
+def test_mpd_entry_points_validate_on_the_host():
+    lib = rl.load()
+    ctx = rl.rl_create(0)
+    try:
+        w = rl.rl_window(16, 16, 0.0, 0.0, 2.0, 2.0)
+        fake = C.c_void_p(0x1000)
+        lo = C.c_int64()
+        hi = C.c_int64()
+        assert lib.rl_count_histogram(ctx, fake, C.byref(w), 0, fake, None) == rl.RL_E_INVALID
+        assert lib.rl_count_histogram(ctx, None, C.byref(w), 10, fake, None) == rl.RL_E_INVALID
+        bad = [(0.0, 1.0, -1.0, 1.0, 10), (1.0, 0.0, -1.0, 1.0, 10), (1.0, 1.0, 1.0, -1.0, 10),
+               (1.0, 1.0, -1.0, 1.0, 0), (1.0, 1.0, -1.0, 1.0, 5000), (math.nan, 1.0, -1.0, 1.0, 10),
+               (1.0, 1.0, -math.inf, 1.0, 10)]
+        for n_avg, mu_ref, a, b, nb in bad:
+            assert lib.rl_mpd(ctx, fake, C.byref(w), n_avg, mu_ref, a, b, nb, fake, None) == rl.RL_E_INVALID
+        assert lib.rl_probability_sums(ctx, fake, C.byref(w), 1.0, math.nan, C.byref(lo), C.byref(hi),
+                                       None) == rl.RL_E_INVALID
+        assert lib.rl_probability_sums(ctx, fake, C.byref(w), -1.0, 1.0, C.byref(lo), C.byref(hi),
+                                       None) == rl.RL_E_INVALID
+        assert lib.rl_mpd_moments(ctx, fake, 0, 10, 100, fake, fake, None) == rl.RL_E_INVALID
+        assert lib.rl_mpd_moments(ctx, fake, 3, 10, 0, fake, fake, None) == rl.RL_E_INVALID
+    finally:
+        rl.rl_destroy(ctx)
