@@ -41,9 +41,12 @@ def lib():
         L.oracle_mpd_thresholds.argtypes = [dbl, dbl, dbl, dbl, i32, vp]
         L.oracle_mpd.argtypes = [vp, i64, vp, i32, vp]
         L.oracle_probability_sums.argtypes = [vp, i64, dbl, dbl, vp, vp]
+        L.oracle_codec_encode.argtypes = [vp, i64, vp, vp, vp, vp]
+        L.oracle_codec_decode.argtypes = [vp, i64, i32, vp, i64, vp]
         for f in ("oracle_ray_positions", "oracle_bin", "oracle_shoot", "oracle_normalise",
                   "oracle_stats", "oracle_max_threads", "oracle_count_histogram",
-                  "oracle_mpd_thresholds", "oracle_mpd", "oracle_probability_sums"):
+                  "oracle_mpd_thresholds", "oracle_mpd", "oracle_probability_sums",
+                  "oracle_codec_encode", "oracle_codec_decode"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -181,3 +184,29 @@ def probability_sums(counts, n_avg_value, mu_lim):
     if lib().oracle_probability_sums(_p(counts), counts.size, n_avg_value, mu_lim, _p(lo), _p(hi)) != 0:
         raise ValueError("oracle_probability_sums: invalid arguments")
     return int(lo[0]), int(hi[0])
+
+
+def codec_encode(counts):
+    """Indexed map of Appendix B: returns (values, bits, packed uint32 words)."""
+    counts = np.ascontiguousarray(counts, dtype=np.int32).ravel()
+    values = np.zeros(counts.size, np.int32)
+    nd = np.zeros(1, np.int64)
+    bits = np.zeros(1, np.int32)
+    packed = np.zeros(counts.size, np.uint32)
+    if lib().oracle_codec_encode(_p(counts), counts.size, _p(values), _p(nd), _p(bits), _p(packed)) != 0:
+        raise ValueError("oracle_codec_encode: invalid arguments")
+    b = int(bits[0])
+    words = (counts.size * b + 31) // 32
+    return values[: int(nd[0])].copy(), b, packed[:words].copy()
+
+
+def codec_decode(packed, n_pix, bits, values):
+    packed = np.ascontiguousarray(packed, dtype=np.uint32)
+    values = np.ascontiguousarray(values, dtype=np.int32)
+    counts = np.zeros(int(n_pix), np.int32)
+    if packed.size < (int(n_pix) * int(bits) + 31) // 32:
+        raise ValueError("packed stream too short")
+    if lib().oracle_codec_decode(_p(packed), int(n_pix), int(bits), _p(values), values.size,
+                                 _p(counts)) != 0:
+        raise ValueError("oracle_codec_decode: invalid arguments")
+    return counts

@@ -26,6 +26,8 @@
 
 #include <math.h>
 #include <stddef.h>
+#include <stdlib.h>
+#include <string.h>
 #include <omp.h>
 
 static int grid_ok(int64_t n1, int64_t n2, double h1, double h2) {
@@ -265,5 +267,68 @@ int oracle_probability_sums(const int32_t* counts, int64_t n_pix, double n_avg, 
         if ((double)counts[k] / n_avg < mu_lim) lo += 1;
     *below = lo;
     *above = n_pix - lo;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Indexed-map codec (Appendix B)
+ * ------------------------------------------------------------------------ */
+
+static int cmp_i32(const void* a, const void* b) {
+    const int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+    return (x > y) - (x < y);
+}
+
+/* position of v in the ascending table values[0..n) (v is present) */
+static int64_t index_of(const int32_t* values, int64_t n, int32_t v) {
+    int64_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) / 2;
+        if (values[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+int oracle_codec_encode(const int32_t* counts, int64_t n_pix, int32_t* values, int64_t* n_distinct,
+                        int32_t* bits, uint32_t* packed) {
+    if (n_pix < 1 || !counts || !values || !n_distinct || !bits || !packed) return -1;
+    for (int64_t k = 0; k < n_pix; ++k) if (counts[k] < 0) return -1;
+    /* distinct values: sort a copy, keep the first of each run */
+    memcpy(values, counts, (size_t)n_pix * sizeof(int32_t));
+    qsort(values, (size_t)n_pix, sizeof(int32_t), cmp_i32);
+    int64_t nd = 0;
+    for (int64_t k = 0; k < n_pix; ++k)
+        if (k == 0 || values[k] != values[nd - 1]) values[nd++] = values[k];
+    /* fewest bits b >= 1 with 2^b >= nd */
+    int32_t b = 1;
+    while (b < 32 && ((int64_t)1 << b) < nd) ++b;
+    for (int64_t w = 0; w < n_pix; ++w) packed[w] = 0;
+    for (int64_t p = 0; p < n_pix; ++p) {
+        const int64_t idx = index_of(values, nd, counts[p]);
+        for (int32_t t = 0; t < b; ++t) {
+            if ((idx >> t) & 1) {
+                const int64_t bit = p * (int64_t)b + t;
+                packed[bit / 32] |= (uint32_t)1u << (bit % 32);
+            }
+        }
+    }
+    *n_distinct = nd;
+    *bits = b;
+    return 0;
+}
+
+int oracle_codec_decode(const uint32_t* packed, int64_t n_pix, int32_t bits, const int32_t* values,
+                        int64_t n_distinct, int32_t* counts) {
+    if (n_pix < 1 || bits < 1 || bits > 32 || !packed || !values || n_distinct < 1 || !counts) return -1;
+    for (int64_t p = 0; p < n_pix; ++p) {
+        int64_t idx = 0;
+        for (int32_t t = 0; t < bits; ++t) {
+            const int64_t bit = p * (int64_t)bits + t;
+            if ((packed[bit / 32] >> (bit % 32)) & 1u) idx |= (int64_t)1 << t;
+        }
+        if (idx >= n_distinct) return -1;
+        counts[p] = values[idx];
+    }
     return 0;
 }

@@ -82,6 +82,21 @@ int oracle_mpd(const int32_t* counts, int64_t n_pix, const double* thr, int32_t 
 int oracle_probability_sums(const int32_t* counts, int64_t n_pix, double n_avg, double mu_lim,
                             int64_t* below, int64_t* above);
 
+/* Indexed maps (Appendix B): the distinct count values of a map, ascending,
+ * form the index file values[0 .. n_distinct); each pixel is replaced by the
+ * position of its value, written with the fewest bits that hold every index
+ * (bits = smallest b >= 1 with 2^b >= n_distinct). Pixel p's index occupies
+ * bits [p*bits, (p+1)*bits) of a stream of 32-bit words, least significant
+ * bit first. values must hold n_pix entries and packed n_pix words (always
+ * enough: bits <= 32); the words past ceil(n_pix * bits / 32) are left zero.
+ * Counts must be >= 0. */
+int oracle_codec_encode(const int32_t* counts, int64_t n_pix, int32_t* values, int64_t* n_distinct,
+                        int32_t* bits, uint32_t* packed);
+
+/* Inverse of oracle_codec_encode. */
+int oracle_codec_decode(const uint32_t* packed, int64_t n_pix, int32_t bits, const int32_t* values,
+                        int64_t n_distinct, int32_t* counts);
+
 int oracle_max_threads(void);
 
 #ifdef __cplusplus

@@ -38,6 +38,9 @@ MUTANTS = {
                                "if ((double)counts[k] / n_avg <= mu_lim) lo += 1;"),
     "histogram-overflow-dropped": ("hist[c < n_values - 1 ? c : n_values - 1] += 1;",
                                    "if (c < n_values - 1) hist[c] += 1;"),
+    "codec-bits-off-by-one": ("while (b < 32 && ((int64_t)1 << b) < nd) ++b;",
+                              "while (b < 32 && ((int64_t)1 << b) <= nd) ++b;"),
+    "codec-unsorted-index": ("qsort(values, (size_t)n_pix, sizeof(int32_t), cmp_i32);", ""),
     "row-offset": ("const double x2 = base2 + ((double)j + 0.5) * d2;\n        for (int64_t i = 0; i < n1; ++i) {\n            const double x1 = base1 + ((double)i + 0.5) * d1;\n            double y1, y2;",
                    "const double x2 = base2 + ((double)(j - row_begin) + 0.5) * d2;\n        for (int64_t i = 0; i < n1; ++i) {\n            const double x1 = base1 + ((double)i + 0.5) * d1;\n            double y1, y2;"),
 }
@@ -61,6 +64,7 @@ def test_planted_mistake_is_caught(name, tmp_path):
     env = dict(os.environ, ORACLE_LIB=str(lib), OMP_NUM_THREADS=os.environ.get("OMP_NUM_THREADS", "4"))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_mpd.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_mpd.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_codec.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutant {name} passed every pin:\n{r.stdout[-2000:]}"
