@@ -274,6 +274,31 @@ rl_status rl_probability_sums(rl_context* ctx, const int32_t* d_counts, const rl
 rl_status rl_mpd_moments(rl_context* ctx, const int64_t* d_bins, int32_t n_maps, int32_t n_bins,
                          int64_t n_pix, double* d_mean, double* d_std, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Indexed maps (Appendix B)
+ * ------------------------------------------------------------------------ */
+
+/* Converts a count map into an index file and an indexed map (Appendix B):
+ * d_values[0 .. n_distinct) receives the distinct counts in ascending order,
+ * and pixel p's position in that table is written with the fewest bits that
+ * hold every position (bits = smallest b >= 1 with 2^b >= n_distinct) into
+ * d_packed, at bits [p*bits, (p+1)*bits) of a stream of 32-bit words, least
+ * significant bit first (pixels in map order, x1 fastest). Needs
+ * values_capacity >= n_distinct and packed_capacity >= ceil(p1 p2 bits / 32)
+ * words; with d_values or d_packed NULL only *h_n_distinct and *h_bits are
+ * computed (a size query). Counts must be >= 0. Synchronises the stream. */
+rl_status rl_codec_encode(rl_context* ctx, const int32_t* d_counts, const rl_window* win,
+                          int32_t* d_values, int64_t values_capacity, uint32_t* d_packed,
+                          int64_t packed_capacity, int64_t* h_n_distinct, int32_t* h_bits,
+                          hipStream_t stream);
+
+/* Inverse of rl_codec_encode: d_counts[p] = d_values[index of p]. A position
+ * past the table (a stream the encoder did not write) decodes to -1.
+ * 1 <= bits <= 32, n_distinct >= 1. Asynchronous. */
+rl_status rl_codec_decode(rl_context* ctx, const uint32_t* d_packed, int32_t bits,
+                          const int32_t* d_values, int64_t n_distinct, const rl_window* win,
+                          int32_t* d_counts, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

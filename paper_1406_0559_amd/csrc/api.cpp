@@ -520,8 +520,8 @@ rl_status rl_stats_get(rl_context* ctx, const int32_t* d_counts, const int64_t* 
     if (e == hipSuccess)
         e = rl::launch_count_stats(d_counts, (int64_t)win->p1 * win->p2, acc, stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(acc + 2, d_escaped, sizeof(int64_t), hipMemcpyDeviceToDevice, stream);
-    unsigned long long host[3] = {0, 0, 0};
+        e = hipMemcpyAsync(acc + 3, d_escaped, sizeof(int64_t), hipMemcpyDeviceToDevice, stream);
+    unsigned long long host[4] = {0, 0, 0, 0};
     if (e == hipSuccess) e = hipMemcpyAsync(host, acc, sizeof(host), hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     hipError_t e2 = ctx->stats.release(stream);
@@ -532,7 +532,7 @@ rl_status rl_stats_get(rl_context* ctx, const int32_t* d_counts, const int64_t* 
     rl_stats st;
     st.shot = grid->n1 * grid->n2;
     st.binned = (int64_t)host[0];
-    st.escaped = (int64_t)host[2];
+    st.escaped = (int64_t)host[3];
     st.n_avg = n_avg;
     st.mean_count = (double)st.binned / ((double)win->p1 * (double)win->p2);
     st.mean_mu = st.mean_count / n_avg;
@@ -751,6 +751,98 @@ rl_status rl_mpd_moments(rl_context* ctx, const int64_t* d_bins, int32_t n_maps,
     hipError_t e = rl::launch_mpd_moments(reinterpret_cast<const unsigned long long*>(d_bins), n_maps,
                                           n_bins, (double)n_pix, d_mean, d_std, stream);
     if (e != hipSuccess) return hip_fail(e, "mpd moments launch");
+    return RL_OK;
+}
+
+rl_status rl_codec_encode(rl_context* ctx, const int32_t* d_counts, const rl_window* win,
+                          int32_t* d_values, int64_t values_capacity, uint32_t* d_packed,
+                          int64_t packed_capacity, int64_t* h_n_distinct, int32_t* h_bits,
+                          hipStream_t stream) {
+    g_error.clear();
+    if (!ctx) return fail(RL_E_INVALID, "context is NULL");
+    RL_TRY(check_counts(d_counts, win));
+    if (!h_n_distinct || !h_bits) return fail(RL_E_INVALID, "output pointers are NULL");
+    const bool size_only = !d_values || !d_packed;
+    if (!size_only && (values_capacity < 1 || packed_capacity < 1))
+        return fail(RL_E_INVALID, "capacities must be >= 1");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return hip_fail(dg.err, "hipSetDevice");
+    RL_TRY(ensure_ready(ctx));
+    const int64_t n_pix = (int64_t)win->p1 * win->p2;
+    // 1. largest count and negatives
+    hipError_t e = ctx->stats.acquire(4 * sizeof(unsigned long long), stream);
+    if (e != hipSuccess) return hip_fail(e, "stats scratch");
+    unsigned long long* acc = static_cast<unsigned long long*>(ctx->stats.ptr);
+    e = rl::launch_fill_u32(reinterpret_cast<unsigned int*>(acc), 8, 0u, stream);
+    if (e == hipSuccess) e = rl::launch_count_stats(d_counts, n_pix, acc, stream);
+    unsigned long long host[3] = {0, 0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(host, acc, sizeof(host), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    hipError_t e2 = ctx->stats.release(stream);
+    if (e == hipSuccess) e = e2;
+    if (e != hipSuccess) return hip_fail(e, "codec statistics");
+    if (host[2]) return fail(RL_E_INVALID, "counts must be >= 0 (%llu negative)", host[2]);
+    const int64_t n_values = (int64_t)host[1] + 1;
+    // 2. histogram of values, distinct flags and their ranks
+    const int64_t nb = rl::scan_blocks(n_values);
+    const size_t hist_b = (size_t)n_values * 8, flag_b = (size_t)n_values * 4;
+    const size_t off_flag = (hist_b + 255) & ~(size_t)255;
+    const size_t off_rank = (off_flag + flag_b + 255) & ~(size_t)255;
+    const size_t off_sums = (off_rank + flag_b + 255) & ~(size_t)255;
+    const size_t off_total = (off_sums + (size_t)nb * 4 + 255) & ~(size_t)255;
+    const size_t need = off_total + 256;
+    e = ctx->aux.acquire(need, stream);
+    if (e != hipSuccess) return hip_fail(e, "codec scratch");
+    char* base = static_cast<char*>(ctx->aux.ptr);
+    auto* hist = reinterpret_cast<unsigned long long*>(base);
+    auto* flag = reinterpret_cast<int32_t*>(base + off_flag);
+    auto* rank = reinterpret_cast<int32_t*>(base + off_rank);
+    auto* sums = reinterpret_cast<int32_t*>(base + off_sums);
+    auto* total = reinterpret_cast<int64_t*>(base + off_total);
+    e = rl::launch_fill_u32(reinterpret_cast<unsigned int*>(hist), n_values * 2, 0u, stream);
+    if (e == hipSuccess) e = rl::launch_count_hist(d_counts, n_pix, n_values, hist, stream);
+    if (e == hipSuccess) e = rl::launch_distinct_ranks(hist, n_values, flag, rank, sums, total, stream);
+    int64_t nd = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&nd, total, sizeof(nd), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) { (void)ctx->aux.release(stream); return hip_fail(e, "codec ranks"); }
+    int32_t bits = 1;
+    while (bits < 32 && ((int64_t)1 << bits) < nd) ++bits;
+    *h_n_distinct = nd;
+    *h_bits = bits;
+    const int64_t words = (n_pix * bits + 31) / 32;
+    if (size_only) {
+        e = ctx->aux.release(stream);
+        return e == hipSuccess ? RL_OK : hip_fail(e, "codec scratch");
+    }
+    if (values_capacity < nd || packed_capacity < words) {
+        (void)ctx->aux.release(stream);
+        return fail(RL_E_INVALID, "need %lld value slots and %lld packed words", (long long)nd,
+                    (long long)words);
+    }
+    // 3. index table and packed map
+    e = rl::launch_codec_pack(d_counts, n_pix, flag, rank, n_values, bits, d_values, d_packed, stream);
+    e2 = ctx->aux.release(stream);
+    if (e == hipSuccess) e = e2;
+    if (e != hipSuccess) return hip_fail(e, "codec pack");
+    return RL_OK;
+}
+
+rl_status rl_codec_decode(rl_context* ctx, const uint32_t* d_packed, int32_t bits,
+                          const int32_t* d_values, int64_t n_distinct, const rl_window* win,
+                          int32_t* d_counts, hipStream_t stream) {
+    g_error.clear();
+    if (!ctx) return fail(RL_E_INVALID, "context is NULL");
+    RL_TRY(check_window(win));
+    if (!d_packed || !d_values || !d_counts) return fail(RL_E_INVALID, "pointers are NULL");
+    if (bits < 1 || bits > 32) return fail(RL_E_INVALID, "bits must be in [1, 32]");
+    if (n_distinct < 1) return fail(RL_E_INVALID, "n_distinct must be >= 1");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return hip_fail(dg.err, "hipSetDevice");
+    RL_TRY(ensure_ready(ctx));
+    hipError_t e = rl::launch_codec_unpack(d_packed, (int64_t)win->p1 * win->p2, bits, d_values,
+                                           n_distinct, d_counts, stream);
+    if (e != hipSuccess) return hip_fail(e, "codec unpack");
     return RL_OK;
 }
 

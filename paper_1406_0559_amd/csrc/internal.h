@@ -84,7 +84,8 @@ hipError_t launch_bin_positions(const double* y1, const double* y2, int64_t n, i
                                 int32_t* counts, unsigned long long* escaped, hipStream_t stream);
 hipError_t launch_normalise(const int32_t* counts, int64_t n, double n_avg, float* mu,
                             hipStream_t stream);
-// out[0] = sum of counts (u64), out[1] = max count (as u64)
+// out[0] = sum of the non-negative counts, out[1] = max count, out[2] += number of
+// negative counts (all u64; out[0..2] caller-zeroed)
 hipError_t launch_count_stats(const int32_t* counts, int64_t n, unsigned long long* out,
                               hipStream_t stream);
 hipError_t launch_fill_u32(unsigned int* p, int64_t n, unsigned int v, hipStream_t stream);
@@ -98,6 +99,18 @@ hipError_t launch_mpd_moments(const unsigned long long* bins, int n_maps, int n_
                               double* mean, double* stdev, hipStream_t stream);
 
 constexpr int kMaxMpdBins = 4096;
+
+// Indexed-map codec: flag/rank the distinct values of a count histogram
+// (exclusive scan; *total = number of distinct values), then pack / unpack.
+int64_t scan_blocks(int64_t n);
+hipError_t launch_distinct_ranks(const unsigned long long* hist, int64_t n_values, int32_t* flag,
+                                 int32_t* rank, int32_t* block_sums, int64_t* total,
+                                 hipStream_t stream);
+hipError_t launch_codec_pack(const int32_t* counts, int64_t n_pix, const int32_t* flag,
+                             const int32_t* rank, int64_t n_values, int bits, int32_t* values,
+                             uint32_t* packed, hipStream_t stream);
+hipError_t launch_codec_unpack(const uint32_t* packed, int64_t n_pix, int bits, const int32_t* values,
+                               int64_t n_values, int32_t* counts, hipStream_t stream);
 
 bool shape_supported(Precision prec, const KernelShape& ks);
 size_t shoot_lds_bytes(Precision prec, bool masses, const KernelShape& ks);

@@ -505,33 +505,38 @@ __global__ void __launch_bounds__(256) count_stats_kernel(const int32_t* __restr
                                                           int64_t n,
                                                           unsigned long long* __restrict__ out) {
     __shared__ unsigned long long ssum[4];
+    __shared__ unsigned long long sneg[4];
     __shared__ int smax[4];
-    unsigned long long s = 0;
+    unsigned long long s = 0, neg = 0;
     int mx = 0;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
          k += (int64_t)gridDim.x * blockDim.x) {
         const int v = counts[k];
-        s += (unsigned long long)(unsigned)v;
+        if (v < 0) neg += 1;
+        else s += (unsigned long long)(unsigned)v;
         mx = v > mx ? v : mx;
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         s += __shfl_xor(s, o);
+        neg += __shfl_xor(neg, o);
         const int t = __shfl_xor(mx, o);
         mx = t > mx ? t : mx;
     }
     const int w = threadIdx.x / kLanes;
-    if ((threadIdx.x % kLanes) == 0) { ssum[w] = s; smax[w] = mx; }
+    if ((threadIdx.x % kLanes) == 0) { ssum[w] = s; sneg[w] = neg; smax[w] = mx; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long bs = 0;
+        unsigned long long bs = 0, bn = 0;
         int bm = 0;
         for (int i = 0; i < (int)(blockDim.x / kLanes); ++i) {
             bs += ssum[i];
+            bn += sneg[i];
             bm = smax[i] > bm ? smax[i] : bm;
         }
         atomicAdd(&out[0], bs);
         atomicMax(&out[1], (unsigned long long)bm);
+        if (bn) atomicAdd(&out[2], bn);
     }
 }
 
@@ -634,6 +639,138 @@ __global__ void mpd_moments_kernel(const unsigned long long* __restrict__ bins, 
     }
     mean[b] = m;
     stdev[b] = n_maps > 1 ? sqrt(v / (double)(n_maps - 1)) : 0.0;
+}
+
+// ----------------------------------------------------------------------------
+// indexed-map codec (Appendix B)
+// ----------------------------------------------------------------------------
+
+constexpr int kScanPerBlock = 1024;   // elements per scan block (256 threads x 4)
+
+// flag[v] = 1 where value v occurs in the map
+__global__ void distinct_flag_kernel(const unsigned long long* __restrict__ hist, int64_t n,
+                                     int32_t* __restrict__ flag) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        flag[v] = hist[v] ? 1 : 0;
+}
+
+// Exclusive scan of a block of 256 x 4 int32 in LDS; returns the block total.
+__device__ int block_exclusive_scan_1024(int32_t (&v)[4], int* sh) {
+    const int t = threadIdx.x;
+    int local = v[0] + v[1] + v[2] + v[3];
+    sh[t] = local;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {       // Hillis-Steele over the 256 thread sums
+        const int add = t >= o ? sh[t - o] : 0;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    const int total = sh[255];
+    int run = sh[t] - local;                   // exclusive prefix of this thread
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { const int x = v[i]; v[i] = run; run += x; }
+    return total;
+}
+
+__global__ void __launch_bounds__(256) scan_block_sums_kernel(const int32_t* __restrict__ in, int64_t n,
+                                                              int32_t* __restrict__ sums) {
+    __shared__ int sh[256];
+    const int64_t base = (int64_t)blockIdx.x * kScanPerBlock + threadIdx.x * 4;
+    int32_t v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = base + i < n ? in[base + i] : 0;
+    const int total = block_exclusive_scan_1024(v, sh);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// One workgroup: exclusive scan of the block sums in place; *grand = total.
+__global__ void __launch_bounds__(256) scan_sums_kernel(int32_t* __restrict__ sums, int64_t nb,
+                                                        int64_t* __restrict__ grand) {
+    __shared__ int sh[256];
+    int64_t carry = 0;
+    for (int64_t c0 = 0; c0 < nb; c0 += kScanPerBlock) {
+        int32_t v[4];
+        const int64_t base = c0 + threadIdx.x * 4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = base + i < nb ? sums[base + i] : 0;
+        const int total = block_exclusive_scan_1024(v, sh);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (base + i < nb) sums[base + i] = (int32_t)(carry + v[i]);
+        carry += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *grand = carry;
+}
+
+__global__ void __launch_bounds__(256) scan_apply_kernel(const int32_t* __restrict__ in, int64_t n,
+                                                         const int32_t* __restrict__ offsets,
+                                                         int32_t* __restrict__ out) {
+    __shared__ int sh[256];
+    const int64_t base = (int64_t)blockIdx.x * kScanPerBlock + threadIdx.x * 4;
+    int32_t v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = base + i < n ? in[base + i] : 0;
+    block_exclusive_scan_1024(v, sh);
+    const int32_t off = offsets[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (base + i < n) out[base + i] = off + v[i];
+}
+
+// values[rank[v]] = v for every value present (ranks ascend with v).
+__global__ void scatter_values_kernel(const int32_t* __restrict__ flag,
+                                      const int32_t* __restrict__ rank, int64_t n,
+                                      int32_t* __restrict__ values) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        if (flag[v]) values[rank[v]] = (int32_t)v;
+}
+
+// One output word per thread: gathers the indices of the pixels whose bits
+// fall into word w (bits [32w, 32w + 32), pixel p at bits [p b, p b + b),
+// least significant bit first). Stores are coalesced and need no atomics.
+__global__ void pack_kernel(const int32_t* __restrict__ counts, int64_t n_pix,
+                            const int32_t* __restrict__ rank, int64_t n_values, int bits,
+                            int64_t n_words, uint32_t* __restrict__ packed) {
+    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < n_words;
+         w += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t lo_bit = w * 32;
+        const int64_t p0 = lo_bit / bits;
+        int64_t p1 = (lo_bit + 31) / bits;
+        if (p1 > n_pix - 1) p1 = n_pix - 1;
+        unsigned long long word = 0;
+        for (int64_t p = p0; p <= p1; ++p) {
+            const int32_t c = counts[p];
+            const unsigned long long idx =
+                (c >= 0 && c < n_values) ? (unsigned long long)(uint32_t)rank[c] : 0ull;
+            const int64_t start = p * bits;
+            if (start >= lo_bit) word |= idx << (start - lo_bit);        // shift < 32
+            else word |= idx >> (lo_bit - start);                        // shift < bits <= 32
+        }
+        packed[w] = (uint32_t)word;
+    }
+}
+
+// Inverse of pack_kernel; an index past the table (a stream not produced by
+// the encoder) decodes to -1 instead of reading out of bounds.
+__global__ void unpack_kernel(const uint32_t* __restrict__ packed, int64_t n_pix, int bits,
+                              const int32_t* __restrict__ values, int64_t n_values,
+                              int32_t* __restrict__ counts) {
+    const unsigned long long mask = bits >= 32 ? 0xFFFFFFFFull : ((1ull << bits) - 1ull);
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n_pix;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t start = p * bits;
+        const int64_t w = start >> 5;
+        const int off = (int)(start & 31);
+        unsigned long long v = (unsigned long long)packed[w] >> off;
+        if (off + bits > 32) v |= (unsigned long long)packed[w + 1] << (32 - off);
+        const unsigned long long idx = v & mask;
+        counts[p] = idx < (unsigned long long)n_values ? values[idx] : -1;
+    }
 }
 
 int grid_for(int64_t n, int threads, int cap) {
@@ -834,6 +971,42 @@ hipError_t launch_mpd_moments(const unsigned long long* bins, int n_maps, int n_
     if (n_bins <= 0) return hipSuccess;
     hipLaunchKernelGGL(mpd_moments_kernel, dim3((n_bins + 255) / 256), dim3(256), 0, s, bins, n_maps,
                        n_bins, n_pix, mean, stdev);
+    return hipGetLastError();
+}
+
+int64_t scan_blocks(int64_t n) { return (n + kScanPerBlock - 1) / kScanPerBlock; }
+
+hipError_t launch_distinct_ranks(const unsigned long long* hist, int64_t n_values, int32_t* flag,
+                                 int32_t* rank, int32_t* block_sums, int64_t* total,
+                                 hipStream_t s) {
+    if (n_values <= 0) return hipSuccess;
+    const int64_t nb = scan_blocks(n_values);
+    hipLaunchKernelGGL(distinct_flag_kernel, dim3(grid_for(n_values, 256, 8192)), dim3(256), 0, s, hist,
+                       n_values, flag);
+    hipLaunchKernelGGL(scan_block_sums_kernel, dim3((unsigned)nb), dim3(256), 0, s, flag, n_values,
+                       block_sums);
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(256), 0, s, block_sums, nb, total);
+    hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nb), dim3(256), 0, s, flag, n_values,
+                       block_sums, rank);
+    return hipGetLastError();
+}
+
+hipError_t launch_codec_pack(const int32_t* counts, int64_t n_pix, const int32_t* flag,
+                             const int32_t* rank, int64_t n_values, int bits, int32_t* values,
+                             uint32_t* packed, hipStream_t s) {
+    const int64_t n_words = (n_pix * bits + 31) / 32;
+    hipLaunchKernelGGL(scatter_values_kernel, dim3(grid_for(n_values, 256, 8192)), dim3(256), 0, s, flag,
+                       rank, n_values, values);
+    hipLaunchKernelGGL(pack_kernel, dim3(grid_for(n_words, 256, 16384)), dim3(256), 0, s, counts, n_pix,
+                       rank, n_values, bits, n_words, packed);
+    return hipGetLastError();
+}
+
+hipError_t launch_codec_unpack(const uint32_t* packed, int64_t n_pix, int bits, const int32_t* values,
+                               int64_t n_values, int32_t* counts, hipStream_t s) {
+    if (n_pix <= 0) return hipSuccess;
+    hipLaunchKernelGGL(unpack_kernel, dim3(grid_for(n_pix, 256, 16384)), dim3(256), 0, s, packed, n_pix,
+                       bits, values, n_values, counts);
     return hipGetLastError();
 }
 

@@ -99,6 +99,8 @@ def load():
         "rl_mpd": [vp, vp, P(rl_window), dbl, dbl, dbl, dbl, i32, vp, vp],
         "rl_probability_sums": [vp, vp, P(rl_window), dbl, dbl, P(i64), P(i64), vp],
         "rl_mpd_moments": [vp, vp, i32, i32, i64, vp, vp, vp],
+        "rl_codec_encode": [vp, vp, P(rl_window), vp, i64, vp, i64, P(i64), P(i32), vp],
+        "rl_codec_decode": [vp, vp, i32, vp, i64, P(rl_window), vp, vp],
         "rl_get_tuning": [vp, C.c_int, i32, P(rl_tuning)],
         "rl_set_tuning": [vp, C.c_int, i32, P(rl_tuning)],
     }
@@ -200,6 +202,20 @@ def rl_probability_sums(ctx, d_counts, win, n_avg, mu_lim, stream=None):
 
 def rl_mpd_moments(ctx, d_bins, n_maps, n_bins, n_pix, d_mean, d_std, stream=None):
     _check(load().rl_mpd_moments(ctx, d_bins, n_maps, n_bins, n_pix, d_mean, d_std, stream))
+
+
+def rl_codec_encode(ctx, d_counts, win, d_values, values_capacity, d_packed, packed_capacity,
+                    stream=None):
+    nd = C.c_int64()
+    bits = C.c_int32()
+    _check(load().rl_codec_encode(ctx, d_counts, C.byref(win), d_values, values_capacity, d_packed,
+                                  packed_capacity, C.byref(nd), C.byref(bits), stream))
+    return nd.value, bits.value
+
+
+def rl_codec_decode(ctx, d_packed, bits, d_values, n_distinct, win, d_counts, stream=None):
+    _check(load().rl_codec_decode(ctx, d_packed, bits, d_values, n_distinct, C.byref(win), d_counts,
+                                  stream))
 
 
 def rl_get_tuning(ctx, precision, n_class) -> rl_tuning:
@@ -397,6 +413,31 @@ class Context:
         rl_mpd_moments(self.handle, bins.data_ptr(), bins.shape[0], bins.shape[1], int(n_pix),
                        mean.data_ptr(), std.data_ptr(), _stream_ptr(stream))
         return mean, std
+
+    # ---- indexed maps ----------------------------------------------------------
+    def encode(self, counts, spec, stream=None):
+        """Returns (values int32[n_distinct], bits, packed uint32 words) on the device."""
+        torch = _torch()
+        _check_counts(counts, spec)
+        nd, bits = rl_codec_encode(self.handle, counts.data_ptr(), window_of(spec), None, 0, None, 0,
+                                   _stream_ptr(stream))
+        words = (spec.p1 * spec.p2 * bits + 31) // 32
+        values = torch.empty(nd, dtype=torch.int32, device=counts.device)
+        packed = torch.empty(words, dtype=torch.int32, device=counts.device)   # 32-bit words
+        nd2, bits2 = rl_codec_encode(self.handle, counts.data_ptr(), window_of(spec), values.data_ptr(),
+                                     nd, packed.data_ptr(), words, _stream_ptr(stream))
+        assert (nd2, bits2) == (nd, bits)
+        return values, bits, packed
+
+    def decode(self, packed, bits, values, spec, counts=None, stream=None):
+        torch = _torch()
+        if counts is None:
+            counts = torch.empty((spec.p2, spec.p1), dtype=torch.int32, device=packed.device)
+        if packed.numel() < (spec.p1 * spec.p2 * bits + 31) // 32:
+            raise ValueError("packed stream too short for the map")
+        rl_codec_decode(self.handle, packed.data_ptr(), int(bits), values.data_ptr(), values.numel(),
+                        window_of(spec), counts.data_ptr(), _stream_ptr(stream))
+        return counts
 
     def get_tuning(self, precision, n_class):
         t = rl_get_tuning(self.handle, PRECISIONS[precision], n_class)

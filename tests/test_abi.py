@@ -187,3 +187,25 @@ def test_mpd_entry_points_validate_on_the_host():
         assert lib.rl_mpd_moments(ctx, fake, 3, 10, 0, fake, fake, None) == rl.RL_E_INVALID
     finally:
         rl.rl_destroy(ctx)
+
+
+def test_codec_entry_points_validate_on_the_host():
+    lib = rl.load()
+    ctx = rl.rl_create(0)
+    try:
+        w = rl.rl_window(16, 16, 0.0, 0.0, 2.0, 2.0)
+        fake = C.c_void_p(0x1000)
+        nd = C.c_int64()
+        bits = C.c_int32()
+        assert lib.rl_codec_encode(ctx, None, C.byref(w), fake, 1, fake, 1, C.byref(nd), C.byref(bits),
+                                   None) == rl.RL_E_INVALID
+        assert lib.rl_codec_encode(ctx, fake, C.byref(w), fake, 0, fake, 1, C.byref(nd), C.byref(bits),
+                                   None) == rl.RL_E_INVALID
+        assert lib.rl_codec_encode(ctx, fake, C.byref(w), fake, 1, fake, 1, None, C.byref(bits),
+                                   None) == rl.RL_E_INVALID
+        for b in (0, 33):
+            assert lib.rl_codec_decode(ctx, fake, b, fake, 4, C.byref(w), fake, None) == rl.RL_E_INVALID
+        assert lib.rl_codec_decode(ctx, fake, 4, fake, 0, C.byref(w), fake, None) == rl.RL_E_INVALID
+        assert lib.rl_codec_decode(ctx, None, 4, fake, 4, C.byref(w), fake, None) == rl.RL_E_INVALID
+    finally:
+        rl.rl_destroy(ctx)
