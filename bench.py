@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--serve-scale", type=float, default=0.25,
                     help="map-size scale of the served requests (1.0 = 1024^2-4096^2 maps)")
     ap.add_argument("--no-tuning-cache", action="store_true")
+    ap.add_argument("--no-post", action="store_true", help="skip the MPD and codec legs")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a known-size "
                          "kernel for scaling hardware traffic counters)")
@@ -166,6 +167,54 @@ def main():
                 "frac_fp64_peak": FLOPS_PER_EVAL * evals / k64 / 1e12 / FP64_PEAK_TFLOPS,
                 "mean_mu": st64["mean_mu"],
                 "mean_mu_rel_diff_fp32c": abs(st["mean_mu"] - st64["mean_mu"]) / st64["mean_mu"]}
+
+    # ---- post-processing of the map: MPD (Section 3.2.1 / 4) and codec (App. B) ----
+    post = None
+    if not args.no_post:
+        mu_th_abs = abs(st["mu_th"])
+        n_pix = spec.p1 * spec.p2
+        final = counts.clone()
+
+        def timed(fn, reps=5):
+            fn()
+            torch.cuda.synchronize()
+            ms = []
+            for _ in range(reps):
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                fn()
+                b.record(stream)
+                b.synchronize()
+                ms.append(a.elapsed_time(b))
+            return float(np.median(ms))
+
+        hist = torch.zeros(st["max_count"] + 1, dtype=torch.int64, device="cuda")
+        bins = torch.zeros(102, dtype=torch.int64, device="cuda")
+        t_hist = timed(lambda: ctx.count_histogram(final, spec, hist.numel(), hist=hist.zero_(),
+                                                   stream=stream))
+        t_mpd = timed(lambda: ctx.mpd(final, spec, mu_th_abs, -1.5, 1.5, 100, n_avg=n_avg,
+                                      bins=bins.zero_(), stream=stream))
+        t_sum = timed(lambda: ctx.probability_sums(final, spec, 1.25 * mu_th_abs, n_avg=n_avg,
+                                                   stream=stream))
+        values, bits, packed = ctx.encode(final, spec, stream=stream)
+        t_enc = timed(lambda: ctx.encode(final, spec, stream=stream), reps=3)
+        back = torch.empty_like(final)
+        t_dec = timed(lambda: ctx.decode(packed, bits, values, spec, counts=back, stream=stream))
+        assert torch.equal(back, final), "codec round trip failed"
+        gbs = lambda nbytes, ms: nbytes / (ms * 1e-3) / 1e9
+        post = {"pixels": n_pix,
+                "count_histogram_us": t_hist * 1e3, "count_histogram_GBps": gbs(4 * n_pix, t_hist),
+                "mpd_100bins_us": t_mpd * 1e3, "mpd_GBps": gbs(4 * n_pix, t_mpd),
+                "probability_sums_us": t_sum * 1e3,
+                "p_mu_above_1.25_mu_th": ctx.probability_sums(final, spec, 1.25 * mu_th_abs,
+                                                              n_avg=n_avg)[1] / n_pix,
+                "codec_distinct_values": int(values.numel()), "codec_bits": bits,
+                "codec_bytes": int(packed.numel() * 4 + values.numel() * 4),
+                "codec_ratio_vs_int32": (packed.numel() * 4 + values.numel() * 4) / (4 * n_pix),
+                "encode_ms": t_enc, "decode_us": t_dec * 1e3,
+                "decode_GBps": gbs(4 * n_pix + packed.numel() * 4, t_dec),
+                "hbm_peak_GBps": 8000.0}
 
     # ---- 64-map batched persistent launch ---------------------------------------
     batch = None
@@ -294,6 +343,7 @@ def main():
         "mean_mu": st["mean_mu"],
         "mu_th": st["mu_th"],
         "batch": batch,
+        "post_processing": post,
         "serving": serving,
         "tuning": "autotuned cache" if tuned else "defaults",
     }
