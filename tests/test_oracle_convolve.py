@@ -1,0 +1,69 @@
+"""Pins of the oracle's finite-source convolution (Section 2.4, eq. 6)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import convolve as cv
+
+
+def test_fft_convolution_equals_the_defining_sum():
+    rng = np.random.default_rng(1)
+    M = rng.integers(0, 50, size=(32, 48)).astype(np.float64)
+    for shape, R in (("uniform", 2.5), ("gaussian", 3.0), ("power", 4.0)):
+        K = cv.source_kernel(shape, 48, 32, 1.0, 1.0, R)
+        assert np.allclose(cv.convolve(M, K), cv.convolve_direct(M, K), rtol=0, atol=1e-10)
+
+
+def test_delta_kernel_is_the_identity_and_flux_is_conserved():
+    rng = np.random.default_rng(2)
+    M = rng.integers(0, 1000, size=(64, 64)).astype(np.float64)
+    K = np.zeros_like(M)
+    K[0, 0] = 1.0
+    assert np.allclose(cv.convolve(M, K), M, rtol=0, atol=1e-9)
+    K = cv.source_kernel("gaussian", 64, 64, 1.0, 1.0, 6.0)
+    C = cv.convolve(M, K)
+    assert abs(C.sum() - M.sum()) < 1e-8 * M.sum()
+    assert abs(cv.convolve(M, K, n_avg=4.0).sum() - M.sum() / 4.0) < 1e-8 * M.sum()
+
+
+def test_shift_equivariance():
+    rng = np.random.default_rng(3)
+    M = rng.random((32, 32))
+    K = cv.source_kernel("power", 32, 32, 1.0, 1.0, 3.0, hole=0.5)
+    a = np.roll(cv.convolve(M, K), (3, -5), axis=(0, 1))
+    b = cv.convolve(np.roll(M, (3, -5), axis=(0, 1)), K)
+    assert np.allclose(a, b, atol=1e-12)
+
+
+def test_uniform_kernel_weights_match_disc_area():
+    """A large uniform disc: the kernel is ~1/(pi R^2) inside and 0 outside, and
+    its number of touched pixels matches the disc area up to the rim."""
+    R = 20.0
+    K = cv.source_kernel("uniform", 128, 128, 1.0, 1.0, R)
+    assert abs(K.sum() - 1.0) < 1e-12
+    assert abs(K[0, 0] * math.pi * R * R - 1.0) < 0.01
+    full = np.count_nonzero(K > 0.999 * K[0, 0])
+    assert abs(full - math.pi * R * R) < 2 * math.pi * R
+    assert K[0, 25] == 0.0 and K[25, 0] == 0.0
+
+
+def test_profile_shapes():
+    r = np.array([0.0, 0.5, 1.0, 2.0, 2.999, 3.0, 4.0])
+    u = cv.brightness("uniform", r, 3.0)
+    assert u.tolist() == [1, 1, 1, 1, 1, 0, 0]
+    g = cv.brightness("gaussian", r, 3.0)
+    assert g[0] == 1.0 and abs(g[3] - math.exp(-2.0)) < 1e-15 and g[5] == 0.0
+    p = cv.brightness("power", r, 3.0)
+    assert abs(p[0] - (0.03 / 3.0) ** -0.75) < 1e-12           # flat inside the core r < R/100
+    assert abs(p[1] - (0.5 / 3.0) ** -0.75) < 1e-12
+    assert abs(p[4] / p[3] - (2.999 / 2.0) ** -0.75) < 1e-12
+    h = cv.brightness("uniform", r, 3.0, hole=1.0)
+    assert h.tolist() == [0, 0, 1, 1, 1, 0, 0]
+
+
+def test_invalid():
+    with pytest.raises(ValueError):
+        cv.source_kernel("uniform", 16, 16, 1.0, 1.0, 10.0)
+    with pytest.raises(ValueError):
+        cv.brightness("cone", 1.0, 2.0)
