@@ -299,6 +299,46 @@ rl_status rl_codec_decode(rl_context* ctx, const uint32_t* d_packed, int32_t bit
                           const int32_t* d_values, int64_t n_distinct, const rl_window* win,
                           int32_t* d_counts, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Finite sources (Section 2.4)
+ * ------------------------------------------------------------------------ */
+
+/* Source profile shapes (Section 3.1: uniform disc, Gaussian, thin-disc power
+ * law, optionally with a central hole). */
+typedef enum {
+    RL_PROFILE_UNIFORM = 0,    /* I = 1 for r < radius */
+    RL_PROFILE_GAUSSIAN = 1,   /* I = exp(-r^2 / (2 sigma^2)), sigma = radius / 3, cut at radius */
+    RL_PROFILE_POWER = 2       /* I = (max(r, radius / 100) / radius)^(-3/4) for r < radius */
+} rl_profile_shape;
+
+/* A circular source: shape, radius (where the brightness drops to zero, the
+ * size of Table "components") and an optional central hole (I = 0 for
+ * r < hole), both in Einstein radii like the map window. */
+typedef struct {
+    int32_t shape;
+    double radius;
+    double hole;
+} rl_profile;
+
+/* Convolution kernel of a source on the map's pixel grid (Section 2.4: the
+ * profile binned in pixels of the map's pixel size, padded with zeros to the
+ * map's size): pixel (i, j) around the source centre gets the mean brightness
+ * over an 8 x 8 grid of sub-samples, the kernel is centred on pixel (0, 0)
+ * with wrap-around (so convolution does not shift the map) and normalised to
+ * unit sum (so it conserves rays). d_kernel is double[p2 x p1], overwritten.
+ * The source must fit: 2 ceil(radius / pixel) + 1 <= p on both axes.
+ * Asynchronous. */
+rl_status rl_source_kernel(rl_context* ctx, const rl_profile* profile, const rl_window* win,
+                           double* d_kernel, hipStream_t stream);
+
+/* Finite-source map (Section 2.4, eq. 6): d_out = F^-1[F(M) F(K)] / n_avg, the
+ * circular convolution of the count map M (int32, p2 x p1) with the kernel K
+ * (double, p2 x p1, e.g. from rl_source_kernel) divided by n_avg (pass N_avg
+ * for a magnification map, 1 for convolved counts), in FP64. p1 and p2 must
+ * be powers of two in [2, 4096]. d_out is double[p2 x p1]. Asynchronous. */
+rl_status rl_convolve(rl_context* ctx, const int32_t* d_counts, const double* d_kernel,
+                      const rl_window* win, double n_avg, double* d_out, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -225,7 +225,8 @@ struct rl_context {
     Scratch lens;        // FP32 lens copies
     Scratch batch;       // map records + work items + counter
     Scratch stats;       // reduction outputs
-    Scratch aux;         // MPD thresholds
+    Scratch aux;         // MPD thresholds, codec tables, source samples
+    Scratch fft;         // convolution planes
     void* host_stage = nullptr;  // pinned staging for batch records
     size_t host_cap = 0;
     hipEvent_t stage_done = nullptr;
@@ -337,6 +338,7 @@ rl_status rl_destroy(rl_context* ctx) {
         ctx->batch.destroy();
         ctx->stats.destroy();
         ctx->aux.destroy();
+        ctx->fft.destroy();
         if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
         if (ctx->stage_done) (void)hipEventDestroy(ctx->stage_done);
     }
@@ -843,6 +845,57 @@ rl_status rl_codec_decode(rl_context* ctx, const uint32_t* d_packed, int32_t bit
     hipError_t e = rl::launch_codec_unpack(d_packed, (int64_t)win->p1 * win->p2, bits, d_values,
                                            n_distinct, d_counts, stream);
     if (e != hipSuccess) return hip_fail(e, "codec unpack");
+    return RL_OK;
+}
+
+rl_status rl_source_kernel(rl_context* ctx, const rl_profile* profile, const rl_window* win,
+                           double* d_kernel, hipStream_t stream) {
+    g_error.clear();
+    if (!ctx) return fail(RL_E_INVALID, "context is NULL");
+    RL_TRY(check_window(win));
+    if (!profile || !d_kernel) return fail(RL_E_INVALID, "pointers are NULL");
+    if (profile->shape < RL_PROFILE_UNIFORM || profile->shape > RL_PROFILE_POWER)
+        return fail(RL_E_INVALID, "unknown profile shape");
+    if (!is_finite(profile->radius) || !(profile->radius > 0.0) || !is_finite(profile->hole) ||
+        profile->hole < 0.0)
+        return fail(RL_E_INVALID, "radius must be finite and > 0, hole finite and >= 0");
+    const double pix1 = win->width1 / (double)win->p1, pix2 = win->width2 / (double)win->p2;
+    const double h1d = std::ceil(profile->radius / pix1), h2d = std::ceil(profile->radius / pix2);
+    if (2.0 * h1d + 1.0 > (double)win->p1 || 2.0 * h2d + 1.0 > (double)win->p2)
+        return fail(RL_E_INVALID, "source larger than the map");
+    const int h1 = (int)h1d, h2 = (int)h2d;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return hip_fail(dg.err, "hipSetDevice");
+    RL_TRY(ensure_ready(ctx));
+    hipError_t e = ctx->aux.acquire(rl::source_scratch_bytes(h1, h2), stream);
+    if (e != hipSuccess) return hip_fail(e, "source scratch");
+    e = rl::launch_source_kernel(profile->shape, profile->radius, profile->hole, pix1, pix2, h1, h2,
+                                 win->p1, win->p2, d_kernel, static_cast<double*>(ctx->aux.ptr), stream);
+    hipError_t e2 = ctx->aux.release(stream);
+    if (e == hipSuccess) e = e2;
+    if (e != hipSuccess) return hip_fail(e, "source kernel launch");
+    return RL_OK;
+}
+
+rl_status rl_convolve(rl_context* ctx, const int32_t* d_counts, const double* d_kernel,
+                      const rl_window* win, double n_avg, double* d_out, hipStream_t stream) {
+    g_error.clear();
+    if (!ctx) return fail(RL_E_INVALID, "context is NULL");
+    RL_TRY(check_counts(d_counts, win));
+    if (!d_kernel || !d_out) return fail(RL_E_INVALID, "pointers are NULL");
+    if (!is_finite(n_avg) || !(n_avg > 0.0)) return fail(RL_E_INVALID, "n_avg must be finite and > 0");
+    auto pow2 = [](int v) { return v >= 2 && v <= rl::kMaxFftSide && (v & (v - 1)) == 0; };
+    if (!pow2(win->p1) || !pow2(win->p2))
+        return fail(RL_E_INVALID, "map sides must be powers of two in [2, %d]", rl::kMaxFftSide);
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return hip_fail(dg.err, "hipSetDevice");
+    RL_TRY(ensure_ready(ctx));
+    hipError_t e = ctx->fft.acquire(rl::convolve_scratch_bytes(win->p1, win->p2), stream);
+    if (e != hipSuccess) return hip_fail(e, "convolution scratch");
+    e = rl::launch_convolve(d_counts, d_kernel, win->p1, win->p2, n_avg, d_out, ctx->fft.ptr, stream);
+    hipError_t e2 = ctx->fft.release(stream);
+    if (e == hipSuccess) e = e2;
+    if (e != hipSuccess) return hip_fail(e, "convolution launch");
     return RL_OK;
 }
 

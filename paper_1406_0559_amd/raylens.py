@@ -58,6 +58,13 @@ class rl_map_desc(C.Structure):
                 ("d_counts", C.c_void_p), ("d_escaped", C.c_void_p)]
 
 
+class rl_profile(C.Structure):
+    _fields_ = [("shape", C.c_int32), ("radius", C.c_double), ("hole", C.c_double)]
+
+
+PROFILES = {"uniform": 0, "gaussian": 1, "power": 2}
+
+
 class rl_tuning(C.Structure):
     _fields_ = [("rays_x", C.c_int32), ("rays_y", C.c_int32), ("lens_tile", C.c_int32),
                 ("waves", C.c_int32), ("submap", C.c_int32), ("item_cells", C.c_int32)]
@@ -101,6 +108,8 @@ def load():
         "rl_mpd_moments": [vp, vp, i32, i32, i64, vp, vp, vp],
         "rl_codec_encode": [vp, vp, P(rl_window), vp, i64, vp, i64, P(i64), P(i32), vp],
         "rl_codec_decode": [vp, vp, i32, vp, i64, P(rl_window), vp, vp],
+        "rl_source_kernel": [vp, P(rl_profile), P(rl_window), vp, vp],
+        "rl_convolve": [vp, vp, vp, P(rl_window), dbl, vp, vp],
         "rl_get_tuning": [vp, C.c_int, i32, P(rl_tuning)],
         "rl_set_tuning": [vp, C.c_int, i32, P(rl_tuning)],
     }
@@ -216,6 +225,14 @@ def rl_codec_encode(ctx, d_counts, win, d_values, values_capacity, d_packed, pac
 def rl_codec_decode(ctx, d_packed, bits, d_values, n_distinct, win, d_counts, stream=None):
     _check(load().rl_codec_decode(ctx, d_packed, bits, d_values, n_distinct, C.byref(win), d_counts,
                                   stream))
+
+
+def rl_source_kernel(ctx, profile, win, d_kernel, stream=None):
+    _check(load().rl_source_kernel(ctx, C.byref(profile), C.byref(win), d_kernel, stream))
+
+
+def rl_convolve(ctx, d_counts, d_kernel, win, n_avg, d_out, stream=None):
+    _check(load().rl_convolve(ctx, d_counts, d_kernel, C.byref(win), n_avg, d_out, stream))
 
 
 def rl_get_tuning(ctx, precision, n_class) -> rl_tuning:
@@ -438,6 +455,26 @@ class Context:
         rl_codec_decode(self.handle, packed.data_ptr(), int(bits), values.data_ptr(), values.numel(),
                         window_of(spec), counts.data_ptr(), _stream_ptr(stream))
         return counts
+
+    # ---- finite sources ---------------------------------------------------------
+    def source_kernel(self, spec, shape, radius, hole=0.0, kernel=None, stream=None):
+        torch = _torch()
+        if kernel is None:
+            kernel = torch.empty((spec.p2, spec.p1), dtype=torch.float64, device=f"cuda:{self.device}")
+        rl_source_kernel(self.handle, rl_profile(PROFILES[shape], radius, hole), window_of(spec),
+                         kernel.data_ptr(), _stream_ptr(stream))
+        return kernel
+
+    def convolve(self, counts, kernel, spec, n_avg=1.0, out=None, stream=None):
+        torch = _torch()
+        _check_counts(counts, spec)
+        if kernel.dtype != torch.float64 or kernel.numel() != spec.p1 * spec.p2 or not kernel.is_contiguous():
+            raise ValueError("kernel must be a contiguous float64 p2 x p1 tensor")
+        if out is None:
+            out = torch.empty((spec.p2, spec.p1), dtype=torch.float64, device=counts.device)
+        rl_convolve(self.handle, counts.data_ptr(), kernel.data_ptr(), window_of(spec), n_avg,
+                    out.data_ptr(), _stream_ptr(stream))
+        return out
 
     def get_tuning(self, precision, n_class):
         t = rl_get_tuning(self.handle, PRECISIONS[precision], n_class)

@@ -209,3 +209,21 @@ def test_codec_entry_points_validate_on_the_host():
         assert lib.rl_codec_decode(ctx, None, 4, fake, 4, C.byref(w), fake, None) == rl.RL_E_INVALID
     finally:
         rl.rl_destroy(ctx)
+
+
+def test_convolution_entry_points_validate_on_the_host():
+    lib = rl.load()
+    ctx = rl.rl_create(0)
+    try:
+        w = rl.rl_window(64, 64, 0.0, 0.0, 2.0, 2.0)
+        fake = C.c_void_p(0x1000)
+        for prof in (rl.rl_profile(5, 0.1, 0.0), rl.rl_profile(0, -0.1, 0.0), rl.rl_profile(0, 0.1, -1.0),
+                     rl.rl_profile(1, math.nan, 0.0), rl.rl_profile(0, 5.0, 0.0)):
+            assert lib.rl_source_kernel(ctx, C.byref(prof), C.byref(w), fake, None) == rl.RL_E_INVALID
+        for ww in (rl.rl_window(48, 64, 0.0, 0.0, 2.0, 2.0), rl.rl_window(8192, 2, 0.0, 0.0, 2.0, 2.0),
+                   rl.rl_window(1, 64, 0.0, 0.0, 2.0, 2.0)):
+            assert lib.rl_convolve(ctx, fake, fake, C.byref(ww), 1.0, fake, None) == rl.RL_E_INVALID
+        assert lib.rl_convolve(ctx, fake, fake, C.byref(w), 0.0, fake, None) == rl.RL_E_INVALID
+        assert lib.rl_convolve(ctx, fake, None, C.byref(w), 1.0, fake, None) == rl.RL_E_INVALID
+    finally:
+        rl.rl_destroy(ctx)

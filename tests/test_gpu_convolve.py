@@ -1,0 +1,76 @@
+"""Finite-source maps on the GPU against the oracle (Section 2.4, eq. 6):
+source kernels to 1e-13 relative, FFT convolutions to 1e-10 of the map's
+largest value (both FP64; the FFTs differ only in rounding order)."""
+import numpy as np
+import pytest
+
+from oracle import convolve as ocv
+from paper_1406_0559_amd import inputs
+from paper_1406_0559_amd import raylens as rl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available()
+    c = rl.Context(0)
+    yield c
+    c.close()
+
+
+def spec_of(p1, p2, W1=4.0, W2=4.0):
+    return inputs.MapSpec(name="conv", kappa=0.5, gamma=0.2, s=0.0, n1=10, n2=10, h1=1.0, h2=1.0,
+                          p1=p1, p2=p2, W1=W1, W2=W2)
+
+
+@pytest.mark.parametrize("shape,radius,hole", [("uniform", 0.237, 0.0), ("gaussian", 0.311, 0.0),
+                                               ("power", 0.419, 0.05), ("uniform", 0.013, 0.0)])
+def test_source_kernel_matches_the_oracle(ctx, shape, radius, hole):
+    spec = spec_of(128, 64, 4.0, 3.0)
+    k = ctx.source_kernel(spec, shape, radius, hole).cpu().numpy()
+    ref = ocv.source_kernel(shape, spec.p1, spec.p2, spec.W1 / spec.p1, spec.W2 / spec.p2, radius, hole)
+    assert np.abs(k - ref).max() <= 1e-13 * ref.max()
+    assert abs(k.sum() - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("p1,p2", [(2, 2), (16, 8), (64, 256), (1024, 512)])
+def test_convolution_matches_the_oracle(ctx, p1, p2):
+    rng = np.random.default_rng(p1 + p2)
+    spec = spec_of(p1, p2)
+    M = rng.integers(0, 1000, size=(p2, p1)).astype(np.int32)
+    K = rng.random((p2, p1))
+    K /= K.sum()
+    out = ctx.convolve(torch.from_numpy(M).cuda(), torch.from_numpy(K).cuda(), spec, n_avg=3.7)
+    ref = ocv.convolve(M, K, 3.7)
+    assert np.abs(out.cpu().numpy() - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def test_delta_kernel_and_flux(ctx):
+    rng = np.random.default_rng(5)
+    spec = spec_of(256, 128)
+    M = rng.integers(0, 5000, size=(128, 256)).astype(np.int32)
+    K = np.zeros((128, 256))
+    K[0, 0] = 1.0
+    out = ctx.convolve(torch.from_numpy(M).cuda(), torch.from_numpy(K).cuda(), spec).cpu().numpy()
+    assert np.abs(out - M).max() < 1e-8
+    k = ctx.source_kernel(spec, "gaussian", 0.2)
+    out = ctx.convolve(torch.from_numpy(M).cuda(), k, spec).cpu().numpy()
+    assert abs(out.sum() - M.sum()) < 1e-9 * M.sum()
+
+
+def test_finite_source_map_of_the_full_size_workload(ctx):
+    """The 4096^2 GERLUMPH-like map convolved with a Gaussian disc of radius
+    0.2 Einstein radii (1e16 cm for R_Ein = 5e16 cm), as magnification."""
+    spec = inputs.config_gerlumph()
+    f = spec.lenses()
+    counts, _ = ctx.shoot(rl.DeviceLenses(f.x1, f.x2, f.m), spec, "fp32c")
+    navg = rl.rl_n_avg(rl.grid_of(spec), rl.window_of(spec))
+    k = ctx.source_kernel(spec, "gaussian", 0.2)
+    mu = ctx.convolve(counts, k, spec, n_avg=navg).cpu().numpy()
+    ref = ocv.convolve(counts.cpu().numpy(), k.cpu().numpy(), navg)
+    assert np.abs(mu - ref).max() <= 1e-10 * np.abs(ref).max()
+    assert abs(mu.mean() - counts.sum().item() / counts.numel() / navg) < 1e-9
+    # smoothing: the convolved map varies less than the point-source map
+    assert mu.std() < (counts.cpu().numpy() / navg).std()
