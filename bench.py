@@ -202,8 +202,15 @@ def main():
         back = torch.empty_like(final)
         t_dec = timed(lambda: ctx.decode(packed, bits, values, spec, counts=back, stream=stream))
         assert torch.equal(back, final), "codec round trip failed"
+        # finite source (Section 2.4, eq. 6): Gaussian disc of 0.2 Einstein radii
+        kern = ctx.source_kernel(spec, "gaussian", 0.2, stream=stream)
+        conv = torch.empty((spec.p2, spec.p1), dtype=torch.float64, device="cuda")
+        t_kern = timed(lambda: ctx.source_kernel(spec, "gaussian", 0.2, kernel=kern, stream=stream))
+        t_conv = timed(lambda: ctx.convolve(final, kern, spec, n_avg=n_avg, out=conv, stream=stream))
         gbs = lambda nbytes, ms: nbytes / (ms * 1e-3) / 1e9
         post = {"pixels": n_pix,
+                "source_kernel_us": t_kern * 1e3, "convolve_ms": t_conv,
+                "convolve_min_GBps": gbs(20 * n_pix, t_conv),
                 "count_histogram_us": t_hist * 1e3, "count_histogram_GBps": gbs(4 * n_pix, t_hist),
                 "mpd_100bins_us": t_mpd * 1e3, "mpd_GBps": gbs(4 * n_pix, t_mpd),
                 "probability_sums_us": t_sum * 1e3,
