@@ -335,7 +335,9 @@ rl_status rl_source_kernel(rl_context* ctx, const rl_profile* profile, const rl_
  * circular convolution of the count map M (int32, p2 x p1) with the kernel K
  * (double, p2 x p1, e.g. from rl_source_kernel) divided by n_avg (pass N_avg
  * for a magnification map, 1 for convolved counts), in FP64. p1 and p2 must
- * be powers of two in [2, 4096]. d_out is double[p2 x p1]. Asynchronous. */
+ * be products of 2, 3 and 5 in [2, 10240] (4096 and 10000 are). d_out is
+ * double[p2 x p1]; the library holds 32 p1 p2 bytes of scratch per context
+ * while it runs. Asynchronous. */
 rl_status rl_convolve(rl_context* ctx, const int32_t* d_counts, const double* d_kernel,
                       const rl_window* win, double n_avg, double* d_out, hipStream_t stream);
 

@@ -86,3 +86,19 @@ def convolve_direct(counts, kernel, n_avg=1.0):
     for b, a in zip(*np.nonzero(K)):
         C += K[b, a] * np.roll(np.roll(M, b, axis=0), a, axis=1)
     return C / n_avg
+
+
+def convolve_at(counts, kernel, points, n_avg=1.0):
+    """C at the given pixels (j, i) by the defining sum over the kernel's
+    non-zero entries, for spot checks of large maps:
+    C[j, i] = sum over (b, a) of K[b, a] M[(j - b) mod p2, (i - a) mod p1] / n_avg."""
+    M = np.asarray(counts)
+    K = np.asarray(kernel, dtype=np.float64)
+    p2, p1 = M.shape
+    nz_b, nz_a = np.nonzero(K)
+    w = K[nz_b, nz_a]
+    out = []
+    for j, i in points:
+        vals = M[(j - nz_b) % p2, (i - nz_a) % p1].astype(np.float64)
+        out.append(float(np.sum(w * vals)) / n_avg)
+    return np.array(out)

@@ -884,9 +884,8 @@ rl_status rl_convolve(rl_context* ctx, const int32_t* d_counts, const double* d_
     RL_TRY(check_counts(d_counts, win));
     if (!d_kernel || !d_out) return fail(RL_E_INVALID, "pointers are NULL");
     if (!is_finite(n_avg) || !(n_avg > 0.0)) return fail(RL_E_INVALID, "n_avg must be finite and > 0");
-    auto pow2 = [](int v) { return v >= 2 && v <= rl::kMaxFftSide && (v & (v - 1)) == 0; };
-    if (!pow2(win->p1) || !pow2(win->p2))
-        return fail(RL_E_INVALID, "map sides must be powers of two in [2, %d]", rl::kMaxFftSide);
+    if (!rl::fft_side_supported(win->p1) || !rl::fft_side_supported(win->p2))
+        return fail(RL_E_INVALID, "map sides must be products of 2, 3 and 5 in [2, %d]", rl::kMaxFftSide);
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return hip_fail(dg.err, "hipSetDevice");
     RL_TRY(ensure_ready(ctx));

@@ -7,11 +7,21 @@
 // both spectra (F(M)[u] = (Z[u] + conj Z[-u]) / 2, F(K)[u] = (Z[u] - conj Z[-u]) / 2i);
 // their product is Hermitian, and one inverse 2D FFT returns C. All in FP64.
 //
-// 2D FFTs are row FFTs (one workgroup per row, radix-2 in LDS with a
-// bit-reversed load), a tiled transpose, and row FFTs again; the product is
-// formed in the transposed layout and the inverse undoes the two passes in
-// reverse order. Sizes are powers of two up to 4096 per side (a 4096-point
-// complex FP64 row is the 64 KiB of LDS one workgroup may use).
+// K is scaled by a power of two before packing so that both spectra keep full
+// precision (see norms_kernel). Each axis is a batch of row FFTs in LDS, one
+// workgroup per row: mixed radix (2, 3, 4, 5), decimation in time from a
+// digit-reversed load for forward transforms and decimation in frequency with
+// a digit-reversed store for inverse ones, so no pass needs a separate
+// reordering. After a norm reduction, five passes over HBM:
+//   1. forward along x1, packing Z = M + i 2^e K on load;
+//   2. transpose (32 x 32 LDS tiles);
+//   3. per pair of rows u1, -u1: forward along x2, spectrum product, inverse
+//      along x2 (the pair shares one workgroup, so the product needs no pass);
+//   4. transpose back;
+//   5. inverse along x1, writing Re(C) / (p1 p2 n_avg).
+// Sides are products of 2, 3 and 5 up to 10240 (one FP64 complex row of 10240
+// points is 160 KiB, the LDS of one workgroup on gfx950); sides above 5120 do
+// pass 3 as forward rows, a product pass and inverse rows.
 #include <climits>
 
 #include "internal.h"
@@ -24,51 +34,337 @@ struct cplx { double x, y; };
 __device__ __forceinline__ cplx cmul(cplx a, cplx b) {
     return cplx{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
+__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return cplx{a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ cplx csub(cplx a, cplx b) { return cplx{a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ cplx cscale(cplx a, double s) { return cplx{a.x * s, a.y * s}; }
+__device__ __forceinline__ cplx conj(cplx a) { return cplx{a.x, -a.y}; }
+// sg * i * a, sg = +1 or -1
+__device__ __forceinline__ cplx rot(cplx a, double sg) { return cplx{-sg * a.y, sg * a.x}; }
 
-// tw[k] = exp(-2 pi i k / n), k < n / 2
+// tw[k] = exp(-2 pi i k / n), k < n
 __global__ void twiddle_kernel(cplx* __restrict__ tw, int n) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n / 2) return;
+    if (k >= n) return;
     double s, c;
     sincospi(2.0 * (double)k / (double)n, &s, &c);
     tw[k] = cplx{c, -s};
 }
 
-__global__ void pack_kernel(const int32_t* __restrict__ m, const double* __restrict__ k, int64_t n,
-                            cplx* __restrict__ z) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        z[i] = cplx{(double)m[i], k[i]};
+// In-place DFTs of 2, 3, 4 and 5 points: y_k = sum_q a_q exp(sg 2 pi i k q / r),
+// sg = -1 forward, +1 inverse.
+constexpr double kSin60 = 0.86602540378443864676;    // sqrt(3) / 2
+constexpr double kCos72 = 0.30901699437494742410;    // (sqrt(5) - 1) / 4
+constexpr double kCos144 = -0.80901699437494742410;  // -(sqrt(5) + 1) / 4
+constexpr double kSin72 = 0.95105651629515357212;
+constexpr double kSin144 = 0.58778525229247312917;
+
+template <int R>
+__device__ __forceinline__ void small_dft(cplx* a, double sg) {
+    if constexpr (R == 2) {
+        const cplx t = a[1];
+        a[1] = csub(a[0], t);
+        a[0] = cadd(a[0], t);
+    } else if constexpr (R == 3) {
+        const cplx t = cadd(a[1], a[2]);
+        const cplx d = cscale(csub(a[1], a[2]), kSin60);
+        const cplx m = csub(a[0], cscale(t, 0.5));
+        a[0] = cadd(a[0], t);
+        a[1] = cadd(m, rot(d, sg));
+        a[2] = csub(m, rot(d, sg));
+    } else if constexpr (R == 4) {
+        const cplx t0 = cadd(a[0], a[2]), t1 = csub(a[0], a[2]);
+        const cplx t2 = cadd(a[1], a[3]), t3 = rot(csub(a[1], a[3]), sg);
+        a[0] = cadd(t0, t2);
+        a[2] = csub(t0, t2);
+        a[1] = cadd(t1, t3);
+        a[3] = csub(t1, t3);
+    } else {
+        const cplx t1 = cadd(a[1], a[4]), t2 = cadd(a[2], a[3]);
+        const cplx d1 = csub(a[1], a[4]), d2 = csub(a[2], a[3]);
+        const cplx p1 = cadd(a[0], cadd(cscale(t1, kCos72), cscale(t2, kCos144)));
+        const cplx p2 = cadd(a[0], cadd(cscale(t1, kCos144), cscale(t2, kCos72)));
+        const cplx q1 = rot(cadd(cscale(d1, kSin72), cscale(d2, kSin144)), sg);
+        const cplx q2 = rot(csub(cscale(d1, kSin144), cscale(d2, kSin72)), sg);
+        a[0] = cadd(a[0], cadd(t1, t2));
+        a[1] = cadd(p1, q1);
+        a[4] = csub(p1, q1);
+        a[2] = cadd(p2, q2);
+        a[3] = csub(p2, q2);
+    }
 }
 
-// In-place FFT of each row of length n = 2^logn (one workgroup per row).
-// Forward uses tw, inverse its conjugate; no scaling.
-__global__ void __launch_bounds__(256) fft_rows_kernel(cplx* __restrict__ z, int n, int logn,
-                                                       const cplx* __restrict__ tw, int inverse) {
-    extern __shared__ __align__(16) char smem[];
-    cplx* buf = reinterpret_cast<cplx*>(smem);
-    cplx* row = z + (int64_t)blockIdx.x * n;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const int r = (int)(__brev((unsigned)i) >> (32 - logn));
-        buf[r] = row[i];
+}  // namespace
+
+// Mixed-radix plan of one FFT length n = r_0 r_1 ... r_{ns-1} (radices 2-5).
+// L[s] = r_0 ... r_{s-1}; stage s joins n / L[s+1] groups of r_s transforms of
+// length L[s]. For L[s] > 1, div[s] = ceil(2^32 / L[s]) divides a butterfly
+// index by L[s] with one high multiply (exact for index * L[s] < 2^32).
+struct FftPlan {
+    int32_t n, ns;
+    int32_t r[16];
+    int32_t L[17];
+    uint32_t div[16];
+};
+
+namespace {
+
+bool make_plan(int n, FftPlan* P) {
+    if (n < 2) return false;
+    P->n = n;
+    P->ns = 0;
+    int m = n;
+    auto push = [&](int r) {
+        if (P->ns >= 16) return false;
+        P->r[P->ns++] = r;
+        m /= r;
+        return true;
+    };
+    while (m % 4 == 0) if (!push(4)) return false;
+    while (m % 2 == 0) if (!push(2)) return false;
+    while (m % 3 == 0) if (!push(3)) return false;
+    while (m % 5 == 0) if (!push(5)) return false;
+    if (m != 1) return false;
+    P->L[0] = 1;
+    for (int s = 0; s < P->ns; ++s) {
+        P->L[s + 1] = P->L[s] * P->r[s];
+        P->div[s] = P->L[s] == 1 ? 0u
+                  : (uint32_t)((((uint64_t)1 << 32) + (uint64_t)P->L[s] - 1) / (uint64_t)P->L[s]);
     }
+    return true;
+}
+
+// Position of natural index i in the digit-reversed order that an in-place
+// decimation-in-time pass reads (and a decimation-in-frequency pass writes).
+__device__ __forceinline__ int digit_pos(int i, const FftPlan& P) {
+    int p = 0;
+    for (int s = P.ns - 1; s >= 0; --s) {
+        int d;
+        switch (P.r[s]) {
+            case 4: d = i & 3; i >>= 2; break;
+            case 2: d = i & 1; i >>= 1; break;
+            case 3: d = i % 3; i /= 3; break;
+            default: d = i % 5; i /= 5; break;
+        }
+        p += d * P.L[s];
+    }
+    return p;
+}
+
+// One stage over `rows` consecutive LDS rows of length n. DIT: twiddle, then
+// DFT; DIF: DFT, then twiddle. tw is exp(-2 pi i k / n); inverse conjugates.
+template <int R, bool DIF>
+__device__ __forceinline__ void stage(cplx* buf, const FftPlan& P, int s, int rows,
+                                      const cplx* __restrict__ tw, bool inverse) {
+    const int n = P.n, Ls = P.L[s], Ln = P.L[s + 1];
+    const int tstep = n / Ln;
+    const int nb = n / R;
+    const double sg = inverse ? 1.0 : -1.0;
+    for (int b = threadIdx.x; b < rows * nb; b += blockDim.x) {
+        int bb = b, row = 0;
+        while (bb >= nb) { bb -= nb; ++row; }
+        const int g = Ls == 1 ? bb : (int)__umulhi((unsigned)bb, P.div[s]);
+        const int j = bb - g * Ls;
+        cplx* base = buf + row * n + g * Ln + j;
+        cplx a[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) a[q] = base[q * Ls];
+        if (!DIF) {
+#pragma unroll
+            for (int q = 1; q < R; ++q) {
+                cplx w = tw[j * q * tstep];
+                if (inverse) w.y = -w.y;
+                a[q] = cmul(a[q], w);
+            }
+        }
+        small_dft<R>(a, sg);
+        if (DIF) {
+#pragma unroll
+            for (int q = 1; q < R; ++q) {
+                cplx w = tw[j * q * tstep];
+                if (inverse) w.y = -w.y;
+                a[q] = cmul(a[q], w);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < R; ++q) base[q * Ls] = a[q];
+    }
+}
+
+template <bool DIF>
+__device__ void run_stage(cplx* buf, const FftPlan& P, int s, int rows, const cplx* tw, bool inverse) {
+    switch (P.r[s]) {
+        case 4: stage<4, DIF>(buf, P, s, rows, tw, inverse); break;
+        case 2: stage<2, DIF>(buf, P, s, rows, tw, inverse); break;
+        case 3: stage<3, DIF>(buf, P, s, rows, tw, inverse); break;
+        default: stage<5, DIF>(buf, P, s, rows, tw, inverse); break;
+    }
+}
+
+// Digit-reversed input -> natural-order transform.
+__device__ void dit(cplx* buf, const FftPlan& P, int rows, const cplx* tw, bool inverse) {
+    for (int s = 0; s < P.ns; ++s) {
+        run_stage<false>(buf, P, s, rows, tw, inverse);
+        __syncthreads();
+    }
+}
+
+// Natural-order input -> digit-reversed transform (the transpose of dit).
+__device__ void dif(cplx* buf, const FftPlan& P, int rows, const cplx* tw, bool inverse) {
+    for (int s = P.ns - 1; s >= 0; --s) {
+        run_stage<true>(buf, P, s, rows, tw, inverse);
+        __syncthreads();
+    }
+}
+
+enum RowMode { kFwdPack = 0, kFwd = 1, kInv = 2, kInvOut = 3 };
+
+// One workgroup per row of length P.n (<= MAXN), transformed in LDS.
+// kFwdPack: row of Z = M + iK from the counts and the kernel, forward, natural
+//           order out. kFwd: complex row, forward. kInv: complex row, inverse,
+//           natural order out. kInvOut: inverse, Re * scale to a double row.
+// bal[0] = 2^e multiplies K on the way in, bal[1] = 2^-e undoes it on the way out.
+template <int MAXN, int THREADS, int MODE>
+__global__ void __launch_bounds__(THREADS)
+row_fft_kernel(const int32_t* __restrict__ counts, const double* __restrict__ kern, cplx* z,
+               double* __restrict__ out, FftPlan P, const cplx* __restrict__ tw, double scale,
+               const double* __restrict__ bal) {
+    __shared__ cplx buf[MAXN];
+    const int n = P.n;
+    const int64_t off = (int64_t)blockIdx.x * n;
+    if (MODE == kFwdPack || MODE == kFwd) {
+        const double sk = MODE == kFwdPack ? bal[0] : 1.0;
+        for (int i = threadIdx.x; i < n; i += THREADS) {
+            const int p = digit_pos(i, P);
+            if (MODE == kFwdPack) buf[p] = cplx{(double)counts[off + i], kern[off + i] * sk};
+            else buf[p] = z[off + i];
+        }
+        __syncthreads();
+        dit(buf, P, 1, tw, false);
+        for (int i = threadIdx.x; i < n; i += THREADS) z[off + i] = buf[i];
+    } else {
+        for (int i = threadIdx.x; i < n; i += THREADS) buf[i] = z[off + i];
+        __syncthreads();
+        dif(buf, P, 1, tw, true);
+        const double su = MODE == kInvOut ? bal[1] : 1.0;
+        for (int i = threadIdx.x; i < n; i += THREADS) {
+            const cplx v = buf[digit_pos(i, P)];
+            if (MODE == kInvOut) out[off + i] = (v.x * scale) * su;
+            else z[off + i] = v;
+        }
+    }
+}
+
+// Balance of the two-for-one transform. Recovering F(K) from Z = M + iK
+// subtracts terms of the size of F(M), so K's spectrum would carry rounding
+// errors of M's magnitude; packing Z = M + i 2^e K with 2^e close to
+// ||M||_2 / ||K||_2 makes both spectra equally precise, and the power of two
+// is undone exactly at the end. The norms are reduced in a fixed order
+// (kNormBlocks partial sums, then one workgroup), so the result is reproducible.
+constexpr int kNormBlocks = 1024;
+
+__global__ void __launch_bounds__(256) norms_kernel(const int32_t* __restrict__ m,
+                                                    const double* __restrict__ k, int64_t n,
+                                                    double* __restrict__ part) {
+    __shared__ double sm[256], sk[256];
+    double am = 0.0, ak = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)kNormBlocks * 256) {
+        const double a = (double)m[i], b = k[i];
+        am += a * a;
+        ak += b * b;
+    }
+    sm[threadIdx.x] = am;
+    sk[threadIdx.x] = ak;
     __syncthreads();
-    for (int half = 1; half < n; half <<= 1) {
-        const int stride = n / (2 * half);
-        for (int b = threadIdx.x; b < n / 2; b += blockDim.x) {
-            const int j = b & (half - 1);
-            const int i0 = ((b - j) << 1) + j;
-            const int i1 = i0 + half;
-            cplx w = tw[j * stride];
-            if (inverse) w.y = -w.y;
-            const cplx t = cmul(w, buf[i1]);
-            const cplx a = buf[i0];
-            buf[i0] = cplx{a.x + t.x, a.y + t.y};
-            buf[i1] = cplx{a.x - t.x, a.y - t.y};
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sm[threadIdx.x] += sm[threadIdx.x + w];
+            sk[threadIdx.x] += sk[threadIdx.x + w];
         }
         __syncthreads();
     }
-    for (int i = threadIdx.x; i < n; i += blockDim.x) row[i] = buf[i];
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = sm[0];
+        part[2 * blockIdx.x + 1] = sk[0];
+    }
+}
+
+__global__ void __launch_bounds__(256) balance_kernel(const double* __restrict__ part,
+                                                      double* __restrict__ bal) {
+    __shared__ double sm[256], sk[256];
+    double am = 0.0, ak = 0.0;
+    for (int b = threadIdx.x; b < kNormBlocks; b += 256) {
+        am += part[2 * b];
+        ak += part[2 * b + 1];
+    }
+    sm[threadIdx.x] = am;
+    sk[threadIdx.x] = ak;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sm[threadIdx.x] += sm[threadIdx.x + w];
+            sk[threadIdx.x] += sk[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        int e = 0;
+        if (sm[0] > 0.0 && sk[0] > 0.0 && isfinite(sm[0]) && isfinite(sk[0])) {
+            e = (int)rint(0.5 * (log2(sm[0]) - log2(sk[0])));
+            e = e < -900 ? -900 : (e > 900 ? 900 : e);
+        }
+        bal[0] = ldexp(1.0, e);
+        bal[1] = ldexp(1.0, -e);
+    }
+}
+
+// F(M)(u) F(K)(u) from Z-hat(u) and Z-hat(-u) of Z = M + iK.
+__device__ __forceinline__ cplx spectrum_product(cplx zu, cplx zm) {
+    const cplx fm = cplx{0.5 * (zu.x + zm.x), 0.5 * (zu.y - zm.y)};   // (zu + conj zm) / 2
+    const cplx dk = cplx{zu.x - zm.x, zu.y + zm.y};                    // zu - conj zm
+    const cplx fk = cplx{0.5 * dk.y, -0.5 * dk.x};                     // dk / 2i
+    return cmul(fm, fk);
+}
+
+// Second axis, product and first inverse axis in one pass. t holds p1 rows of
+// length n2 = P.n (entry (u1, x2) after the first forward axis); workgroup u1
+// takes rows u1 and (p1 - u1) mod p1, whose spectra pair up under u -> -u:
+// forward DIT both, form the product of the two real signals' spectra, inverse
+// DIF both, store natural order.
+template <int MAXN, int THREADS>
+__global__ void __launch_bounds__(THREADS)
+pair_kernel(cplx* __restrict__ t, int p1, FftPlan P, const cplx* __restrict__ tw) {
+    __shared__ cplx buf[2 * MAXN];
+    const int n = P.n;
+    const int ua = blockIdx.x, ub = (p1 - ua) % p1;
+    const bool self = ua == ub;
+    const int rows = self ? 1 : 2;
+    cplx* A = buf;
+    cplx* B = buf + n;
+    for (int i = threadIdx.x; i < rows * n; i += THREADS) {
+        const int r = i >= n, k = i - r * n;
+        buf[r * n + digit_pos(k, P)] = t[(int64_t)(r ? ub : ua) * n + k];
+    }
+    __syncthreads();
+    dit(buf, P, rows, tw, false);
+    for (int u = threadIdx.x; u < n; u += THREADS) {
+        const int m = (n - u) % n;
+        if (self) {
+            if (m < u) continue;
+            const cplx pr = spectrum_product(A[u], A[m]);
+            A[u] = pr;
+            if (m != u) A[m] = conj(pr);
+        } else {
+            const cplx pr = spectrum_product(A[u], B[m]);
+            A[u] = pr;
+            B[m] = conj(pr);
+        }
+    }
+    __syncthreads();
+    dif(buf, P, rows, tw, true);
+    for (int i = threadIdx.x; i < rows * n; i += THREADS) {
+        const int r = i >= n, k = i - r * n;
+        t[(int64_t)(r ? ub : ua) * n + k] = buf[r * n + digit_pos(k, P)];
+    }
 }
 
 // out (cols x rows) = transpose of in (rows x cols), 32 x 32 tiles via LDS.
@@ -88,8 +384,8 @@ __global__ void __launch_bounds__(256) transpose_kernel(const cplx* __restrict__
     }
 }
 
-// Spectrum product in the transposed layout t (n1 rows of length n2, entry
-// (u1, u2) = Z-hat(u2, u1)): each pair (u, -u) is handled by one thread.
+// Product on whole planes (used when a row pair does not fit LDS): t in the
+// transposed layout (p1 rows of length n2), pairs (u, -u) by one thread.
 __global__ void product_kernel(cplx* __restrict__ t, int n1, int n2) {
     const int64_t total = (int64_t)n1 * n2;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
@@ -97,22 +393,10 @@ __global__ void product_kernel(cplx* __restrict__ t, int n1, int n2) {
         const int u1 = (int)(i / n2), u2 = (int)(i % n2);
         const int64_t p = (int64_t)((n1 - u1) % n1) * n2 + (n2 - u2) % n2;
         if (p < i) continue;
-        const cplx zu = t[i], zm = t[p];
-        // F(M)[u] = (zu + conj zm) / 2, F(K)[u] = (zu - conj zm) / (2i)
-        const cplx fm = cplx{0.5 * (zu.x + zm.x), 0.5 * (zu.y - zm.y)};
-        const cplx dk = cplx{zu.x - zm.x, zu.y + zm.y};
-        const cplx fk = cplx{0.5 * dk.y, -0.5 * dk.x};
-        const cplx prod = cmul(fm, fk);
+        const cplx prod = spectrum_product(t[i], t[p]);
         t[i] = prod;
-        if (p != i) t[p] = cplx{prod.x, -prod.y};
+        if (p != i) t[p] = conj(prod);
     }
-}
-
-__global__ void output_kernel(const cplx* __restrict__ z, int64_t n, double scale,
-                              double* __restrict__ out) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        out[i] = z[i].x * scale;
 }
 
 // ----------------------------------------------------------------------------
@@ -191,15 +475,31 @@ int grid_of(int64_t n, int cap) {
     return (int)(g < 1 ? 1 : (g > cap ? cap : g));
 }
 
-int log2i(int n) {
-    int l = 0;
-    while ((1 << l) < n) ++l;
-    return l;
+// LDS size classes: rows up to 1024 / 4096 / 10240 points (16 / 64 / 160 KiB),
+// row pairs up to 512 / 2048 / 5120 points.
+template <int MODE>
+hipError_t rows(const int32_t* counts, const double* kern, cplx* z, double* out, int nrows,
+                const FftPlan& P, const cplx* tw, double scale, const double* bal, hipStream_t s) {
+    if (P.n <= 1024)
+        hipLaunchKernelGGL((row_fft_kernel<1024, 256, MODE>), dim3(nrows), dim3(256), 0, s, counts, kern,
+                           z, out, P, tw, scale, bal);
+    else if (P.n <= 4096)
+        hipLaunchKernelGGL((row_fft_kernel<4096, 512, MODE>), dim3(nrows), dim3(512), 0, s, counts, kern,
+                           z, out, P, tw, scale, bal);
+    else
+        hipLaunchKernelGGL((row_fft_kernel<kMaxFftSide, 1024, MODE>), dim3(nrows), dim3(1024), 0, s,
+                           counts, kern, z, out, P, tw, scale, bal);
+    return hipGetLastError();
 }
 
-hipError_t fft_rows(cplx* z, int rows, int n, const cplx* tw, bool inverse, hipStream_t s) {
-    hipLaunchKernelGGL(fft_rows_kernel, dim3(rows), dim3(256), (size_t)n * sizeof(cplx), s, z, n,
-                       log2i(n), tw, inverse ? 1 : 0);
+hipError_t pairs(cplx* t, int p1, const FftPlan& P, const cplx* tw, hipStream_t s) {
+    const dim3 grid(p1 / 2 + 1);
+    if (P.n <= 512)
+        hipLaunchKernelGGL((pair_kernel<512, 256>), grid, dim3(256), 0, s, t, p1, P, tw);
+    else if (P.n <= 2048)
+        hipLaunchKernelGGL((pair_kernel<2048, 512>), grid, dim3(512), 0, s, t, p1, P, tw);
+    else
+        hipLaunchKernelGGL((pair_kernel<kMaxFftSide / 2, 1024>), grid, dim3(1024), 0, s, t, p1, P, tw);
     return hipGetLastError();
 }
 
@@ -211,33 +511,50 @@ hipError_t transpose(const cplx* in, cplx* out, int rows, int cols, hipStream_t 
 
 }  // namespace
 
+bool fft_side_supported(int n) {
+    FftPlan P;
+    return n >= 2 && n <= kMaxFftSide && make_plan(n, &P);
+}
+
 size_t convolve_scratch_bytes(int p1, int p2) {
     const size_t plane = (size_t)p1 * p2 * sizeof(cplx);
-    return 2 * plane + (size_t)(p1 / 2 + p2 / 2 + 2) * sizeof(cplx) + 256;
+    return 2 * plane + (size_t)(p1 + p2) * sizeof(cplx) + (2 * kNormBlocks + 2) * sizeof(double) + 256;
 }
 
 hipError_t launch_convolve(const int32_t* counts, const double* kernel, int p1, int p2, double n_avg,
                            double* out, void* scratch, hipStream_t s) {
+    FftPlan P1, P2;
+    if (!make_plan(p1, &P1) || !make_plan(p2, &P2) || p1 > kMaxFftSide || p2 > kMaxFftSide)
+        return hipErrorInvalidValue;
     const int64_t n = (int64_t)p1 * p2;
     cplx* z = static_cast<cplx*>(scratch);              // p2 x p1
     cplx* t = z + n;                                    // p1 x p2
-    cplx* tw1 = t + n;                                  // p1 / 2 twiddles
-    cplx* tw2 = tw1 + (p1 / 2 > 0 ? p1 / 2 : 1);        // p2 / 2 twiddles
-    hipLaunchKernelGGL(twiddle_kernel, dim3((p1 / 2 + 255) / 256 + 1), dim3(256), 0, s, tw1, p1);
-    hipLaunchKernelGGL(twiddle_kernel, dim3((p2 / 2 + 255) / 256 + 1), dim3(256), 0, s, tw2, p2);
-    hipLaunchKernelGGL(pack_kernel, dim3(grid_of(n, 8192)), dim3(256), 0, s, counts, kernel, n, z);
-    hipError_t e = fft_rows(z, p2, p1, tw1, false, s);           // along x1
-    if (e == hipSuccess) e = transpose(z, t, p2, p1, s);         // t: p1 x p2
-    if (e == hipSuccess) e = fft_rows(t, p1, p2, tw2, false, s); // along x2
+    cplx* tw1 = t + n;                                  // p1 twiddles
+    cplx* tw2 = tw1 + p1;                               // p2 twiddles
+    double* part = reinterpret_cast<double*>(tw2 + p2); // kNormBlocks x {|M|^2, |K|^2}
+    double* bal = part + 2 * kNormBlocks;               // {2^e, 2^-e}
+    hipLaunchKernelGGL(twiddle_kernel, dim3((p1 + 255) / 256), dim3(256), 0, s, tw1, p1);
+    hipLaunchKernelGGL(twiddle_kernel, dim3((p2 + 255) / 256), dim3(256), 0, s, tw2, p2);
+    hipLaunchKernelGGL(norms_kernel, dim3(kNormBlocks), dim3(256), 0, s, counts, kernel, n, part);
+    hipLaunchKernelGGL(balance_kernel, dim3(1), dim3(256), 0, s, part, bal);
+    // forward along x1 (rows of the map), Z = M + i 2^e K packed on the way in
+    hipError_t e = rows<kFwdPack>(counts, kernel, z, nullptr, p2, P1, tw1, 1.0, bal, s);
+    if (e == hipSuccess) e = transpose(z, t, p2, p1, s);            // t: p1 x p2
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(product_kernel, dim3(grid_of(n, 8192)), dim3(256), 0, s, t, p1, p2);
-    e = fft_rows(t, p1, p2, tw2, true, s);
-    if (e == hipSuccess) e = transpose(t, z, p1, p2, s);
-    if (e == hipSuccess) e = fft_rows(z, p2, p1, tw1, true, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(output_kernel, dim3(grid_of(n, 8192)), dim3(256), 0, s, z, n,
-                       1.0 / ((double)n * n_avg), out);
-    return hipGetLastError();
+    if (p2 <= kMaxFftSide / 2) {
+        e = pairs(t, p1, P2, tw2, s);                               // x2 forward, product, x2 inverse
+    } else {
+        e = rows<kFwd>(nullptr, nullptr, t, nullptr, p1, P2, tw2, 1.0, bal, s);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(product_kernel, dim3(grid_of(n, 8192)), dim3(256), 0, s, t, p1, p2);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = rows<kInv>(nullptr, nullptr, t, nullptr, p1, P2, tw2, 1.0, bal, s);
+    }
+    if (e == hipSuccess) e = transpose(t, z, p1, p2, s);            // z: p2 x p1
+    if (e == hipSuccess)
+        e = rows<kInvOut>(nullptr, nullptr, z, out, p2, P1, tw1, 1.0 / ((double)n * n_avg), bal, s);
+    return e;
 }
 
 size_t source_scratch_bytes(int h1, int h2) {

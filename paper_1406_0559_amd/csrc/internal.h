@@ -115,7 +115,9 @@ hipError_t launch_codec_unpack(const uint32_t* packed, int64_t n_pix, int bits, 
 bool shape_supported(Precision prec, const KernelShape& ks);
 size_t shoot_lds_bytes(Precision prec, bool masses, const KernelShape& ks);
 
-// Finite-source convolution (convolve.hip). p1, p2 powers of two in [2, 4096].
+// Finite-source convolution (convolve.hip). Sides: products of 2, 3 and 5 in
+// [2, kMaxFftSide].
+bool fft_side_supported(int n);
 size_t convolve_scratch_bytes(int p1, int p2);
 hipError_t launch_convolve(const int32_t* counts, const double* kernel, int p1, int p2, double n_avg,
                            double* out, void* scratch, hipStream_t stream);
@@ -123,6 +125,6 @@ size_t source_scratch_bytes(int h1, int h2);
 hipError_t launch_source_kernel(int shape, double radius, double hole, double pix1, double pix2,
                                 int h1, int h2, int p1, int p2, double* kernel, double* scratch,
                                 hipStream_t stream);
-constexpr int kMaxFftSide = 4096;
+constexpr int kMaxFftSide = 10240;
 
 }  // namespace rl

@@ -220,8 +220,10 @@ def test_convolution_entry_points_validate_on_the_host():
         for prof in (rl.rl_profile(5, 0.1, 0.0), rl.rl_profile(0, -0.1, 0.0), rl.rl_profile(0, 0.1, -1.0),
                      rl.rl_profile(1, math.nan, 0.0), rl.rl_profile(0, 5.0, 0.0)):
             assert lib.rl_source_kernel(ctx, C.byref(prof), C.byref(w), fake, None) == rl.RL_E_INVALID
-        for ww in (rl.rl_window(48, 64, 0.0, 0.0, 2.0, 2.0), rl.rl_window(8192, 2, 0.0, 0.0, 2.0, 2.0),
-                   rl.rl_window(1, 64, 0.0, 0.0, 2.0, 2.0)):
+        # sides must be products of 2, 3 and 5 in [2, 10240]
+        for ww in (rl.rl_window(49, 64, 0.0, 0.0, 2.0, 2.0), rl.rl_window(64, 7, 0.0, 0.0, 2.0, 2.0),
+                   rl.rl_window(10368, 2, 0.0, 0.0, 2.0, 2.0), rl.rl_window(1, 64, 0.0, 0.0, 2.0, 2.0),
+                   rl.rl_window(2 * 5003, 64, 0.0, 0.0, 2.0, 2.0)):
             assert lib.rl_convolve(ctx, fake, fake, C.byref(ww), 1.0, fake, None) == rl.RL_E_INVALID
         assert lib.rl_convolve(ctx, fake, fake, C.byref(w), 0.0, fake, None) == rl.RL_E_INVALID
         assert lib.rl_convolve(ctx, fake, None, C.byref(w), 1.0, fake, None) == rl.RL_E_INVALID

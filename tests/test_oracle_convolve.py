@@ -67,3 +67,12 @@ def test_invalid():
         cv.source_kernel("uniform", 16, 16, 1.0, 1.0, 10.0)
     with pytest.raises(ValueError):
         cv.brightness("cone", 1.0, 2.0)
+
+
+def test_convolve_at_agrees_with_the_direct_sum():
+    rng = np.random.default_rng(8)
+    M = rng.integers(0, 100, size=(24, 36)).astype(np.int32)
+    K = cv.source_kernel("power", 36, 24, 0.1, 0.1, 0.35, 0.05)
+    full = cv.convolve_direct(M, K, 2.0)
+    pts = [(0, 0), (23, 35), (5, 30), (12, 0)]
+    assert np.allclose(cv.convolve_at(M, K, pts, 2.0), [full[j, i] for j, i in pts], rtol=1e-14)
