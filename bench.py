@@ -54,9 +54,12 @@ def parse():
 
 
 def kernel_source_hash():
+    """sha256 over the shoot kernel's sources (shoot.hip, then internal.h)."""
     import hashlib
-    path = os.path.join(ROOT, "paper_1406_0559_amd", "csrc", "kernels.hip")
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+    h = hashlib.sha256()
+    for name in ("shoot.hip", "internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_1406_0559_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
 
 
 def measured_traffic(workload):
@@ -72,7 +75,7 @@ def measured_traffic(workload):
         if line.startswith("- ") and ":" in line:
             k, v = line[2:].split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
-    if vals.get("kernels.hip sha256") != kernel_source_hash():
+    if vals.get("shoot kernel sources sha256") != kernel_source_hash():
         return None
     fetch = float(vals["fetch bytes per launch"])
     write = float(vals["write bytes per launch"])

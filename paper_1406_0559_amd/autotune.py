@@ -34,7 +34,7 @@ def candidates(precision: str):
     """Binning always goes through the LDS sub-map here: global-only binning
     is within a per cent in time but moves ~20x more bytes to memory (one
     device-scope atomic per binned ray instead of one per touched pixel)."""
-    rays = [(4, 4), (2, 8), (8, 2)] if precision == "fp32c" else [(4, 4)]
+    rays = [(4, 4), (2, 8), (8, 2), (4, 8), (8, 4)] if precision == "fp32c" else [(4, 4)]
     for (rx, ry), tile, waves, sub in itertools.product(rays, (128, 256, 512, 1024), (1, 2, 4),
                                                        (1, 2)):
         yield dict(rays_x=rx, rays_y=ry, lens_tile=tile, waves=waves, submap=sub)

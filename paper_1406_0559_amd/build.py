@@ -25,7 +25,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall",
           "-I", INCLUDE, "-I", CSRC]
 DEVICE = ["-x", "hip", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = [("kernels.hip", True), ("convolve.hip", True), ("api.cpp", True)]
+SOURCES = [("shoot.hip", True), ("maps.hip", True), ("convolve.hip", True), ("api.cpp", True)]
 
 
 def _compile(src, device, verbose):

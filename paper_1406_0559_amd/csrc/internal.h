@@ -1,4 +1,5 @@
-// Internal declarations shared by the kernels (kernels.hip) and the C-ABI
+// Internal declarations shared by the kernels (shoot.hip, maps.hip,
+// convolve.hip) and the C-ABI
 // layer (api.cpp) of the raylens library. Not part of the public interface.
 #pragma once
 
@@ -63,14 +64,15 @@ struct WorkItem {
 };
 
 struct KernelShape {
-    int32_t rays_x, rays_y;    // rays per lane along x1 / x2 (product 16)
+    int32_t rays_x, rays_y;    // rays per lane along x1 / x2 (product 16; 32 = two cells per wave)
     int32_t lens_tile;         // lenses per LDS pass (multiple of kBlock)
     int32_t waves;             // waves per workgroup
     int32_t submap;            // 0 global atomics, 1 bounding-box LDS sub-map, 2 64x64 LDS window
     int32_t item_cells;        // cells per batch work item
 };
 
-// Launchers (kernels.hip). Each returns the hipError_t of the launch.
+// Launchers (shoot.hip; maps.hip from launch_count_hist on). Each returns the
+// hipError_t of the launch.
 hipError_t launch_prep_lenses(const double* x1, const double* x2, const double* m, int64_t n,
                               float4* out_xy, float* out_m, bool write_unit_mass,
                               hipStream_t stream);

@@ -1,0 +1,320 @@
+// HIP kernels for the statistics and storage of finished maps on gfx950:
+// count histograms, binned magnification probability distributions and
+// probability sums (Vernardos & Fluke 2014, Section 3.2.1 and Section 4), the
+// mean and spread of MPDs over lens realisations, and the indexed-map codec
+// (Appendix B). All are single passes over the int32 count map, bound by HBM
+// bandwidth; every decision that floating point takes is an FP64 comparison
+// made the same way as in a plain sequential evaluation.
+#include <climits>
+
+#include "internal.h"
+
+namespace rl {
+namespace {
+
+// ----------------------------------------------------------------------------
+// magnification probability distributions (Section 3.2.1 and Section 4)
+// ----------------------------------------------------------------------------
+
+constexpr int kHistLds = 8192;   // count values histogrammed in LDS per workgroup
+
+// Frequency of each count value; values >= n_values - 1 share the last entry.
+// Low values (where almost every pixel lies) go to an LDS copy first.
+__global__ void __launch_bounds__(256) count_hist_kernel(const int32_t* __restrict__ counts,
+                                                         int64_t n, int64_t n_values,
+                                                         unsigned long long* __restrict__ hist) {
+    __shared__ unsigned int sh[kHistLds];
+    const int nl = (int)(n_values < kHistLds ? n_values : kHistLds);
+    for (int e = threadIdx.x; e < nl; e += blockDim.x) sh[e] = 0;
+    __syncthreads();
+    const int64_t last = n_values - 1;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        int64_t c = counts[k];
+        c = c < 0 ? 0 : c;
+        const int64_t v = c < last ? c : last;
+        if (v < nl) atomicAdd(&sh[v], 1u);
+        else atomicAdd(&hist[v], 1ull);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nl; e += blockDim.x)
+        if (sh[e]) atomicAdd(&hist[e], (unsigned long long)sh[e]);
+}
+
+// Binned MPD: bin = number of count thresholds <= N (thresholds ascending), so
+// bin 0 is the underflow and bin nthr the overflow. Thresholds and bins in LDS.
+__global__ void __launch_bounds__(256) mpd_kernel(const int32_t* __restrict__ counts, int64_t n,
+                                                  const double* __restrict__ thr, int nthr,
+                                                  unsigned long long* __restrict__ bins) {
+    extern __shared__ __align__(16) char smem[];
+    double* st = reinterpret_cast<double*>(smem);
+    unsigned int* sb = reinterpret_cast<unsigned int*>(st + nthr);
+    for (int e = threadIdx.x; e < nthr; e += blockDim.x) st[e] = thr[e];
+    for (int e = threadIdx.x; e <= nthr; e += blockDim.x) sb[e] = 0;
+    __syncthreads();
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const double c = (double)counts[k];
+        int lo = 0, hi = nthr;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (st[mid] <= c) lo = mid + 1;
+            else hi = mid;
+        }
+        atomicAdd(&sb[lo], 1u);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e <= nthr; e += blockDim.x)
+        if (sb[e]) atomicAdd(&bins[e], (unsigned long long)sb[e]);
+}
+
+// Pixels with N / N_avg < mu_lim (one FP64 division each, as the definition).
+__global__ void __launch_bounds__(256) prob_sum_kernel(const int32_t* __restrict__ counts, int64_t n,
+                                                       double n_avg, double mu_lim,
+                                                       unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long part[4];
+    unsigned long long below = 0;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x)
+        below += ((double)counts[k] / n_avg < mu_lim) ? 1ull : 0ull;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) below += __shfl_xor(below, o);
+    if ((threadIdx.x % kLanes) == 0) part[threadIdx.x / kLanes] = below;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int i = 0; i < (int)(blockDim.x / kLanes); ++i) t += part[i];
+        atomicAdd(out, t);
+    }
+}
+
+// Mean and sample standard deviation over n_maps MPDs of one bin per thread,
+// in probabilities (bin count / n_pix).
+__global__ void mpd_moments_kernel(const unsigned long long* __restrict__ bins, int n_maps,
+                                   int n_bins, double n_pix, double* __restrict__ mean,
+                                   double* __restrict__ stdev) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n_bins) return;
+    double s = 0.0;
+    for (int r = 0; r < n_maps; ++r) s += (double)bins[(int64_t)r * n_bins + b] / n_pix;
+    const double m = s / (double)n_maps;
+    double v = 0.0;
+    for (int r = 0; r < n_maps; ++r) {
+        const double d = (double)bins[(int64_t)r * n_bins + b] / n_pix - m;
+        v += d * d;
+    }
+    mean[b] = m;
+    stdev[b] = n_maps > 1 ? sqrt(v / (double)(n_maps - 1)) : 0.0;
+}
+
+// ----------------------------------------------------------------------------
+// indexed-map codec (Appendix B)
+// ----------------------------------------------------------------------------
+
+constexpr int kScanPerBlock = 1024;   // elements per scan block (256 threads x 4)
+
+// flag[v] = 1 where value v occurs in the map
+__global__ void distinct_flag_kernel(const unsigned long long* __restrict__ hist, int64_t n,
+                                     int32_t* __restrict__ flag) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        flag[v] = hist[v] ? 1 : 0;
+}
+
+// Exclusive scan of a block of 256 x 4 int32 in LDS; returns the block total.
+__device__ int block_exclusive_scan_1024(int32_t (&v)[4], int* sh) {
+    const int t = threadIdx.x;
+    int local = v[0] + v[1] + v[2] + v[3];
+    sh[t] = local;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {       // Hillis-Steele over the 256 thread sums
+        const int add = t >= o ? sh[t - o] : 0;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    const int total = sh[255];
+    int run = sh[t] - local;                   // exclusive prefix of this thread
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { const int x = v[i]; v[i] = run; run += x; }
+    return total;
+}
+
+__global__ void __launch_bounds__(256) scan_block_sums_kernel(const int32_t* __restrict__ in, int64_t n,
+                                                              int32_t* __restrict__ sums) {
+    __shared__ int sh[256];
+    const int64_t base = (int64_t)blockIdx.x * kScanPerBlock + threadIdx.x * 4;
+    int32_t v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = base + i < n ? in[base + i] : 0;
+    const int total = block_exclusive_scan_1024(v, sh);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// One workgroup: exclusive scan of the block sums in place; *grand = total.
+__global__ void __launch_bounds__(256) scan_sums_kernel(int32_t* __restrict__ sums, int64_t nb,
+                                                        int64_t* __restrict__ grand) {
+    __shared__ int sh[256];
+    int64_t carry = 0;
+    for (int64_t c0 = 0; c0 < nb; c0 += kScanPerBlock) {
+        int32_t v[4];
+        const int64_t base = c0 + threadIdx.x * 4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = base + i < nb ? sums[base + i] : 0;
+        const int total = block_exclusive_scan_1024(v, sh);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (base + i < nb) sums[base + i] = (int32_t)(carry + v[i]);
+        carry += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *grand = carry;
+}
+
+__global__ void __launch_bounds__(256) scan_apply_kernel(const int32_t* __restrict__ in, int64_t n,
+                                                         const int32_t* __restrict__ offsets,
+                                                         int32_t* __restrict__ out) {
+    __shared__ int sh[256];
+    const int64_t base = (int64_t)blockIdx.x * kScanPerBlock + threadIdx.x * 4;
+    int32_t v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = base + i < n ? in[base + i] : 0;
+    block_exclusive_scan_1024(v, sh);
+    const int32_t off = offsets[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (base + i < n) out[base + i] = off + v[i];
+}
+
+// values[rank[v]] = v for every value present (ranks ascend with v).
+__global__ void scatter_values_kernel(const int32_t* __restrict__ flag,
+                                      const int32_t* __restrict__ rank, int64_t n,
+                                      int32_t* __restrict__ values) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += (int64_t)gridDim.x * blockDim.x)
+        if (flag[v]) values[rank[v]] = (int32_t)v;
+}
+
+// One output word per thread: gathers the indices of the pixels whose bits
+// fall into word w (bits [32w, 32w + 32), pixel p at bits [p b, p b + b),
+// least significant bit first). Stores are coalesced and need no atomics.
+__global__ void pack_kernel(const int32_t* __restrict__ counts, int64_t n_pix,
+                            const int32_t* __restrict__ rank, int64_t n_values, int bits,
+                            int64_t n_words, uint32_t* __restrict__ packed) {
+    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < n_words;
+         w += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t lo_bit = w * 32;
+        const int64_t p0 = lo_bit / bits;
+        int64_t p1 = (lo_bit + 31) / bits;
+        if (p1 > n_pix - 1) p1 = n_pix - 1;
+        unsigned long long word = 0;
+        for (int64_t p = p0; p <= p1; ++p) {
+            const int32_t c = counts[p];
+            const unsigned long long idx =
+                (c >= 0 && c < n_values) ? (unsigned long long)(uint32_t)rank[c] : 0ull;
+            const int64_t start = p * bits;
+            if (start >= lo_bit) word |= idx << (start - lo_bit);        // shift < 32
+            else word |= idx >> (lo_bit - start);                        // shift < bits <= 32
+        }
+        packed[w] = (uint32_t)word;
+    }
+}
+
+// Inverse of pack_kernel; an index past the table (a stream not produced by
+// the encoder) decodes to -1 instead of reading out of bounds.
+__global__ void unpack_kernel(const uint32_t* __restrict__ packed, int64_t n_pix, int bits,
+                              const int32_t* __restrict__ values, int64_t n_values,
+                              int32_t* __restrict__ counts) {
+    const unsigned long long mask = bits >= 32 ? 0xFFFFFFFFull : ((1ull << bits) - 1ull);
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n_pix;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t start = p * bits;
+        const int64_t w = start >> 5;
+        const int off = (int)(start & 31);
+        unsigned long long v = (unsigned long long)packed[w] >> off;
+        if (off + bits > 32) v |= (unsigned long long)packed[w + 1] << (32 - off);
+        const unsigned long long idx = v & mask;
+        counts[p] = idx < (unsigned long long)n_values ? values[idx] : -1;
+    }
+}
+
+int grid_for(int64_t n, int threads, int cap) {
+    int64_t g = (n + threads - 1) / threads;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_count_hist(const int32_t* counts, int64_t n, int64_t n_values,
+                             unsigned long long* hist, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(count_hist_kernel, dim3(grid_for(n, 256 * 16, 2048)), dim3(256), 0, s, counts,
+                       n, n_values, hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_mpd(const int32_t* counts, int64_t n, const double* thr, int nthr,
+                      unsigned long long* bins, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const size_t lds = (size_t)nthr * sizeof(double) + (size_t)(nthr + 1) * sizeof(unsigned int);
+    hipLaunchKernelGGL(mpd_kernel, dim3(grid_for(n, 256 * 16, 2048)), dim3(256), lds, s, counts, n,
+                       thr, nthr, bins);
+    return hipGetLastError();
+}
+
+hipError_t launch_prob_sum(const int32_t* counts, int64_t n, double n_avg, double mu_lim,
+                           unsigned long long* out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(prob_sum_kernel, dim3(grid_for(n, 256 * 16, 2048)), dim3(256), 0, s, counts, n,
+                       n_avg, mu_lim, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_mpd_moments(const unsigned long long* bins, int n_maps, int n_bins, double n_pix,
+                              double* mean, double* stdev, hipStream_t s) {
+    if (n_bins <= 0) return hipSuccess;
+    hipLaunchKernelGGL(mpd_moments_kernel, dim3((n_bins + 255) / 256), dim3(256), 0, s, bins, n_maps,
+                       n_bins, n_pix, mean, stdev);
+    return hipGetLastError();
+}
+
+int64_t scan_blocks(int64_t n) { return (n + kScanPerBlock - 1) / kScanPerBlock; }
+
+hipError_t launch_distinct_ranks(const unsigned long long* hist, int64_t n_values, int32_t* flag,
+                                 int32_t* rank, int32_t* block_sums, int64_t* total,
+                                 hipStream_t s) {
+    if (n_values <= 0) return hipSuccess;
+    const int64_t nb = scan_blocks(n_values);
+    hipLaunchKernelGGL(distinct_flag_kernel, dim3(grid_for(n_values, 256, 8192)), dim3(256), 0, s, hist,
+                       n_values, flag);
+    hipLaunchKernelGGL(scan_block_sums_kernel, dim3((unsigned)nb), dim3(256), 0, s, flag, n_values,
+                       block_sums);
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(256), 0, s, block_sums, nb, total);
+    hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nb), dim3(256), 0, s, flag, n_values,
+                       block_sums, rank);
+    return hipGetLastError();
+}
+
+hipError_t launch_codec_pack(const int32_t* counts, int64_t n_pix, const int32_t* flag,
+                             const int32_t* rank, int64_t n_values, int bits, int32_t* values,
+                             uint32_t* packed, hipStream_t s) {
+    const int64_t n_words = (n_pix * bits + 31) / 32;
+    hipLaunchKernelGGL(scatter_values_kernel, dim3(grid_for(n_values, 256, 8192)), dim3(256), 0, s, flag,
+                       rank, n_values, values);
+    hipLaunchKernelGGL(pack_kernel, dim3(grid_for(n_words, 256, 16384)), dim3(256), 0, s, counts, n_pix,
+                       rank, n_values, bits, n_words, packed);
+    return hipGetLastError();
+}
+
+hipError_t launch_codec_unpack(const uint32_t* packed, int64_t n_pix, int bits, const int32_t* values,
+                               int64_t n_values, int32_t* counts, hipStream_t s) {
+    if (n_pix <= 0) return hipSuccess;
+    hipLaunchKernelGGL(unpack_kernel, dim3(grid_for(n_pix, 256, 16384)), dim3(256), 0, s, packed, n_pix,
+                       bits, values, n_values, counts);
+    return hipGetLastError();
+}
+
+}  // namespace rl

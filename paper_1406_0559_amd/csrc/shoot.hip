@@ -8,7 +8,8 @@
 //   * A "cell" is a fixed 1024-ray tile of the ray grid (cx x cy rays, shape
 //     chosen from the grid spacing so it is roughly square on the sky). One
 //     wave of 64 lanes processes one cell, each lane holding a KX x KY block
-//     of rays in registers. Rays of a lane share their x1 (per column) and
+//     of 16 rays in registers, or two cells, each on half of the lanes with
+//     32 rays per lane (fewer per-lens differences per ray, more registers). Rays of a lane share their x1 (per column) and
 //     x2 (per row) offsets, so per lens a lane computes KX + KY differences
 //     and then one fma + one v_rcp_f32 + two fma per ray.
 //   * Lenses are staged per wave into LDS in tiles and read back as
@@ -86,60 +87,115 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
 // deflection sums
 // ----------------------------------------------------------------------------
 
+// Differences of the lane's rays to lens k: dx per column, dy and dy^2 per row,
+// and the mass-weighted numerators.
+template <int KX, int KY, bool MASS>
+struct LensTerms {
+    float dx[KX], wx[KX], dy2[KY], wy[KY];
+
+    __device__ __forceinline__ LensTerms(const float* __restrict__ wl, int k, const float (&ox)[KX],
+                                         const float (&oy)[KY]) {
+        float lx, ly, lm = 1.0f;
+        if constexpr (MASS) {
+            const float4 v = reinterpret_cast<const float4*>(wl)[k];
+            lx = v.x; ly = v.y; lm = v.z;
+        } else {
+            const float2 v = reinterpret_cast<const float2*>(wl)[k];
+            lx = v.x; ly = v.y;
+        }
+#pragma unroll
+        for (int a = 0; a < KX; ++a) {
+            dx[a] = ox[a] - lx;
+            wx[a] = MASS ? lm * dx[a] : dx[a];
+        }
+#pragma unroll
+        for (int b = 0; b < KY; ++b) {
+            const float d = oy[b] - ly;
+            dy2[b] = d * d;
+            wy[b] = MASS ? lm * d : d;
+        }
+    }
+};
+
+// One lens against the lane's rays. Rays come in pairs (same column, grid rows
+// 2m and 2m + 1; KY is even and cells start on even rows, so the pair is a
+// property of the ray grid, not of the kernel shape). Both reciprocals of a
+// pair come from one v_rcp_f32: q = 1 / (r2_a r2_b), 1 / r2_a = r2_b q,
+// 1 / r2_b = r2_a q (3 multiplies replace a reciprocal, which issues at about a
+// third of the plain FP32 rate). A product that underflows to zero (a ray on
+// a lens) makes the pair's block sums non-finite; deflect_f32 then redoes that
+// pair's block with one reciprocal per ray (lens_step_f32_single).
+// Phase-ordered in groups of up to 16 rays: all r^2, then all reciprocals,
+// then all accumulations, so no v_rcp_f32 result is consumed right after it
+// issues.
 template <int KX, int KY, bool MASS>
 __device__ __forceinline__ void lens_step_f32(const float* __restrict__ wl, int k,
                                               const float (&ox)[KX], const float (&oy)[KY],
                                               float (&p1)[KX * KY], float (&p2)[KX * KY]) {
-    float lx, ly, lm = 1.0f;
-    if constexpr (MASS) {
-        const float4 v = reinterpret_cast<const float4*>(wl)[k];
-        lx = v.x; ly = v.y; lm = v.z;
-    } else {
-        const float2 v = reinterpret_cast<const float2*>(wl)[k];
-        lx = v.x; ly = v.y;
+    static_assert(KY % 2 == 0, "rays are paired along x2");
+    constexpr int R = KX * KY;
+    constexpr int G = R > 16 ? 16 : R;
+    const LensTerms<KX, KY, MASS> T(wl, k, ox, oy);
+#pragma unroll
+    for (int g0 = 0; g0 < R; g0 += G) {
+        float r2[G], q[G / 2];
+#pragma unroll
+        for (int t = 0; t < G; ++t) {
+            const int r = g0 + t, a = r / KY, b = r % KY;
+            r2[t] = __builtin_fmaf(T.dx[a], T.dx[a], T.dy2[b]);
+        }
+#pragma unroll
+        for (int u = 0; u < G / 2; ++u) q[u] = r2[2 * u] * r2[2 * u + 1];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < G / 2; ++u) q[u] = __builtin_amdgcn_rcpf(q[u]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < G / 2; ++u) {
+            const int r = g0 + 2 * u, a = r / KY, b = r % KY;
+            const float ia = r2[2 * u + 1] * q[u];
+            const float ib = r2[2 * u] * q[u];
+            p1[r] = __builtin_fmaf(T.wx[a], ia, p1[r]);
+            p2[r] = __builtin_fmaf(T.wy[b], ia, p2[r]);
+            p1[r + 1] = __builtin_fmaf(T.wx[a], ib, p1[r + 1]);
+            p2[r + 1] = __builtin_fmaf(T.wy[b + 1], ib, p2[r + 1]);
+        }
     }
-    float dx[KX], wx[KX], dy[KY], dy2[KY], wy[KY];
+}
+
+// One reciprocal per ray, applied only to the pairs flagged in `redo` (bit u
+// = rays 2u and 2u + 1).
+template <int KX, int KY, bool MASS>
+__device__ __forceinline__ void lens_step_f32_single(const float* __restrict__ wl, int k,
+                                                     const float (&ox)[KX], const float (&oy)[KY],
+                                                     float (&p1)[KX * KY], float (&p2)[KX * KY],
+                                                     unsigned redo) {
+    constexpr int R = KX * KY;
+    const LensTerms<KX, KY, MASS> T(wl, k, ox, oy);
 #pragma unroll
-    for (int a = 0; a < KX; ++a) {
-        dx[a] = ox[a] - lx;
-        wx[a] = MASS ? lm * dx[a] : dx[a];
-    }
-#pragma unroll
-    for (int b = 0; b < KY; ++b) {
-        dy[b] = oy[b] - ly;
-        dy2[b] = dy[b] * dy[b];
-        wy[b] = MASS ? lm * dy[b] : dy[b];
-    }
-    // Phase-ordered: all r^2, then all reciprocals, then all accumulations, so
-    // no v_rcp_f32 result is consumed right after it issues.
-    float inv[KX * KY];
-#pragma unroll
-    for (int a = 0; a < KX; ++a)
-#pragma unroll
-        for (int b = 0; b < KY; ++b) inv[a * KY + b] = __builtin_fmaf(dx[a], dx[a], dy2[b]);
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int r = 0; r < KX * KY; ++r) inv[r] = __builtin_amdgcn_rcpf(inv[r]);
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int a = 0; a < KX; ++a) {
-#pragma unroll
-        for (int b = 0; b < KY; ++b) {
-            p1[a * KY + b] = __builtin_fmaf(wx[a], inv[a * KY + b], p1[a * KY + b]);
-            p2[a * KY + b] = __builtin_fmaf(wy[b], inv[a * KY + b], p2[a * KY + b]);
+    for (int r = 0; r < R; ++r) {
+        const int a = r / KY, b = r % KY;
+        const float inv = __builtin_amdgcn_rcpf(__builtin_fmaf(T.dx[a], T.dx[a], T.dy2[b]));
+        if ((redo >> (r / 2)) & 1u) {
+            p1[r] = __builtin_fmaf(T.wx[a], inv, p1[r]);
+            p2[r] = __builtin_fmaf(T.wy[b], inv, p2[r]);
         }
     }
 }
 
 // FP32-compensated deflection of the cell's rays; alpha returned in FP64 as
-// sum + compensation.
-template <int KX, int KY, bool MASS>
-__device__ __forceinline__ void deflect_f32(const MapParams& P, int64_t i0, int64_t j0, int lane,
-                                            int L, float* __restrict__ wl,
+// sum + compensation. With CPW cells per wave, each cell is handled by
+// kLanes / CPW lanes (cl = lane within the cell) and has its own rebased copy
+// of the lens tile at wl + half * L entries.
+template <int KX, int KY, bool MASS, int CPW>
+__device__ __forceinline__ void deflect_f32(const MapParams& P, int64_t i0, int64_t j0, int cl,
+                                            int half, int L, float* __restrict__ wl,
                                             double (&al1)[KX * KY], double (&al2)[KX * KY]) {
     constexpr int R = KX * KY;
+    constexpr int LPC = kLanes / CPW;
     const int lanes_x = P.cx / KX;
-    const int lxi = lane % lanes_x, lyi = lane / lanes_x;
+    const int lxi = cl % lanes_x, lyi = cl / lanes_x;
+    float* __restrict__ wh = wl + (size_t)half * L * (MASS ? 4 : 2);
     // cell centre (a grid line between rays): C = base + (i0 + cx/2) d
     const double C1 = P.base1 + (double)(i0 + P.cx / 2) * P.d1;
     const double C2 = P.base2 + (double)(j0 + P.cy / 2) * P.d2;
@@ -159,24 +215,41 @@ __device__ __forceinline__ void deflect_f32(const MapParams& P, int64_t i0, int6
     const int64_t n = P.n_lens;
     for (int64_t t0 = 0; t0 < n; t0 += L) {
         const int cnt = (int)((n - t0) < (int64_t)L ? (n - t0) : (int64_t)L);
-        for (int q = lane; q < cnt; q += kLanes) {
+        for (int q = cl; q < cnt; q += LPC) {
             const float4 h = P.lens32[t0 + q];
             const float r1 = rebase(h.x, h.y, C1h, C1l);
             const float r2 = rebase(h.z, h.w, C2h, C2l);
             if constexpr (MASS) {
-                reinterpret_cast<float4*>(wl)[q] = make_float4(r1, r2, P.mass32[t0 + q], 0.0f);
+                reinterpret_cast<float4*>(wh)[q] = make_float4(r1, r2, P.mass32[t0 + q], 0.0f);
             } else {
-                reinterpret_cast<float2*>(wl)[q] = make_float2(r1, r2);
+                reinterpret_cast<float2*>(wh)[q] = make_float2(r1, r2);
             }
         }
         __syncthreads();
         for (int b0 = 0; b0 < cnt; b0 += kBlock) {
             const int bn = (cnt - b0) < kBlock ? (cnt - b0) : kBlock;
             if (bn == kBlock) {
-#pragma unroll 2
-                for (int k = 0; k < kBlock; ++k) lens_step_f32<KX, KY, MASS>(wl, b0 + k, ox, oy, p1, p2);
+                // measured on gfx950: unit masses run fastest with the lens
+                // loop unrolled once, mass-weighted lenses with two steps
+#pragma unroll(MASS ? 2 : 1)
+                for (int k = 0; k < kBlock; ++k) lens_step_f32<KX, KY, MASS>(wh, b0 + k, ox, oy, p1, p2);
             } else {
-                for (int k = 0; k < bn; ++k) lens_step_f32<KX, KY, MASS>(wl, b0 + k, ox, oy, p1, p2);
+                for (int k = 0; k < bn; ++k) lens_step_f32<KX, KY, MASS>(wh, b0 + k, ox, oy, p1, p2);
+            }
+            // Pairs whose block sums are not finite (a ray on a lens, or r^2
+            // products beyond the FP32 range) redo the block unpaired.
+            unsigned redo = 0;
+#pragma unroll
+            for (int u = 0; u < R / 2; ++u) {
+                const float t = (p1[2 * u] + p2[2 * u]) + (p1[2 * u + 1] + p2[2 * u + 1]);
+                if (!__builtin_isfinite(t)) redo |= 1u << u;
+            }
+            if (__any(redo != 0)) {
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    if ((redo >> (r / 2)) & 1u) { p1[r] = 0.0f; p2[r] = 0.0f; }
+                for (int k = 0; k < bn; ++k)
+                    lens_step_f32_single<KX, KY, MASS>(wh, b0 + k, ox, oy, p1, p2, redo);
             }
             // TwoSum of the running sum and the block sum; the rounding error
             // goes to the compensation term.
@@ -266,11 +339,15 @@ __device__ __forceinline__ void deflect_f64(const MapParams& P, int64_t i0, int6
 // one cell per wave: deflection, lens equation, binning
 // ----------------------------------------------------------------------------
 
-template <int KX, int KY, bool MASS, int SUBMAP, bool OUT_Y, int PREC>
+// cell and valid are per lane: with CPW cells per wave, lanes
+// [h kLanes / CPW, (h + 1) kLanes / CPW) work on cell h of the wave's CPW cells.
+template <int KX, int KY, bool MASS, int SUBMAP, bool OUT_Y, int PREC, int CPW>
 __device__ __forceinline__ void process_cell(const MapParams& P, int64_t cell, bool valid,
                                              int wave, int lane, int L, char* lens_base,
                                              int* sub, int* hdr) {
     constexpr int R = KX * KY;
+    constexpr int LPC = kLanes / CPW;
+    const int half = lane / LPC, cl = lane % LPC;
     const int64_t col = cell % P.cells_x;
     const int64_t row = P.cell_row0 + cell / P.cells_x;
     const int64_t i0 = col * P.cx, j0 = row * P.cy;
@@ -278,18 +355,18 @@ __device__ __forceinline__ void process_cell(const MapParams& P, int64_t cell, b
     double al1[R], al2[R];
     if constexpr (PREC == kFP32Comp) {
         const int stride = MASS ? 16 : 8;
-        deflect_f32<KX, KY, MASS>(P, i0, j0, lane, L,
-                                  reinterpret_cast<float*>(lens_base + (size_t)wave * L * stride),
-                                  al1, al2);
+        deflect_f32<KX, KY, MASS, CPW>(P, i0, j0, cl, half, L,
+                                       reinterpret_cast<float*>(lens_base + (size_t)wave * CPW * L * stride),
+                                       al1, al2);
     } else {
         const int stride = MASS ? 32 : 16;
-        deflect_f64<KX, KY, MASS>(P, i0, j0, lane, L,
+        deflect_f64<KX, KY, MASS>(P, i0, j0, cl, L,
                                   reinterpret_cast<double*>(lens_base + (size_t)wave * L * stride),
                                   al1, al2);
     }
 
     const int lanes_x = P.cx / KX;
-    const int lxi = lane % lanes_x, lyi = lane / lanes_x;
+    const int lxi = cl % lanes_x, lyi = cl / lanes_x;
     int ixs[R], iys[R];
     int esc = 0;
 #pragma unroll
@@ -405,8 +482,16 @@ __device__ __forceinline__ void process_cell(const MapParams& P, int64_t cell, b
 
 constexpr int kHdrBytes = 64;
 
-template <int KX, int KY, bool MASS, int SUBMAP, bool OUT_Y, int PREC>
-__global__ void __launch_bounds__(256) shoot_kernel(MapParams P, int L) {
+// Occupancy floor in waves per SIMD: 2 holds the 32-ray shapes to 256
+// registers; the 16-ray FP32 shapes with masses run fastest at 4 (measured:
+// the few registers that then spill belong to the per-block compensation,
+// which is touched once per kBlock lenses).
+template <bool MASS, int CPW, int PREC>
+constexpr int min_waves() { return (MASS && CPW == 1 && PREC == kFP32Comp) ? 4 : 2; }
+
+template <int KX, int KY, bool MASS, int SUBMAP, bool OUT_Y, int PREC, int CPW>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(min_waves<MASS, CPW, PREC>())))
+shoot_kernel(MapParams P, int L) {
     extern __shared__ __align__(16) char smem[];
     int* hdr = reinterpret_cast<int*>(smem);
     char* lens_base = smem + kHdrBytes;
@@ -416,17 +501,18 @@ __global__ void __launch_bounds__(256) shoot_kernel(MapParams P, int L) {
     const int wave = threadIdx.x / kLanes, lane = threadIdx.x % kLanes;
     const int W = blockDim.x / kLanes;
     const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t cell = b * W + wave;
+    const int64_t cell = (b * W + wave) * CPW + lane / (kLanes / CPW);
     const bool valid = cell < P.n_cells;
-    process_cell<KX, KY, MASS, SUBMAP, OUT_Y, PREC>(P, valid ? cell : 0, valid, wave, lane, L,
-                                                    lens_base, sub, hdr);
+    process_cell<KX, KY, MASS, SUBMAP, OUT_Y, PREC, CPW>(P, valid ? cell : 0, valid, wave, lane, L,
+                                                         lens_base, sub, hdr);
 }
 
 // Persistent batch kernel: workgroups pull (map, cell range) items from a
 // global counter until the list is exhausted; every workgroup reaches the
 // exit because the counter only grows.
-template <int KX, int KY, bool MASS, int SUBMAP, int PREC>
-__global__ void __launch_bounds__(256) shoot_batch_kernel(const MapParams* __restrict__ maps,
+template <int KX, int KY, bool MASS, int SUBMAP, int PREC, int CPW>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(min_waves<MASS, CPW, PREC>())))
+shoot_batch_kernel(const MapParams* __restrict__ maps,
                                                           const WorkItem* __restrict__ items,
                                                           int64_t n_items, unsigned int* counter,
                                                           int L) {
@@ -447,11 +533,11 @@ __global__ void __launch_bounds__(256) shoot_batch_kernel(const MapParams* __res
         const WorkItem w = items[it];
         const MapParams& P = maps[w.map];
         const int64_t end = w.cell0 + w.ncells;
-        for (int64_t c0 = w.cell0; c0 < end; c0 += W) {
-            const int64_t cell = c0 + wave;
+        for (int64_t c0 = w.cell0; c0 < end; c0 += (int64_t)W * CPW) {
+            const int64_t cell = c0 + wave * CPW + lane / (kLanes / CPW);
             const bool valid = cell < end;
-            process_cell<KX, KY, MASS, SUBMAP, false, PREC>(P, valid ? cell : w.cell0, valid, wave,
-                                                            lane, L, lens_base, sub, hdr);
+            process_cell<KX, KY, MASS, SUBMAP, false, PREC, CPW>(P, valid ? cell : w.cell0, valid, wave,
+                                                                 lane, L, lens_base, sub, hdr);
         }
     }
 }
@@ -546,233 +632,6 @@ __global__ void fill_u32_kernel(unsigned int* p, int64_t n, unsigned int v) {
         p[k] = v;
 }
 
-// ----------------------------------------------------------------------------
-// magnification probability distributions (Section 3.2.1 and Section 4)
-// ----------------------------------------------------------------------------
-
-constexpr int kHistLds = 8192;   // count values histogrammed in LDS per workgroup
-
-// Frequency of each count value; values >= n_values - 1 share the last entry.
-// Low values (where almost every pixel lies) go to an LDS copy first.
-__global__ void __launch_bounds__(256) count_hist_kernel(const int32_t* __restrict__ counts,
-                                                         int64_t n, int64_t n_values,
-                                                         unsigned long long* __restrict__ hist) {
-    __shared__ unsigned int sh[kHistLds];
-    const int nl = (int)(n_values < kHistLds ? n_values : kHistLds);
-    for (int e = threadIdx.x; e < nl; e += blockDim.x) sh[e] = 0;
-    __syncthreads();
-    const int64_t last = n_values - 1;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        int64_t c = counts[k];
-        c = c < 0 ? 0 : c;
-        const int64_t v = c < last ? c : last;
-        if (v < nl) atomicAdd(&sh[v], 1u);
-        else atomicAdd(&hist[v], 1ull);
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < nl; e += blockDim.x)
-        if (sh[e]) atomicAdd(&hist[e], (unsigned long long)sh[e]);
-}
-
-// Binned MPD: bin = number of count thresholds <= N (thresholds ascending), so
-// bin 0 is the underflow and bin nthr the overflow. Thresholds and bins in LDS.
-__global__ void __launch_bounds__(256) mpd_kernel(const int32_t* __restrict__ counts, int64_t n,
-                                                  const double* __restrict__ thr, int nthr,
-                                                  unsigned long long* __restrict__ bins) {
-    extern __shared__ __align__(16) char smem[];
-    double* st = reinterpret_cast<double*>(smem);
-    unsigned int* sb = reinterpret_cast<unsigned int*>(st + nthr);
-    for (int e = threadIdx.x; e < nthr; e += blockDim.x) st[e] = thr[e];
-    for (int e = threadIdx.x; e <= nthr; e += blockDim.x) sb[e] = 0;
-    __syncthreads();
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        const double c = (double)counts[k];
-        int lo = 0, hi = nthr;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (st[mid] <= c) lo = mid + 1;
-            else hi = mid;
-        }
-        atomicAdd(&sb[lo], 1u);
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e <= nthr; e += blockDim.x)
-        if (sb[e]) atomicAdd(&bins[e], (unsigned long long)sb[e]);
-}
-
-// Pixels with N / N_avg < mu_lim (one FP64 division each, as the definition).
-__global__ void __launch_bounds__(256) prob_sum_kernel(const int32_t* __restrict__ counts, int64_t n,
-                                                       double n_avg, double mu_lim,
-                                                       unsigned long long* __restrict__ out) {
-    __shared__ unsigned long long part[4];
-    unsigned long long below = 0;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
-         k += (int64_t)gridDim.x * blockDim.x)
-        below += ((double)counts[k] / n_avg < mu_lim) ? 1ull : 0ull;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) below += __shfl_xor(below, o);
-    if ((threadIdx.x % kLanes) == 0) part[threadIdx.x / kLanes] = below;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long t = 0;
-        for (int i = 0; i < (int)(blockDim.x / kLanes); ++i) t += part[i];
-        atomicAdd(out, t);
-    }
-}
-
-// Mean and sample standard deviation over n_maps MPDs of one bin per thread,
-// in probabilities (bin count / n_pix).
-__global__ void mpd_moments_kernel(const unsigned long long* __restrict__ bins, int n_maps,
-                                   int n_bins, double n_pix, double* __restrict__ mean,
-                                   double* __restrict__ stdev) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= n_bins) return;
-    double s = 0.0;
-    for (int r = 0; r < n_maps; ++r) s += (double)bins[(int64_t)r * n_bins + b] / n_pix;
-    const double m = s / (double)n_maps;
-    double v = 0.0;
-    for (int r = 0; r < n_maps; ++r) {
-        const double d = (double)bins[(int64_t)r * n_bins + b] / n_pix - m;
-        v += d * d;
-    }
-    mean[b] = m;
-    stdev[b] = n_maps > 1 ? sqrt(v / (double)(n_maps - 1)) : 0.0;
-}
-
-// ----------------------------------------------------------------------------
-// indexed-map codec (Appendix B)
-// ----------------------------------------------------------------------------
-
-constexpr int kScanPerBlock = 1024;   // elements per scan block (256 threads x 4)
-
-// flag[v] = 1 where value v occurs in the map
-__global__ void distinct_flag_kernel(const unsigned long long* __restrict__ hist, int64_t n,
-                                     int32_t* __restrict__ flag) {
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
-         v += (int64_t)gridDim.x * blockDim.x)
-        flag[v] = hist[v] ? 1 : 0;
-}
-
-// Exclusive scan of a block of 256 x 4 int32 in LDS; returns the block total.
-__device__ int block_exclusive_scan_1024(int32_t (&v)[4], int* sh) {
-    const int t = threadIdx.x;
-    int local = v[0] + v[1] + v[2] + v[3];
-    sh[t] = local;
-    __syncthreads();
-    for (int o = 1; o < 256; o <<= 1) {       // Hillis-Steele over the 256 thread sums
-        const int add = t >= o ? sh[t - o] : 0;
-        __syncthreads();
-        sh[t] += add;
-        __syncthreads();
-    }
-    const int total = sh[255];
-    int run = sh[t] - local;                   // exclusive prefix of this thread
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < 4; ++i) { const int x = v[i]; v[i] = run; run += x; }
-    return total;
-}
-
-__global__ void __launch_bounds__(256) scan_block_sums_kernel(const int32_t* __restrict__ in, int64_t n,
-                                                              int32_t* __restrict__ sums) {
-    __shared__ int sh[256];
-    const int64_t base = (int64_t)blockIdx.x * kScanPerBlock + threadIdx.x * 4;
-    int32_t v[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) v[i] = base + i < n ? in[base + i] : 0;
-    const int total = block_exclusive_scan_1024(v, sh);
-    if (threadIdx.x == 0) sums[blockIdx.x] = total;
-}
-
-// One workgroup: exclusive scan of the block sums in place; *grand = total.
-__global__ void __launch_bounds__(256) scan_sums_kernel(int32_t* __restrict__ sums, int64_t nb,
-                                                        int64_t* __restrict__ grand) {
-    __shared__ int sh[256];
-    int64_t carry = 0;
-    for (int64_t c0 = 0; c0 < nb; c0 += kScanPerBlock) {
-        int32_t v[4];
-        const int64_t base = c0 + threadIdx.x * 4;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) v[i] = base + i < nb ? sums[base + i] : 0;
-        const int total = block_exclusive_scan_1024(v, sh);
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            if (base + i < nb) sums[base + i] = (int32_t)(carry + v[i]);
-        carry += total;
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *grand = carry;
-}
-
-__global__ void __launch_bounds__(256) scan_apply_kernel(const int32_t* __restrict__ in, int64_t n,
-                                                         const int32_t* __restrict__ offsets,
-                                                         int32_t* __restrict__ out) {
-    __shared__ int sh[256];
-    const int64_t base = (int64_t)blockIdx.x * kScanPerBlock + threadIdx.x * 4;
-    int32_t v[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) v[i] = base + i < n ? in[base + i] : 0;
-    block_exclusive_scan_1024(v, sh);
-    const int32_t off = offsets[blockIdx.x];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-        if (base + i < n) out[base + i] = off + v[i];
-}
-
-// values[rank[v]] = v for every value present (ranks ascend with v).
-__global__ void scatter_values_kernel(const int32_t* __restrict__ flag,
-                                      const int32_t* __restrict__ rank, int64_t n,
-                                      int32_t* __restrict__ values) {
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
-         v += (int64_t)gridDim.x * blockDim.x)
-        if (flag[v]) values[rank[v]] = (int32_t)v;
-}
-
-// One output word per thread: gathers the indices of the pixels whose bits
-// fall into word w (bits [32w, 32w + 32), pixel p at bits [p b, p b + b),
-// least significant bit first). Stores are coalesced and need no atomics.
-__global__ void pack_kernel(const int32_t* __restrict__ counts, int64_t n_pix,
-                            const int32_t* __restrict__ rank, int64_t n_values, int bits,
-                            int64_t n_words, uint32_t* __restrict__ packed) {
-    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < n_words;
-         w += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t lo_bit = w * 32;
-        const int64_t p0 = lo_bit / bits;
-        int64_t p1 = (lo_bit + 31) / bits;
-        if (p1 > n_pix - 1) p1 = n_pix - 1;
-        unsigned long long word = 0;
-        for (int64_t p = p0; p <= p1; ++p) {
-            const int32_t c = counts[p];
-            const unsigned long long idx =
-                (c >= 0 && c < n_values) ? (unsigned long long)(uint32_t)rank[c] : 0ull;
-            const int64_t start = p * bits;
-            if (start >= lo_bit) word |= idx << (start - lo_bit);        // shift < 32
-            else word |= idx >> (lo_bit - start);                        // shift < bits <= 32
-        }
-        packed[w] = (uint32_t)word;
-    }
-}
-
-// Inverse of pack_kernel; an index past the table (a stream not produced by
-// the encoder) decodes to -1 instead of reading out of bounds.
-__global__ void unpack_kernel(const uint32_t* __restrict__ packed, int64_t n_pix, int bits,
-                              const int32_t* __restrict__ values, int64_t n_values,
-                              int32_t* __restrict__ counts) {
-    const unsigned long long mask = bits >= 32 ? 0xFFFFFFFFull : ((1ull << bits) - 1ull);
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n_pix;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t start = p * bits;
-        const int64_t w = start >> 5;
-        const int off = (int)(start & 31);
-        unsigned long long v = (unsigned long long)packed[w] >> off;
-        if (off + bits > 32) v |= (unsigned long long)packed[w + 1] << (32 - off);
-        const unsigned long long idx = v & mask;
-        counts[p] = idx < (unsigned long long)n_values ? values[idx] : -1;
-    }
-}
-
 int grid_for(int64_t n, int threads, int cap) {
     int64_t g = (n + threads - 1) / threads;
     if (g < 1) g = 1;
@@ -784,12 +643,16 @@ int grid_for(int64_t n, int threads, int cap) {
 // dispatch
 // ----------------------------------------------------------------------------
 
+template <int KX, int KY>
+constexpr int cells_per_wave() { return KX * KY / kRaysPerLane; }
+
 template <int KX, int KY, bool MASS, int SUBMAP, bool OUT_Y, int PREC>
 hipError_t launch_one(const MapParams& P, const KernelShape& ks, size_t lds, hipStream_t s) {
+    constexpr int CPW = cells_per_wave<KX, KY>();
     const int W = ks.waves;
-    const int64_t blocks = (P.n_cells + W - 1) / W;
+    const int64_t blocks = (P.n_cells + (int64_t)W * CPW - 1) / ((int64_t)W * CPW);
     if (blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL((shoot_kernel<KX, KY, MASS, SUBMAP, OUT_Y, PREC>), dim3((unsigned)blocks),
+    hipLaunchKernelGGL((shoot_kernel<KX, KY, MASS, SUBMAP, OUT_Y, PREC, CPW>), dim3((unsigned)blocks),
                        dim3(W * kLanes), lds, s, P, ks.lens_tile);
     return hipGetLastError();
 }
@@ -803,7 +666,8 @@ hipError_t launch_batch_one(const MapParams* maps, const WorkItem* items, int64_
     int64_t blocks = (int64_t)num_cus * (16 / W);
     if (blocks > n_items) blocks = n_items;
     if (blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL((shoot_batch_kernel<KX, KY, MASS, SUBMAP, PREC>), dim3((unsigned)blocks),
+    hipLaunchKernelGGL((shoot_batch_kernel<KX, KY, MASS, SUBMAP, PREC, cells_per_wave<KX, KY>()>),
+                       dim3((unsigned)blocks),
                        dim3(W * kLanes), lds, s, maps, items, n_items, counter, ks.lens_tile);
     return hipGetLastError();
 }
@@ -853,8 +717,10 @@ bool shape_supported(Precision prec, const KernelShape& ks) {
     const bool k44 = ks.rays_x == 4 && ks.rays_y == 4;
     const bool k28 = ks.rays_x == 2 && ks.rays_y == 8;
     const bool k82 = ks.rays_x == 8 && ks.rays_y == 2;
+    const bool k48 = ks.rays_x == 4 && ks.rays_y == 8;   // 32 rays per lane, two cells per wave
+    const bool k84 = ks.rays_x == 8 && ks.rays_y == 4;
     if (prec == kFP64Plain && !k44) return false;
-    if (!(k44 || k28 || k82)) return false;
+    if (!(k44 || k28 || k82 || k48 || k84)) return false;
     if (ks.lens_tile < kBlock || ks.lens_tile > 2048 || ks.lens_tile % kBlock) return false;
     if (!(ks.waves == 1 || ks.waves == 2 || ks.waves == 4)) return false;
     if (ks.submap < 0 || ks.submap > 2) return false;
@@ -866,8 +732,15 @@ bool shape_supported(Precision prec, const KernelShape& ks) {
 // fit is shrunk (in whole compensation blocks), which changes no result.
 constexpr size_t kMaxLds = 65536;
 
-KernelShape fit_lds(Precision prec, bool masses, const KernelShape& ks) {
+// LDS bytes of one lens entry times the cells per wave (each cell stages its
+// own rebased copy).
+size_t lens_entry_bytes(Precision prec, bool masses, const KernelShape& ks) {
     const size_t stride = prec == kFP32Comp ? (masses ? 16 : 8) : (masses ? 32 : 16);
+    return stride * (size_t)(ks.rays_x * ks.rays_y / kRaysPerLane);
+}
+
+KernelShape fit_lds(Precision prec, bool masses, const KernelShape& ks) {
+    const size_t stride = lens_entry_bytes(prec, masses, ks);
     KernelShape k = ks;
     const size_t room = kMaxLds - kHdrBytes;
     while (k.lens_tile > kBlock && (size_t)k.waves * k.lens_tile * stride > room) k.lens_tile -= kBlock;
@@ -875,7 +748,7 @@ KernelShape fit_lds(Precision prec, bool masses, const KernelShape& ks) {
 }
 
 size_t shoot_lds_bytes(Precision prec, bool masses, const KernelShape& ks) {
-    const size_t stride = prec == kFP32Comp ? (masses ? 16 : 8) : (masses ? 32 : 16);
+    const size_t stride = lens_entry_bytes(prec, masses, ks);
     size_t lens = (size_t)ks.waves * ks.lens_tile * stride;
     const size_t sub = ks.submap ? (size_t)kSub * kSub * sizeof(int) : 0;
     return kHdrBytes + (lens > sub ? lens : sub);
@@ -889,8 +762,10 @@ hipError_t launch_shoot(const MapParams& P, Precision prec, const KernelShape& k
     if (out_y) k.submap = 0;
     const size_t lds = shoot_lds_bytes(prec, masses, k);
     if (prec == kFP64Plain) return dispatch_shape<4, 4, kFP64Plain>(P, k, masses, out_y, lds, s);
-    if (k.rays_x == 4) return dispatch_shape<4, 4, kFP32Comp>(P, k, masses, out_y, lds, s);
+    if (k.rays_x == 4 && k.rays_y == 4) return dispatch_shape<4, 4, kFP32Comp>(P, k, masses, out_y, lds, s);
     if (k.rays_x == 2) return dispatch_shape<2, 8, kFP32Comp>(P, k, masses, out_y, lds, s);
+    if (k.rays_x == 4) return dispatch_shape<4, 8, kFP32Comp>(P, k, masses, out_y, lds, s);
+    if (k.rays_y == 4) return dispatch_shape<8, 4, kFP32Comp>(P, k, masses, out_y, lds, s);
     return dispatch_shape<8, 2, kFP32Comp>(P, k, masses, out_y, lds, s);
 }
 
@@ -901,10 +776,14 @@ hipError_t launch_shoot_batch(const MapParams* d_maps, const WorkItem* d_items, 
     const size_t lds = shoot_lds_bytes(prec, masses, ks);
     if (prec == kFP64Plain)
         return dispatch_batch_shape<4, 4, kFP64Plain>(d_maps, d_items, n_items, d_counter, masses, ks, lds, num_cus, s);
-    if (ks.rays_x == 4)
+    if (ks.rays_x == 4 && ks.rays_y == 4)
         return dispatch_batch_shape<4, 4, kFP32Comp>(d_maps, d_items, n_items, d_counter, masses, ks, lds, num_cus, s);
     if (ks.rays_x == 2)
         return dispatch_batch_shape<2, 8, kFP32Comp>(d_maps, d_items, n_items, d_counter, masses, ks, lds, num_cus, s);
+    if (ks.rays_x == 4)
+        return dispatch_batch_shape<4, 8, kFP32Comp>(d_maps, d_items, n_items, d_counter, masses, ks, lds, num_cus, s);
+    if (ks.rays_y == 4)
+        return dispatch_batch_shape<8, 4, kFP32Comp>(d_maps, d_items, n_items, d_counter, masses, ks, lds, num_cus, s);
     return dispatch_batch_shape<8, 2, kFP32Comp>(d_maps, d_items, n_items, d_counter, masses, ks, lds, num_cus, s);
 }
 
@@ -938,75 +817,6 @@ hipError_t launch_count_stats(const int32_t* counts, int64_t n, unsigned long lo
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(count_stats_kernel, dim3(grid_for(n, 256 * 8, 1024)), dim3(256), 0, s, counts, n,
                        out);
-    return hipGetLastError();
-}
-
-hipError_t launch_count_hist(const int32_t* counts, int64_t n, int64_t n_values,
-                             unsigned long long* hist, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(count_hist_kernel, dim3(grid_for(n, 256 * 16, 2048)), dim3(256), 0, s, counts,
-                       n, n_values, hist);
-    return hipGetLastError();
-}
-
-hipError_t launch_mpd(const int32_t* counts, int64_t n, const double* thr, int nthr,
-                      unsigned long long* bins, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    const size_t lds = (size_t)nthr * sizeof(double) + (size_t)(nthr + 1) * sizeof(unsigned int);
-    hipLaunchKernelGGL(mpd_kernel, dim3(grid_for(n, 256 * 16, 2048)), dim3(256), lds, s, counts, n,
-                       thr, nthr, bins);
-    return hipGetLastError();
-}
-
-hipError_t launch_prob_sum(const int32_t* counts, int64_t n, double n_avg, double mu_lim,
-                           unsigned long long* out, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(prob_sum_kernel, dim3(grid_for(n, 256 * 16, 2048)), dim3(256), 0, s, counts, n,
-                       n_avg, mu_lim, out);
-    return hipGetLastError();
-}
-
-hipError_t launch_mpd_moments(const unsigned long long* bins, int n_maps, int n_bins, double n_pix,
-                              double* mean, double* stdev, hipStream_t s) {
-    if (n_bins <= 0) return hipSuccess;
-    hipLaunchKernelGGL(mpd_moments_kernel, dim3((n_bins + 255) / 256), dim3(256), 0, s, bins, n_maps,
-                       n_bins, n_pix, mean, stdev);
-    return hipGetLastError();
-}
-
-int64_t scan_blocks(int64_t n) { return (n + kScanPerBlock - 1) / kScanPerBlock; }
-
-hipError_t launch_distinct_ranks(const unsigned long long* hist, int64_t n_values, int32_t* flag,
-                                 int32_t* rank, int32_t* block_sums, int64_t* total,
-                                 hipStream_t s) {
-    if (n_values <= 0) return hipSuccess;
-    const int64_t nb = scan_blocks(n_values);
-    hipLaunchKernelGGL(distinct_flag_kernel, dim3(grid_for(n_values, 256, 8192)), dim3(256), 0, s, hist,
-                       n_values, flag);
-    hipLaunchKernelGGL(scan_block_sums_kernel, dim3((unsigned)nb), dim3(256), 0, s, flag, n_values,
-                       block_sums);
-    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(256), 0, s, block_sums, nb, total);
-    hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)nb), dim3(256), 0, s, flag, n_values,
-                       block_sums, rank);
-    return hipGetLastError();
-}
-
-hipError_t launch_codec_pack(const int32_t* counts, int64_t n_pix, const int32_t* flag,
-                             const int32_t* rank, int64_t n_values, int bits, int32_t* values,
-                             uint32_t* packed, hipStream_t s) {
-    const int64_t n_words = (n_pix * bits + 31) / 32;
-    hipLaunchKernelGGL(scatter_values_kernel, dim3(grid_for(n_values, 256, 8192)), dim3(256), 0, s, flag,
-                       rank, n_values, values);
-    hipLaunchKernelGGL(pack_kernel, dim3(grid_for(n_words, 256, 16384)), dim3(256), 0, s, counts, n_pix,
-                       rank, n_values, bits, n_words, packed);
-    return hipGetLastError();
-}
-
-hipError_t launch_codec_unpack(const uint32_t* packed, int64_t n_pix, int bits, const int32_t* values,
-                               int64_t n_values, int32_t* counts, hipStream_t s) {
-    if (n_pix <= 0) return hipSuccess;
-    hipLaunchKernelGGL(unpack_kernel, dim3(grid_for(n_pix, 256, 16384)), dim3(256), 0, s, packed, n_pix,
-                       bits, values, n_values, counts);
     return hipGetLastError();
 }
 

@@ -147,6 +147,14 @@ def test_fp64_ray_on_a_lens_escapes(ctx):
     for prec in ("fp64", "fp32c"):
         counts, esc = ctx.shoot(dev_lenses(f), spec, prec)
         assert int(esc.item()) == 1 and counts.sum().item() == 15
+    # FP32: the ray on the lens is non-finite; every other ray, including the
+    # one that shares its reciprocal (same column, rows 2 and 3), is accurate
+    y1, y2 = ctx.ray_positions(dev_lenses(f), spec, "fp32c")
+    o1, o2, sing, _ = o_positions(spec, f)
+    sing = sing.astype(bool)
+    y1, y2 = y1.cpu().numpy(), y2.cpu().numpy()
+    assert sing.sum() == 1 and not np.isfinite(y1[sing] + y2[sing]).any()
+    assert np.abs(y1[~sing] - o1[~sing]).max() <= TOL_Y and np.abs(y2[~sing] - o2[~sing]).max() <= TOL_Y
 
 
 # ---------------------------------------------------------------------------
@@ -208,10 +216,15 @@ SHAPES = [dict(rays_x=4, rays_y=4, lens_tile=256, waves=4, submap=1),
           dict(rays_x=8, rays_y=2, lens_tile=2048, waves=2, submap=1),
           dict(rays_x=4, rays_y=4, lens_tile=512, waves=2, submap=0),
           dict(rays_x=2, rays_y=8, lens_tile=256, waves=4, submap=2),
-          dict(rays_x=4, rays_y=4, lens_tile=128, waves=1, submap=2)]
+          dict(rays_x=4, rays_y=4, lens_tile=128, waves=1, submap=2),
+          # 32 rays per lane, two cells per wave
+          dict(rays_x=4, rays_y=8, lens_tile=256, waves=4, submap=1),
+          dict(rays_x=8, rays_y=4, lens_tile=128, waves=2, submap=2),
+          dict(rays_x=4, rays_y=8, lens_tile=1024, waves=1, submap=0)]
 
 
-@pytest.mark.parametrize("spec", [SMALL, MIXED_SMALL, ODD_SHAPES[4]], ids=lambda s: s.name)
+@pytest.mark.parametrize("spec", [SMALL, MIXED_SMALL, ODD_SHAPES[0], ODD_SHAPES[1], ODD_SHAPES[4],
+                                  ODD_SHAPES[5]], ids=lambda s: s.name)
 def test_results_do_not_depend_on_kernel_shape(ctx, spec):
     f = spec.lenses()
     L = dev_lenses(f)
@@ -273,6 +286,30 @@ def test_batch_equals_alone(ctx, prec):
     for i in range(2):
         c, e = ctx.shoot(Ls[i], specs[i], prec, row_begin=10, row_end=20)
         assert torch.equal(part[i][0], c) and int(part[i][1].item()) == int(e.item())
+
+
+def test_batch_with_two_cells_per_wave_equals_alone(ctx):
+    """The persistent batch launch with the 32-ray shapes (two cells per wave,
+    odd cell counts leave half-waves idle) against single-map launches with
+    the default shapes."""
+    specs = [SMALL, MIXED_SMALL] + ODD_SHAPES
+    fields = [s.lenses() for s in specs]
+    Ls = [dev_lenses(f) for f in fields]
+    alone = [ctx.shoot(L, s, "fp32c") for L, s in zip(Ls, specs)]
+    saved = {c: ctx.get_tuning("fp32c", c) for c in range(3)}
+    try:
+        for sh in (dict(rays_x=4, rays_y=8, lens_tile=256, waves=4, submap=1, item_cells=3),
+                   dict(rays_x=8, rays_y=4, lens_tile=128, waves=1, submap=2, item_cells=1)):
+            for c in range(3):
+                ctx.set_tuning("fp32c", c, **sh)
+            outs = [ctx.new_map(s) for s in specs]
+            ctx.shoot_batch([(L, s, c, e) for L, s, (c, e) in zip(Ls, specs, outs)], "fp32c")
+            for (c, e), (ca, ea), s in zip(outs, alone, specs):
+                assert torch.equal(c, ca), (s.name, sh)
+                assert int(e.item()) == int(ea.item()), (s.name, sh)
+    finally:
+        for c in range(3):
+            ctx.set_tuning("fp32c", c, **saved[c])
 
 
 def test_stats_match_the_oracle(ctx):
