@@ -104,7 +104,13 @@ def main():
     spec = inputs.WORKLOADS[args.workload]()
     field = spec.lenses()
     ctx = rl.Context(0)
-    tuned = False if args.no_tuning_cache else autotune.apply(ctx, autotune.load())
+    tuned = False
+    if not args.no_tuning_cache:
+        try:    # applies the cached table only if this library build wrote it
+            ctx.autotune(autotune.DEFAULT_CACHE, 0)
+            tuned = True
+        except rl.RaylensError:
+            tuned = False
     L = rl.DeviceLenses(field.x1, field.x2, field.m)
     counts, esc = ctx.new_map(spec)
     mu = torch.empty((spec.p2, spec.p1), dtype=torch.float32, device="cuda")

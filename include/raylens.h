@@ -223,12 +223,31 @@ typedef struct {
     int32_t item_cells;
 } rl_tuning;
 
-/* Reads / sets the kernel shape used for `precision` and lens-count class
- * `n_class` (0: n < 1000, 1: n < 10000, 2: n >= 10000). Host only. */
+/* Reads / sets the kernel shape used for `precision` and tuning class
+ * `n_class`: 0 (n < 1000 lenses), 1 (n < 10000), 2 (n >= 10000) for unit
+ * masses, 3, 4, 5 for the same lens counts with masses (rl_lenses.m != NULL;
+ * a batch uses the class of its largest lens count, with masses if any map
+ * has them). Host only. */
 rl_status rl_get_tuning(rl_context* ctx, rl_precision precision, int32_t n_class,
                         rl_tuning* h_out);
 rl_status rl_set_tuning(rl_context* ctx, rl_precision precision, int32_t n_class,
                         const rl_tuning* h_tuning);
+
+/* Autotuner (the "timed probes" tuning of the kernel shape; the method itself,
+ * Section 2.1, fixes no shape): if cache_path names a JSON table written by
+ * this library build (rl_version) for this device architecture, its shapes
+ * are applied and nothing is timed. Otherwise, for each precision and tuning
+ * class, probe maps are shot under the candidate shapes (rays per lane, lens
+ * tile, waves, binning mode; then the batch work-item size), every shape must
+ * reproduce the first one's counts exactly (else RL_E_DEVICE), and the
+ * fastest is applied; the table is written to cache_path (if not NULL,
+ * through a temporary file and a rename). budget_ms bounds the wall time of
+ * the probing: classes not reached keep their current shapes and the table
+ * records "complete": false. budget_ms == 0 only applies a cache and returns
+ * RL_E_INVALID if there is none. Synchronous; uses the null stream and about
+ * 50 MB of device memory, freed before return. With the environment variable
+ * RL_AUTOTUNE_LOG=1 it prints one line per tuned class to stderr. */
+rl_status rl_autotune(rl_context* ctx, const char* cache_path, int32_t budget_ms);
 
 /* ------------------------------------------------------------------------
  * Magnification probability distributions (MPDs)

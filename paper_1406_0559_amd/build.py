@@ -25,12 +25,25 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall",
           "-I", INCLUDE, "-I", CSRC]
 DEVICE = ["-x", "hip", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = [("shoot.hip", True), ("maps.hip", True), ("convolve.hip", True), ("api.cpp", True)]
+SOURCES = [("shoot.hip", True), ("maps.hip", True), ("convolve.hip", True), ("api.cpp", True),
+           ("tune.cpp", True)]
+
+
+def kernel_id():
+    """First 12 hex digits of the sha256 over the shoot kernel's sources
+    (shoot.hip, then internal.h): tuning caches name the build they are for."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("shoot.hip", "internal.h"):
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:12]
 
 
 def _compile(src, device, verbose):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *COMMON, *(DEVICE if device else []), "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *COMMON, *(DEVICE if device else []), f'-DRL_KERNEL_ID="{kernel_id()}"',
+           "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

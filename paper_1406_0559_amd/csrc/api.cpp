@@ -15,10 +15,12 @@
 #include "internal.h"
 
 namespace {
-
 thread_local std::string g_error;
+}  // namespace
 
-rl_status fail(rl_status st, const char* fmt, ...) {
+namespace rl {
+
+rl_status set_error(rl_status st, const char* fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -26,6 +28,17 @@ rl_status fail(rl_status st, const char* fmt, ...) {
     va_end(ap);
     g_error = buf;
     return st;
+}
+
+void clear_error() { g_error.clear(); }
+
+}  // namespace rl
+
+namespace {
+
+template <typename... A>
+rl_status fail(rl_status st, const char* fmt, A... args) {
+    return rl::set_error(st, fmt, args...);
 }
 
 rl_status hip_fail(hipError_t e, const char* what) {
@@ -86,11 +99,6 @@ rl_status check_rows(const rl_raygrid* g, int64_t rb, int64_t re) {
     return RL_OK;
 }
 
-#define RL_TRY(expr)                      \
-    do {                                  \
-        rl_status st_ = (expr);           \
-        if (st_ != RL_OK) return st_;     \
-    } while (0)
 
 // ---------------------------------------------------------------------------
 // parameter records
@@ -148,7 +156,6 @@ void build_params(const rl_macro* M, const rl_raygrid* G, const rl_window* W, in
     P->inv2 = (double)W->p2 / W->width2;
 }
 
-int n_class(int64_t n) { return n < 1000 ? 0 : (n < 10000 ? 1 : 2); }
 
 // RAII: make the context's device current for the duration of a call.
 struct DeviceGuard {
@@ -231,8 +238,10 @@ struct rl_context {
     size_t host_cap = 0;
     hipEvent_t stage_done = nullptr;
     bool stage_used = false;
-    rl::KernelShape tuning[2][3];
+    rl::KernelShape tuning[2][rl::kTuningClasses];
 };
+
+int rl::context_device(const rl_context* ctx) { return ctx->device; }
 
 namespace {
 
@@ -312,7 +321,13 @@ extern "C" {
 
 const char* rl_last_error(void) { return g_error.c_str(); }
 
-const char* rl_version(void) { return "raylens 0.1 (gfx950)"; }
+#ifndef RL_KERNEL_ID
+#define RL_KERNEL_ID "unversioned"
+#endif
+
+// The kernel id is a digest of the shoot kernel's sources, so tuning caches
+// made by another build are not applied.
+const char* rl_version(void) { return "raylens 0.2 (gfx950, kernels " RL_KERNEL_ID ")"; }
 
 rl_status rl_create(int32_t hip_device, rl_context** out) {
     g_error.clear();
@@ -321,9 +336,12 @@ rl_status rl_create(int32_t hip_device, rl_context** out) {
     rl_context* c = new (std::nothrow) rl_context();
     if (!c) return fail(RL_E_NOMEM, "context allocation failed");
     c->device = hip_device;
+    // defaults measured on gfx950 (the autotuner refines them): unit masses
+    // 8 x 2 rays per lane, mass-weighted lenses 4 x 4; FP64 4 x 4
     for (int p = 0; p < 2; ++p)
-        for (int k = 0; k < 3; ++k)
-            c->tuning[p][k] = rl::KernelShape{4, 4, 256, 4, 1, 16};
+        for (int k = 0; k < rl::kTuningClasses; ++k)
+            c->tuning[p][k] = (p == RL_FP32_COMP && k < 3) ? rl::KernelShape{8, 2, 256, 4, 1, 16}
+                                                           : rl::KernelShape{4, 4, 256, 4, 1, 16};
     *out = c;
     return RL_OK;
 }
@@ -362,7 +380,8 @@ rl_status rl_get_tuning(rl_context* ctx, rl_precision precision, int32_t n_cls, 
     g_error.clear();
     if (!ctx) return fail(RL_E_INVALID, "context is NULL");
     RL_TRY(check_precision(precision));
-    if (n_cls < 0 || n_cls > 2) return fail(RL_E_INVALID, "lens-count class must be 0, 1 or 2");
+    if (n_cls < 0 || n_cls >= rl::kTuningClasses)
+        return fail(RL_E_INVALID, "tuning class must be in [0, %d)", rl::kTuningClasses);
     if (!h_out) return fail(RL_E_INVALID, "h_out is NULL");
     const rl::KernelShape& k = ctx->tuning[precision][n_cls];
     *h_out = rl_tuning{k.rays_x, k.rays_y, k.lens_tile, k.waves, k.submap, k.item_cells};
@@ -373,7 +392,8 @@ rl_status rl_set_tuning(rl_context* ctx, rl_precision precision, int32_t n_cls, 
     g_error.clear();
     if (!ctx) return fail(RL_E_INVALID, "context is NULL");
     RL_TRY(check_precision(precision));
-    if (n_cls < 0 || n_cls > 2) return fail(RL_E_INVALID, "lens-count class must be 0, 1 or 2");
+    if (n_cls < 0 || n_cls >= rl::kTuningClasses)
+        return fail(RL_E_INVALID, "tuning class must be in [0, %d)", rl::kTuningClasses);
     if (!t) return fail(RL_E_INVALID, "tuning is NULL");
     rl::KernelShape k{t->rays_x, t->rays_y, t->lens_tile, t->waves, t->submap, t->item_cells};
     if (!rl::shape_supported((rl::Precision)precision, k))
@@ -406,7 +426,7 @@ rl_status rl_shoot(rl_context* ctx, const rl_lenses* lenses, const rl_macro* mac
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return hip_fail(dg.err, "hipSetDevice");
     RL_TRY(ensure_ready(ctx));
-    const rl::KernelShape& ks = ctx->tuning[precision][n_class(lenses->n)];
+    const rl::KernelShape& ks = ctx->tuning[precision][rl::tuning_class(lenses->n, lenses->m != nullptr)];
     hipError_t e;
     if (precision == RL_FP32_COMP) {
         RL_TRY(prepare_lenses_f32(ctx, lenses, false, &P, stream));
@@ -446,7 +466,7 @@ rl_status rl_ray_positions(rl_context* ctx, const rl_lenses* lenses, const rl_ma
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return hip_fail(dg.err, "hipSetDevice");
     RL_TRY(ensure_ready(ctx));
-    rl::KernelShape ks = ctx->tuning[precision][n_class(lenses->n)];
+    rl::KernelShape ks = ctx->tuning[precision][rl::tuning_class(lenses->n, lenses->m != nullptr)];
     hipError_t e;
     if (precision == RL_FP32_COMP) {
         RL_TRY(prepare_lenses_f32(ctx, lenses, false, &P, stream));
@@ -575,7 +595,7 @@ rl_status rl_shoot_batch(rl_context* ctx, const rl_map_desc* h_maps, int32_t n_m
         masses = masses || h_maps[i].lenses.m != nullptr;
         total_lens += h_maps[i].lenses.n;
     }
-    const rl::KernelShape ks = ctx->tuning[precision][n_class(nmax)];
+    const rl::KernelShape ks = ctx->tuning[precision][rl::tuning_class(nmax, masses)];
 
     std::vector<rl::MapParams> params((size_t)n_maps);
     std::vector<rl::WorkItem> items;

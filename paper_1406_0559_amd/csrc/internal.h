@@ -6,7 +6,28 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "raylens.h"
+
+#define RL_TRY(expr)                      \
+    do {                                  \
+        rl_status st_ = (expr);           \
+        if (st_ != RL_OK) return st_;     \
+    } while (0)
+
 namespace rl {
+
+// Error reporting shared by the C-ABI sources: sets the calling thread's
+// rl_last_error() text (printf-style) and returns st.
+rl_status set_error(rl_status st, const char* fmt, ...);
+void clear_error();
+// HIP device ordinal of a context.
+int context_device(const rl_context* ctx);
+// Tuning classes: lens-count class 0 (N < 1000), 1 (N < 10000), 2; plus 3
+// for lens fields with masses.
+constexpr int kTuningClasses = 6;
+inline int tuning_class(int64_t n, bool masses) {
+    return (n < 1000 ? 0 : (n < 10000 ? 1 : 2)) + (masses ? 3 : 0);
+}
 
 // Rays per origin cell and per wave: one wave of 64 lanes holds 16 rays per
 // lane. A cell is the unit whose centre the FP32 lens coordinates are

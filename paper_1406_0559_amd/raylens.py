@@ -110,6 +110,7 @@ def load():
         "rl_codec_decode": [vp, vp, i32, vp, i64, P(rl_window), vp, vp],
         "rl_source_kernel": [vp, P(rl_profile), P(rl_window), vp, vp],
         "rl_convolve": [vp, vp, vp, P(rl_window), dbl, vp, vp],
+        "rl_autotune": [vp, C.c_char_p, i32],
         "rl_get_tuning": [vp, C.c_int, i32, P(rl_tuning)],
         "rl_set_tuning": [vp, C.c_int, i32, P(rl_tuning)],
     }
@@ -233,6 +234,10 @@ def rl_source_kernel(ctx, profile, win, d_kernel, stream=None):
 
 def rl_convolve(ctx, d_counts, d_kernel, win, n_avg, d_out, stream=None):
     _check(load().rl_convolve(ctx, d_counts, d_kernel, C.byref(win), n_avg, d_out, stream))
+
+
+def rl_autotune(ctx, cache_path=None, budget_ms=0):
+    _check(load().rl_autotune(ctx, None if cache_path is None else str(cache_path).encode(), budget_ms))
 
 
 def rl_get_tuning(ctx, precision, n_class) -> rl_tuning:
@@ -476,6 +481,9 @@ class Context:
                     out.data_ptr(), _stream_ptr(stream))
         return out
 
+    def autotune(self, cache_path=None, budget_ms=0):
+        rl_autotune(self.handle, cache_path, budget_ms)
+
     def get_tuning(self, precision, n_class):
         t = rl_get_tuning(self.handle, PRECISIONS[precision], n_class)
         return {f: getattr(t, f) for f, _ in rl_tuning._fields_}
@@ -505,4 +513,17 @@ def _check_counts(counts, spec):
 
 
 def n_class(n: int) -> int:
+    """Lens-count class: 0 (n < 1000), 1 (n < 10000), 2."""
     return 0 if n < 1000 else (1 if n < 10000 else 2)
+
+
+TUNING_CLASSES = 6
+
+
+def tuning_class(n: int, masses: bool) -> int:
+    """Tuning class of a lens field: its lens-count class, plus 3 with masses."""
+    return n_class(n) + (3 if masses else 0)
+
+
+def spec_tuning_class(spec) -> int:
+    return tuning_class(spec.n_lens, spec.masses != "unit")

@@ -228,7 +228,7 @@ SHAPES = [dict(rays_x=4, rays_y=4, lens_tile=256, waves=4, submap=1),
 def test_results_do_not_depend_on_kernel_shape(ctx, spec):
     f = spec.lenses()
     L = dev_lenses(f)
-    cls = rl.n_class(spec.n_lens)
+    cls = rl.spec_tuning_class(spec)
     saved = ctx.get_tuning("fp32c", cls)
     ref = None
     try:
@@ -296,11 +296,11 @@ def test_batch_with_two_cells_per_wave_equals_alone(ctx):
     fields = [s.lenses() for s in specs]
     Ls = [dev_lenses(f) for f in fields]
     alone = [ctx.shoot(L, s, "fp32c") for L, s in zip(Ls, specs)]
-    saved = {c: ctx.get_tuning("fp32c", c) for c in range(3)}
+    saved = {c: ctx.get_tuning("fp32c", c) for c in range(rl.TUNING_CLASSES)}
     try:
         for sh in (dict(rays_x=4, rays_y=8, lens_tile=256, waves=4, submap=1, item_cells=3),
                    dict(rays_x=8, rays_y=4, lens_tile=128, waves=1, submap=2, item_cells=1)):
-            for c in range(3):
+            for c in range(rl.TUNING_CLASSES):
                 ctx.set_tuning("fp32c", c, **sh)
             outs = [ctx.new_map(s) for s in specs]
             ctx.shoot_batch([(L, s, c, e) for L, s, (c, e) in zip(Ls, specs, outs)], "fp32c")
@@ -308,7 +308,7 @@ def test_batch_with_two_cells_per_wave_equals_alone(ctx):
                 assert torch.equal(c, ca), (s.name, sh)
                 assert int(e.item()) == int(ea.item()), (s.name, sh)
     finally:
-        for c in range(3):
+        for c in range(rl.TUNING_CLASSES):
             ctx.set_tuning("fp32c", c, **saved[c])
 
 
