@@ -15,6 +15,7 @@ for the dominant kernel (timed with events on the stream it runs on) and the
 oracle's rate on a bounded sample on the host cores.
 """
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -47,6 +48,9 @@ def parse():
                     help="map-size scale of the served requests (1.0 = 1024^2-4096^2 maps)")
     ap.add_argument("--no-tuning-cache", action="store_true")
     ap.add_argument("--no-post", action="store_true", help="skip the MPD and codec legs")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-mass 11560-lens map timed beside the main workload")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the lens-count sweep at 1e8 rays")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a known-size "
                          "kernel for scaling hardware traffic counters)")
@@ -255,6 +259,60 @@ def main():
         batch = {"workload": "batch-64x1024sq", "maps": len(maps), "seconds": wb,
                  "maps_per_hour": len(maps) * 3600.0 / wb, "evals_per_s": bevals / wb}
 
+    # ---- second full-size workload: mixed masses, smooth matter, 11560 lenses -------
+    mixed = None
+    if not args.no_mixed and args.workload != "mixed-20000sq-11560":
+        ms_ = inputs.config_mixed()
+        fm = ms_.lenses()
+        Lm = rl.DeviceLenses(fm.x1, fm.x2, fm.m)
+        cm, em = ctx.new_map(ms_)
+        evm = []
+        for k in range(3):
+            cm.zero_()
+            em.zero_()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            ctx.shoot(Lm, ms_, "fp32c", cm, em, stream=stream)
+            b.record(stream)
+            b.synchronize()
+            if k:
+                evm.append(a.elapsed_time(b))
+        km = float(np.mean(evm)) / 1e3
+        mixed = {"workload": ms_.name, "lenses": ms_.n_lens, "masses": ms_.masses,
+                 "kernel_ms": km * 1e3, "evals_per_s": ms_.evals / km,
+                 "tflops_alg": FLOPS_PER_EVAL * ms_.evals / km / 1e12,
+                 "frac": FLOPS_PER_EVAL * ms_.evals / km / 1e12 / FP32_PEAK_TFLOPS}
+        del Lm, cm, em
+
+    # ---- N_* sweep: evaluations/s against the lens count at 1e8 rays --------------
+    sweep = None
+    if not args.no_sweep:
+        base = inputs.config_gerlumph()
+        sweep = []
+        for n_l in (50, 100, 300, 1000, 3000, 10000, 30000, 100000):
+            sp = inputs.scaled(base, ray_factor=(1e8 / base.rays) ** 0.5, name=f"nstar-{n_l}")
+            sp = dataclasses.replace(sp, n_lens=n_l,
+                                            disc_radius=(n_l / base.kappa_star) ** 0.5, seed=7)
+            fs = sp.lenses()
+            Ls_ = rl.DeviceLenses(fs.x1, fs.x2, fs.m)
+            cs, es = ctx.new_map(sp)
+            best = None
+            for k in range(3):
+                cs.zero_()
+                es.zero_()
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                ctx.shoot(Ls_, sp, "fp32c", cs, es, stream=stream)
+                b.record(stream)
+                b.synchronize()
+                if k:
+                    best = a.elapsed_time(b) if best is None else min(best, a.elapsed_time(b))
+            sweep.append({"n_lens": n_l, "rays": sp.rays, "kernel_ms": best,
+                          "evals_per_s": sp.evals / (best / 1e3)})
+            del Ls_, cs, es
+
     # ---- serving: Poisson stream of map requests, continuous batching -------------
     serving = None
     if not args.no_serve:
@@ -360,6 +418,8 @@ def main():
         "mu_th": st["mu_th"],
         "batch": batch,
         "post_processing": post,
+        "mixed_workload": mixed,
+        "nstar_sweep": sweep,
         "serving": serving,
         "tuning": "autotuned cache" if tuned else "defaults",
     }
