@@ -205,8 +205,9 @@ rl_status rl_shoot_batch(rl_context* ctx, const rl_map_desc* h_maps, int32_t n_m
 
 /* Kernel shape. None of these knobs changes any result bit: they only decide
  * how rays are spread over lanes and waves and how lenses are staged.
- *   rays_x, rays_y : rays per lane along x1 and x2 (product 16: 4x4, 2x8, 8x2)
- *   lens_tile      : lenses staged in LDS per pass (multiple of 128, <= 2048)
+ *   rays_x, rays_y : rays per lane along x1 and x2 (product 16: 4x4, 2x8, 8x2; or
+ *                    32: 4x8, 8x4, two ray cells per wave)
+ *   lens_tile      : lenses staged in LDS per pass (multiple of 256, <= 2048)
  *   waves          : waves per workgroup (1, 2 or 4)
  *   submap         : binning mode. 0 = one global atomic per binned ray; 1 = an
  *                    LDS-privatised sub-map over the bounding box of the

@@ -39,7 +39,7 @@ constexpr int kCellRays = kLanes * kRaysPerLane;
 // Lenses per compensation block: each block is summed in plain FP32 and the
 // block sums are added with TwoSum. Fixed, so results do not depend on the
 // LDS lens tile.
-constexpr int kBlock = 128;
+constexpr int kBlock = 256;
 // LDS-privatised sub-map edge (pixels).
 constexpr int kSub = 64;
 

@@ -338,10 +338,11 @@ struct Tuner {
         auto run = [&](rl_tuning t) -> rl_status {
             for (const Result& r : results)
                 if (same_shape(r.t, t)) return RL_OK;
-            rl_status st = rl_set_tuning(ctx, (rl_precision)prec, cls, &t);
-            if (st != RL_OK) return st;
+            // shapes this build does not support (e.g. a tile that is not a
+            // whole number of compensation blocks) are skipped
+            if (rl_set_tuning(ctx, (rl_precision)prec, cls, &t) != RL_OK) return RL_OK;
             double ms;
-            st = time_shoot(pr, prec, tm, &ms, &got);
+            const rl_status st = time_shoot(pr, prec, tm, &ms, &got);
             if (st != RL_OK) return st;
             if (ref.empty()) {
                 ref = got;
@@ -363,7 +364,7 @@ struct Tuner {
         std::sort(stage1.begin(), stage1.end(), [](const Result& a, const Result& b) { return a.ms < b.ms; });
         const size_t top = std::min<size_t>(2, stage1.size());
         for (size_t i = 0; i < top && time_left(); ++i)
-            for (int tile : {128, 256, 512, 1024})
+            for (int tile : {256, 512, 1024, 2048})
                 for (int waves : {1, 2, 4})
                     for (int sub : {1, 2}) {
                         if (!time_left()) break;

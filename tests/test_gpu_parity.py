@@ -212,14 +212,14 @@ def test_fp32_mixed_masses_near_critical_line_at_scale(ctx):
 # ---------------------------------------------------------------------------
 
 SHAPES = [dict(rays_x=4, rays_y=4, lens_tile=256, waves=4, submap=1),
-          dict(rays_x=2, rays_y=8, lens_tile=128, waves=1, submap=0),
+          dict(rays_x=2, rays_y=8, lens_tile=256, waves=1, submap=0),
           dict(rays_x=8, rays_y=2, lens_tile=2048, waves=2, submap=1),
           dict(rays_x=4, rays_y=4, lens_tile=512, waves=2, submap=0),
           dict(rays_x=2, rays_y=8, lens_tile=256, waves=4, submap=2),
-          dict(rays_x=4, rays_y=4, lens_tile=128, waves=1, submap=2),
+          dict(rays_x=4, rays_y=4, lens_tile=768, waves=1, submap=2),
           # 32 rays per lane, two cells per wave
           dict(rays_x=4, rays_y=8, lens_tile=256, waves=4, submap=1),
-          dict(rays_x=8, rays_y=4, lens_tile=128, waves=2, submap=2),
+          dict(rays_x=8, rays_y=4, lens_tile=512, waves=2, submap=2),
           dict(rays_x=4, rays_y=8, lens_tile=1024, waves=1, submap=0)]
 
 
@@ -299,7 +299,7 @@ def test_batch_with_two_cells_per_wave_equals_alone(ctx):
     saved = {c: ctx.get_tuning("fp32c", c) for c in range(rl.TUNING_CLASSES)}
     try:
         for sh in (dict(rays_x=4, rays_y=8, lens_tile=256, waves=4, submap=1, item_cells=3),
-                   dict(rays_x=8, rays_y=4, lens_tile=128, waves=1, submap=2, item_cells=1)):
+                   dict(rays_x=8, rays_y=4, lens_tile=256, waves=1, submap=2, item_cells=1)):
             for c in range(rl.TUNING_CLASSES):
                 ctx.set_tuning("fp32c", c, **sh)
             outs = [ctx.new_map(s) for s in specs]
