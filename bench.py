@@ -283,6 +283,22 @@ def main():
                  "kernel_ms": km * 1e3, "evals_per_s": ms_.evals / km,
                  "tflops_alg": FLOPS_PER_EVAL * ms_.evals / km / 1e12,
                  "frac": FLOPS_PER_EVAL * ms_.evals / km / 1e12 / FP32_PEAK_TFLOPS}
+        if args.fp64_steps > 0:        # the FP64-plain path on the same map, one launch
+            c64, e64 = ctx.new_map(ms_)
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            ctx.shoot(Lm, ms_, "fp64", c64, e64, stream=stream)
+            b.record(stream)
+            b.synchronize()
+            k64m = a.elapsed_time(b) / 1e3
+            st32 = ctx.stats(cm, em, ms_, stream=stream)
+            st64m = ctx.stats(c64, e64, ms_, stream=stream)
+            mixed.update({"fp64_kernel_ms": k64m * 1e3, "fp64_evals_per_s": ms_.evals / k64m,
+                          "speedup_fp32c_over_fp64": k64m / km,
+                          "mean_mu_rel_diff_fp32c": abs(st32["mean_mu"] - st64m["mean_mu"]) /
+                          abs(st64m["mean_mu"])})
+            del c64, e64
         del Lm, cm, em
 
     # ---- N_* sweep: evaluations/s against the lens count at 1e8 rays --------------
@@ -365,24 +381,31 @@ def main():
                          f"({rows * spec.n1} rays x {spec.n_lens} lenses, FP64, OpenMP), "
                          f"{tcpu:.1f} s"}
         # accuracy of the GPU positions on two sampled rows against the oracle
-        o1, o2, _, rmin = oracle.ray_positions(field.x1, field.x2, field.m, spec.kappa, spec.gamma,
-                                               spec.s, spec.n1, spec.n2, spec.c1, spec.c2, spec.h1,
-                                               spec.h2, r0, r0 + 2)
-        lo1, lo2 = spec.w1 - 0.5 * spec.W1 - 1.0, spec.w2 - 0.5 * spec.W2 - 1.0
-        inwin = (o1 >= lo1) & (o1 < lo1 + spec.W1 + 2.0) & (o2 >= lo2) & (o2 < lo2 + spec.W2 + 2.0)
-        far = inwin & (rmin >= 0.015)
-        acc = {"rows": [r0, r0 + 2], "rays_in_window": int(inwin.sum()),
-               "near_lens_rays": int((inwin & ~far).sum())}
-        for prec in ("fp32c", "fp64"):
-            g1, g2 = ctx.ray_positions(L, spec, prec, r0, r0 + 2)
-            g1 = g1.cpu().numpy()
-            g2 = g2.cpu().numpy()
-            err = np.hypot(g1 - o1, g2 - o2)
-            acc[prec] = {"max_abs_dy": float(err[far].max()) if far.any() else None,
-                         "rms_dy": float(np.sqrt(np.mean(err[far] ** 2))) if far.any() else None,
-                         "bit_identical": bool((g1.view(np.int64) == o1.view(np.int64)).all() and
-                                               (g2.view(np.int64) == o2.view(np.int64)).all())}
-        cpu["accuracy_vs_oracle"] = acc
+        def accuracy(sp, fl, Ld, rb):
+            o1, o2, _, rmin = oracle.ray_positions(fl.x1, fl.x2, fl.m, sp.kappa, sp.gamma, sp.s,
+                                                   sp.n1, sp.n2, sp.c1, sp.c2, sp.h1, sp.h2, rb, rb + 2)
+            lo1, lo2 = sp.w1 - 0.5 * sp.W1 - 1.0, sp.w2 - 0.5 * sp.W2 - 1.0
+            inwin = (o1 >= lo1) & (o1 < lo1 + sp.W1 + 2.0) & (o2 >= lo2) & (o2 < lo2 + sp.W2 + 2.0)
+            far = inwin & (rmin >= 0.015)
+            acc = {"workload": sp.name, "rows": [rb, rb + 2], "rays_in_window": int(inwin.sum()),
+                   "near_lens_rays": int((inwin & ~far).sum())}
+            for prec in ("fp32c", "fp64"):
+                g1, g2 = ctx.ray_positions(Ld, sp, prec, rb, rb + 2)
+                g1 = g1.cpu().numpy()
+                g2 = g2.cpu().numpy()
+                err = np.hypot(g1 - o1, g2 - o2)
+                acc[prec] = {"max_abs_dy": float(err[far].max()) if far.any() else None,
+                             "rms_dy": float(np.sqrt(np.mean(err[far] ** 2))) if far.any() else None,
+                             "bit_identical": bool((g1.view(np.int64) == o1.view(np.int64)).all() and
+                                                   (g2.view(np.int64) == o2.view(np.int64)).all())}
+            return acc
+
+        cpu["accuracy_vs_oracle"] = accuracy(spec, field, L, r0)
+        if mixed is not None:
+            ms2 = inputs.config_mixed()
+            fm2 = ms2.lenses()
+            cpu["accuracy_vs_oracle_mixed"] = accuracy(ms2, fm2, rl.DeviceLenses(fm2.x1, fm2.x2, fm2.m),
+                                                       ms2.n2 // 2)
 
     achieved = FLOPS_PER_EVAL * evals / kern_avg_s / 1e12
     traffic = measured_traffic(spec.name)

@@ -9,7 +9,7 @@
 //
 // K is scaled by a power of two before packing so that both spectra keep full
 // precision (see norms_kernel). Each axis is a batch of row FFTs in LDS, one
-// workgroup per row: mixed radix (2, 3, 4, 5), decimation in time from a
+// workgroup per row: mixed radix (16, 8, 4, 2, 3, 5), decimation in time from a
 // digit-reversed load for forward transforms and decimation in frequency with
 // a digit-reversed store for inverse ones, so no pass needs a separate
 // reordering. After a norm reduction, five passes over HBM:
@@ -50,17 +50,69 @@ __global__ void twiddle_kernel(cplx* __restrict__ tw, int n) {
     tw[k] = cplx{c, -s};
 }
 
-// In-place DFTs of 2, 3, 4 and 5 points: y_k = sum_q a_q exp(sg 2 pi i k q / r),
-// sg = -1 forward, +1 inverse.
+// In-place DFTs of 2, 3, 4, 5, 8 and 16 points:
+// y_k = sum_q a_q exp(sg 2 pi i k q / r), sg = -1 forward, +1 inverse.
 constexpr double kSin60 = 0.86602540378443864676;    // sqrt(3) / 2
 constexpr double kCos72 = 0.30901699437494742410;    // (sqrt(5) - 1) / 4
 constexpr double kCos144 = -0.80901699437494742410;  // -(sqrt(5) + 1) / 4
 constexpr double kSin72 = 0.95105651629515357212;
 constexpr double kSin144 = 0.58778525229247312917;
 
+// cos and sin of 2 pi m / 16, m = 0 .. 15
+constexpr double kC16[16] = {1.0, 0.92387953251128675613, 0.70710678118654752440,
+                             0.38268343236508977173, 0.0, -0.38268343236508977173,
+                             -0.70710678118654752440, -0.92387953251128675613, -1.0,
+                             -0.92387953251128675613, -0.70710678118654752440,
+                             -0.38268343236508977173, 0.0, 0.38268343236508977173,
+                             0.70710678118654752440, 0.92387953251128675613};
+constexpr double kS16[16] = {0.0, 0.38268343236508977173, 0.70710678118654752440,
+                             0.92387953251128675613, 1.0, 0.92387953251128675613,
+                             0.70710678118654752440, 0.38268343236508977173, 0.0,
+                             -0.38268343236508977173, -0.70710678118654752440,
+                             -0.92387953251128675613, -1.0, -0.92387953251128675613,
+                             -0.70710678118654752440, -0.38268343236508977173};
+
+template <int R>
+__device__ __forceinline__ void small_dft(cplx* a, double sg);
+
+// DFT of R = A B points as A-point DFTs, twiddles exp(sg 2 pi i q2 k1 / R) and
+// B-point DFTs: with q = B q1 + q2 and k = k1 + A k2,
+// y_k = sum_q2 w_R^(q2 k1) w_B^(q2 k2) sum_q1 a_(B q1 + q2) w_A^(q1 k1).
+template <int A, int B>
+__device__ __forceinline__ void composite_dft(cplx* a, double sg) {
+    constexpr int R = A * B;
+    cplx t[B][A];
+#pragma unroll
+    for (int q2 = 0; q2 < B; ++q2) {
+#pragma unroll
+        for (int q1 = 0; q1 < A; ++q1) t[q2][q1] = a[B * q1 + q2];
+        small_dft<A>(t[q2], sg);
+#pragma unroll
+        for (int k1 = 1; k1 < A; ++k1) {
+            if (q2 == 0) continue;
+            const int m = ((q2 * k1) % R) * (16 / R);   // index into the 16th roots
+            const cplx w = cplx{kC16[m], sg * kS16[m]};
+            t[q2][k1] = cmul(t[q2][k1], w);
+        }
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) {
+        cplx u[B];
+#pragma unroll
+        for (int q2 = 0; q2 < B; ++q2) u[q2] = t[q2][k1];
+        small_dft<B>(u, sg);
+#pragma unroll
+        for (int k2 = 0; k2 < B; ++k2) a[k1 + A * k2] = u[k2];
+    }
+}
+
 template <int R>
 __device__ __forceinline__ void small_dft(cplx* a, double sg) {
-    if constexpr (R == 2) {
+    if constexpr (R == 16) {
+        composite_dft<4, 4>(a, sg);
+    } else if constexpr (R == 8) {
+        composite_dft<4, 2>(a, sg);
+    } else if constexpr (R == 2) {
         const cplx t = a[1];
         a[1] = csub(a[0], t);
         a[0] = cadd(a[0], t);
@@ -95,7 +147,8 @@ __device__ __forceinline__ void small_dft(cplx* a, double sg) {
 
 }  // namespace
 
-// Mixed-radix plan of one FFT length n = r_0 r_1 ... r_{ns-1} (radices 2-5).
+// Mixed-radix plan of one FFT length n = r_0 r_1 ... r_{ns-1} (radices 16, 8,
+// 4, 2, 3, 5: the fewest LDS passes for powers of two).
 // L[s] = r_0 ... r_{s-1}; stage s joins n / L[s+1] groups of r_s transforms of
 // length L[s]. For L[s] > 1, div[s] = ceil(2^32 / L[s]) divides a butterfly
 // index by L[s] with one high multiply (exact for index * L[s] < 2^32).
@@ -108,7 +161,9 @@ struct FftPlan {
 
 namespace {
 
-bool make_plan(int n, FftPlan* P) {
+// max_pow2: the largest power-of-two radix to use (16, 8, 4 or 2), chosen so
+// that every thread of the workgroup has a butterfly in each stage.
+bool make_plan(int n, FftPlan* P, int max_pow2 = 16) {
     if (n < 2) return false;
     P->n = n;
     P->ns = 0;
@@ -119,8 +174,25 @@ bool make_plan(int n, FftPlan* P) {
         m /= r;
         return true;
     };
-    while (m % 4 == 0) if (!push(4)) return false;
-    while (m % 2 == 0) if (!push(2)) return false;
+    // powers of two: as many max_pow2 stages as fit, the remainder folded in
+    // so that a radix-2 stage is left only when nothing larger fits
+    int e = 0;
+    while (m % 2 == 0) { m /= 2; ++e; }
+    m = n;
+    const int k = max_pow2 >= 16 ? 4 : (max_pow2 >= 8 ? 3 : 2);
+    const int q = e / k, rem = e % k;
+    for (int i = 0; i < q; ++i) {
+        // the last full stage absorbs a single leftover factor 2 (R 2 = R/2 4)
+        const bool split = rem == 1 && i == q - 1 && k > 2;
+        if (split) {
+            if (!push(1 << (k - 1)) || !push(4)) return false;
+        } else if (!push(1 << k)) {
+            return false;
+        }
+    }
+    if (rem == 1 && (q == 0 || k == 2)) { if (!push(2)) return false; }
+    if (rem == 2) { if (!push(4)) return false; }
+    if (rem == 3) { if (!push(8)) return false; }
     while (m % 3 == 0) if (!push(3)) return false;
     while (m % 5 == 0) if (!push(5)) return false;
     if (m != 1) return false;
@@ -140,6 +212,8 @@ __device__ __forceinline__ int digit_pos(int i, const FftPlan& P) {
     for (int s = P.ns - 1; s >= 0; --s) {
         int d;
         switch (P.r[s]) {
+            case 16: d = i & 15; i >>= 4; break;
+            case 8: d = i & 7; i >>= 3; break;
             case 4: d = i & 3; i >>= 2; break;
             case 2: d = i & 1; i >>= 1; break;
             case 3: d = i % 3; i /= 3; break;
@@ -193,6 +267,8 @@ __device__ __forceinline__ void stage(cplx* buf, const FftPlan& P, int s, int ro
 template <bool DIF>
 __device__ void run_stage(cplx* buf, const FftPlan& P, int s, int rows, const cplx* tw, bool inverse) {
     switch (P.r[s]) {
+        case 16: stage<16, DIF>(buf, P, s, rows, tw, inverse); break;
+        case 8: stage<8, DIF>(buf, P, s, rows, tw, inverse); break;
         case 4: stage<4, DIF>(buf, P, s, rows, tw, inverse); break;
         case 2: stage<2, DIF>(buf, P, s, rows, tw, inverse); break;
         case 3: stage<3, DIF>(buf, P, s, rows, tw, inverse); break;
@@ -477,6 +553,18 @@ int grid_of(int64_t n, int cap) {
 
 // LDS size classes: rows up to 1024 / 4096 / 10240 points (16 / 64 / 160 KiB),
 // row pairs up to 512 / 2048 / 5120 points.
+// Threads per workgroup of the row and row-pair kernels for a length n.
+int row_threads(int n) { return n <= 1024 ? 256 : (n <= 4096 ? 512 : 1024); }
+int pair_threads(int n) { return n <= 512 ? 256 : (n <= 2048 ? 512 : 1024); }
+
+// Largest power-of-two radix r <= 16 with at least `threads` butterflies per
+// stage over `rows` rows of length n.
+int max_radix(int n, int rows, int threads) {
+    int r = 16;
+    while (r > 4 && (int64_t)rows * n / r < threads) r >>= 1;
+    return r;
+}
+
 template <int MODE>
 hipError_t rows(const int32_t* counts, const double* kern, cplx* z, double* out, int nrows,
                 const FftPlan& P, const cplx* tw, double scale, const double* bal, hipStream_t s) {
@@ -523,8 +611,11 @@ size_t convolve_scratch_bytes(int p1, int p2) {
 
 hipError_t launch_convolve(const int32_t* counts, const double* kernel, int p1, int p2, double n_avg,
                            double* out, void* scratch, hipStream_t s) {
-    FftPlan P1, P2;
-    if (!make_plan(p1, &P1) || !make_plan(p2, &P2) || p1 > kMaxFftSide || p2 > kMaxFftSide)
+    // plans for the x1 rows, the x2 row pairs and (long columns) the x2 rows
+    FftPlan P1, P2, P2r;
+    if (p1 > kMaxFftSide || p2 > kMaxFftSide || !make_plan(p1, &P1, max_radix(p1, 1, row_threads(p1))) ||
+        !make_plan(p2, &P2, max_radix(p2, 2, pair_threads(p2))) ||
+        !make_plan(p2, &P2r, max_radix(p2, 1, row_threads(p2))))
         return hipErrorInvalidValue;
     const int64_t n = (int64_t)p1 * p2;
     cplx* z = static_cast<cplx*>(scratch);              // p2 x p1
@@ -544,12 +635,12 @@ hipError_t launch_convolve(const int32_t* counts, const double* kernel, int p1, 
     if (p2 <= kMaxFftSide / 2) {
         e = pairs(t, p1, P2, tw2, s);                               // x2 forward, product, x2 inverse
     } else {
-        e = rows<kFwd>(nullptr, nullptr, t, nullptr, p1, P2, tw2, 1.0, bal, s);
+        e = rows<kFwd>(nullptr, nullptr, t, nullptr, p1, P2r, tw2, 1.0, bal, s);
         if (e == hipSuccess) {
             hipLaunchKernelGGL(product_kernel, dim3(grid_of(n, 8192)), dim3(256), 0, s, t, p1, p2);
             e = hipGetLastError();
         }
-        if (e == hipSuccess) e = rows<kInv>(nullptr, nullptr, t, nullptr, p1, P2, tw2, 1.0, bal, s);
+        if (e == hipSuccess) e = rows<kInv>(nullptr, nullptr, t, nullptr, p1, P2r, tw2, 1.0, bal, s);
     }
     if (e == hipSuccess) e = transpose(t, z, p1, p2, s);            // z: p2 x p1
     if (e == hipSuccess)
