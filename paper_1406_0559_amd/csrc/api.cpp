@@ -721,11 +721,13 @@ rl_status rl_mpd(rl_context* ctx, const int32_t* d_counts, const rl_window* win,
     const double step = (log_hi - log_lo) / (double)nbins;
     const double scale = n_avg * mu_ref;
     for (int k = 0; k < nthr; ++k) thr[k] = scale * std::pow(10.0, log_lo + (double)k * step);
-    hipError_t e = ctx->aux.acquire(bytes, stream);
+    const size_t thr_bytes = (bytes + 255) & ~(size_t)255;
+    hipError_t e = ctx->aux.acquire(thr_bytes + (size_t)rl::kMpdLut * sizeof(uint16_t), stream);
     if (e != hipSuccess) return hip_fail(e, "threshold scratch");
     RL_TRY(stage_send(ctx, ctx->aux.ptr, bytes, stream));
     e = rl::launch_mpd(d_counts, (int64_t)win->p1 * win->p2, static_cast<const double*>(ctx->aux.ptr),
-                       nthr, reinterpret_cast<unsigned long long*>(d_bins), stream);
+                       nthr, reinterpret_cast<uint16_t*>(static_cast<char*>(ctx->aux.ptr) + thr_bytes),
+                       reinterpret_cast<unsigned long long*>(d_bins), stream);
     hipError_t e2 = ctx->aux.release(stream);
     if (e == hipSuccess) e = e2;
     if (e != hipSuccess) return hip_fail(e, "mpd launch");

@@ -92,8 +92,8 @@ struct KernelShape {
     int32_t item_cells;        // cells per batch work item
 };
 
-// Launchers (shoot.hip; maps.hip from launch_count_hist on). Each returns the
-// hipError_t of the launch.
+// Launchers (shoot.hip; maps.hip from launch_normalise on, except
+// launch_fill_u32). Each returns the hipError_t of the launch.
 hipError_t launch_prep_lenses(const double* x1, const double* x2, const double* m, int64_t n,
                               float4* out_xy, float* out_m, bool write_unit_mass,
                               hipStream_t stream);
@@ -114,7 +114,8 @@ hipError_t launch_count_stats(const int32_t* counts, int64_t n, unsigned long lo
 hipError_t launch_fill_u32(unsigned int* p, int64_t n, unsigned int v, hipStream_t stream);
 hipError_t launch_count_hist(const int32_t* counts, int64_t n, int64_t n_values,
                              unsigned long long* hist, hipStream_t stream);
-hipError_t launch_mpd(const int32_t* counts, int64_t n, const double* thr, int nthr,
+// lut: device scratch of kMpdLut uint16 (the bin of every count below kMpdLut)
+hipError_t launch_mpd(const int32_t* counts, int64_t n, const double* thr, int nthr, uint16_t* lut,
                       unsigned long long* bins, hipStream_t stream);
 hipError_t launch_prob_sum(const int32_t* counts, int64_t n, double n_avg, double mu_lim,
                            unsigned long long* out, hipStream_t stream);
@@ -122,6 +123,7 @@ hipError_t launch_mpd_moments(const unsigned long long* bins, int n_maps, int n_
                               double* mean, double* stdev, hipStream_t stream);
 
 constexpr int kMaxMpdBins = 4096;
+constexpr int kMpdLut = 4096;   // count values binned through a table
 
 // Indexed-map codec: flag/rank the distinct values of a count histogram
 // (exclusive scan; *total = number of distinct values), then pack / unpack.

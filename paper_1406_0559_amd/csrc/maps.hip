@@ -1,5 +1,5 @@
 // HIP kernels for the statistics and storage of finished maps on gfx950:
-// count histograms, binned magnification probability distributions and
+// normalisation to magnification and map statistics (eq. 4), count histograms, binned magnification probability distributions and
 // probability sums (Vernardos & Fluke 2014, Section 3.2.1 and Section 4), the
 // mean and spread of MPDs over lens realisations, and the indexed-map codec
 // (Appendix B). All are single passes over the int32 count map, bound by HBM
@@ -11,6 +11,79 @@
 
 namespace rl {
 namespace {
+
+// Calls f(v) for every count of c[0 .. n) once, over the whole grid: 16-byte
+// vector loads for the aligned body, scalar loads for the few counts before
+// and after it.
+template <typename F>
+__device__ __forceinline__ void grid_counts(const int32_t* __restrict__ c, int64_t n, F&& f) {
+    const uintptr_t addr = reinterpret_cast<uintptr_t>(c);
+    int64_t head = (int64_t)(((16u - (unsigned)(addr & 15u)) & 15u) >> 2);
+    if (head > n) head = n;
+    const int64_t nv = (n - head) >> 2;
+    const int64_t tail0 = head + nv * 4;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    const int4* __restrict__ v = reinterpret_cast<const int4*>(c + head);
+    for (int64_t k = tid; k < nv; k += nth) {
+        const int4 q = v[k];
+        f(q.x);
+        f(q.y);
+        f(q.z);
+        f(q.w);
+    }
+    if (tid < head) f(c[tid]);
+    if (tid < n - tail0) f(c[tail0 + tid]);
+}
+
+// ----------------------------------------------------------------------------
+// normalisation and map statistics (eq. 4)
+// ----------------------------------------------------------------------------
+
+__global__ void normalise_kernel(const int32_t* __restrict__ counts, int64_t n, double n_avg,
+                                 float* __restrict__ mu) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x)
+        mu[k] = (float)((double)counts[k] / n_avg);
+}
+
+__global__ void __launch_bounds__(256) count_stats_kernel(const int32_t* __restrict__ counts,
+                                                          int64_t n,
+                                                          unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long ssum[4];
+    __shared__ unsigned long long sneg[4];
+    __shared__ int smax[4];
+    unsigned long long s = 0, neg = 0;
+    int mx = 0;
+    grid_counts(counts, n, [&](int v) {
+        if (v < 0) neg += 1;
+        else s += (unsigned long long)(unsigned)v;
+        mx = v > mx ? v : mx;
+    });
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        s += __shfl_xor(s, o);
+        neg += __shfl_xor(neg, o);
+        const int t = __shfl_xor(mx, o);
+        mx = t > mx ? t : mx;
+    }
+    const int w = threadIdx.x / kLanes;
+    if ((threadIdx.x % kLanes) == 0) { ssum[w] = s; sneg[w] = neg; smax[w] = mx; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long bs = 0, bn = 0;
+        int bm = 0;
+        for (int i = 0; i < (int)(blockDim.x / kLanes); ++i) {
+            bs += ssum[i];
+            bn += sneg[i];
+            bm = smax[i] > bm ? smax[i] : bm;
+        }
+        atomicAdd(&out[0], bs);
+        atomicMax(&out[1], (unsigned long long)bm);
+        if (bn) atomicAdd(&out[2], bn);
+    }
+}
+
 
 // ----------------------------------------------------------------------------
 // magnification probability distributions (Section 3.2.1 and Section 4)
@@ -28,41 +101,54 @@ __global__ void __launch_bounds__(256) count_hist_kernel(const int32_t* __restri
     for (int e = threadIdx.x; e < nl; e += blockDim.x) sh[e] = 0;
     __syncthreads();
     const int64_t last = n_values - 1;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        int64_t c = counts[k];
-        c = c < 0 ? 0 : c;
+    grid_counts(counts, n, [&](int cv) {
+        const int64_t c = cv < 0 ? 0 : cv;
         const int64_t v = c < last ? c : last;
         if (v < nl) atomicAdd(&sh[v], 1u);
         else atomicAdd(&hist[v], 1ull);
-    }
+    });
     __syncthreads();
     for (int e = threadIdx.x; e < nl; e += blockDim.x)
         if (sh[e]) atomicAdd(&hist[e], (unsigned long long)sh[e]);
 }
 
-// Binned MPD: bin = number of count thresholds <= N (thresholds ascending), so
-// bin 0 is the underflow and bin nthr the overflow. Thresholds and bins in LDS.
+// Bin of a count: the number of thresholds <= N (thresholds ascending), so
+// bin 0 is the underflow and bin nthr the overflow.
+__device__ __forceinline__ int mpd_bin(const double* __restrict__ st, int nthr, double c) {
+    int lo = 0, hi = nthr;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (st[mid] <= c) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// lut[v] = bin of the count v for v < kMpdLut: counts are integers, so the
+// decision for each value is taken once per call instead of once per pixel.
+__global__ void mpd_lut_kernel(const double* __restrict__ thr, int nthr, uint16_t* __restrict__ lut) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < kMpdLut) lut[v] = (uint16_t)mpd_bin(thr, nthr, (double)v);
+}
+
+// Binned MPD. Thresholds, the value table and the bins live in LDS; counts
+// outside [0, kMpdLut) are searched directly.
 __global__ void __launch_bounds__(256) mpd_kernel(const int32_t* __restrict__ counts, int64_t n,
                                                   const double* __restrict__ thr, int nthr,
+                                                  const uint16_t* __restrict__ lut,
                                                   unsigned long long* __restrict__ bins) {
     extern __shared__ __align__(16) char smem[];
     double* st = reinterpret_cast<double*>(smem);
     unsigned int* sb = reinterpret_cast<unsigned int*>(st + nthr);
+    uint16_t* sl = reinterpret_cast<uint16_t*>(sb + nthr + 1);
     for (int e = threadIdx.x; e < nthr; e += blockDim.x) st[e] = thr[e];
     for (int e = threadIdx.x; e <= nthr; e += blockDim.x) sb[e] = 0;
+    for (int e = threadIdx.x; e < kMpdLut; e += blockDim.x) sl[e] = lut[e];
     __syncthreads();
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        const double c = (double)counts[k];
-        int lo = 0, hi = nthr;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (st[mid] <= c) lo = mid + 1;
-            else hi = mid;
-        }
-        atomicAdd(&sb[lo], 1u);
-    }
+    grid_counts(counts, n, [&](int cv) {
+        const int b = (unsigned)cv < (unsigned)kMpdLut ? (int)sl[cv] : mpd_bin(st, nthr, (double)cv);
+        atomicAdd(&sb[b], 1u);
+    });
     __syncthreads();
     for (int e = threadIdx.x; e <= nthr; e += blockDim.x)
         if (sb[e]) atomicAdd(&bins[e], (unsigned long long)sb[e]);
@@ -74,9 +160,7 @@ __global__ void __launch_bounds__(256) prob_sum_kernel(const int32_t* __restrict
                                                        unsigned long long* __restrict__ out) {
     __shared__ unsigned long long part[4];
     unsigned long long below = 0;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
-         k += (int64_t)gridDim.x * blockDim.x)
-        below += ((double)counts[k] / n_avg < mu_lim) ? 1ull : 0ull;
+    grid_counts(counts, n, [&](int cv) { below += ((double)cv / n_avg < mu_lim) ? 1ull : 0ull; });
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) below += __shfl_xor(below, o);
     if ((threadIdx.x % kLanes) == 0) part[threadIdx.x / kLanes] = below;
@@ -248,27 +332,47 @@ int grid_for(int64_t n, int threads, int cap) {
 
 }  // namespace
 
+hipError_t launch_normalise(const int32_t* counts, int64_t n, double n_avg, float* mu,
+                            hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(normalise_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, counts, n,
+                       n_avg, mu);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_stats(const int32_t* counts, int64_t n, unsigned long long* out,
+                              hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    // few blocks: every block ends in device-scope atomics on the same three words
+    hipLaunchKernelGGL(count_stats_kernel, dim3(grid_for(n, 256 * 64, 512)), dim3(256), 0, s, counts, n,
+                       out);
+    return hipGetLastError();
+}
+
 hipError_t launch_count_hist(const int32_t* counts, int64_t n, int64_t n_values,
                              unsigned long long* hist, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(count_hist_kernel, dim3(grid_for(n, 256 * 16, 2048)), dim3(256), 0, s, counts,
+    // fewer, longer blocks: each one zeroes and flushes its LDS histogram once
+    hipLaunchKernelGGL(count_hist_kernel, dim3(grid_for(n, 256 * 64, 512)), dim3(256), 0, s, counts,
                        n, n_values, hist);
     return hipGetLastError();
 }
 
-hipError_t launch_mpd(const int32_t* counts, int64_t n, const double* thr, int nthr,
+hipError_t launch_mpd(const int32_t* counts, int64_t n, const double* thr, int nthr, uint16_t* lut,
                       unsigned long long* bins, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    const size_t lds = (size_t)nthr * sizeof(double) + (size_t)(nthr + 1) * sizeof(unsigned int);
-    hipLaunchKernelGGL(mpd_kernel, dim3(grid_for(n, 256 * 16, 2048)), dim3(256), lds, s, counts, n,
-                       thr, nthr, bins);
+    hipLaunchKernelGGL(mpd_lut_kernel, dim3((kMpdLut + 255) / 256), dim3(256), 0, s, thr, nthr, lut);
+    const size_t lds = (size_t)nthr * sizeof(double) + (size_t)(nthr + 1) * sizeof(unsigned int) +
+                       (size_t)kMpdLut * sizeof(uint16_t);
+    hipLaunchKernelGGL(mpd_kernel, dim3(grid_for(n, 256 * 64, 512)), dim3(256), lds, s, counts, n,
+                       thr, nthr, lut, bins);
     return hipGetLastError();
 }
 
 hipError_t launch_prob_sum(const int32_t* counts, int64_t n, double n_avg, double mu_lim,
                            unsigned long long* out, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(prob_sum_kernel, dim3(grid_for(n, 256 * 16, 2048)), dim3(256), 0, s, counts, n,
+    hipLaunchKernelGGL(prob_sum_kernel, dim3(grid_for(n, 256 * 64, 512)), dim3(256), 0, s, counts, n,
                        n_avg, mu_lim, out);
     return hipGetLastError();
 }

@@ -580,52 +580,6 @@ __global__ void bin_positions_kernel(const double* __restrict__ y1, const double
     if ((threadIdx.x % kLanes) == 0 && esc) atomicAdd(escaped, (unsigned long long)esc);
 }
 
-__global__ void normalise_kernel(const int32_t* __restrict__ counts, int64_t n, double n_avg,
-                                 float* __restrict__ mu) {
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
-         k += (int64_t)gridDim.x * blockDim.x)
-        mu[k] = (float)((double)counts[k] / n_avg);
-}
-
-__global__ void __launch_bounds__(256) count_stats_kernel(const int32_t* __restrict__ counts,
-                                                          int64_t n,
-                                                          unsigned long long* __restrict__ out) {
-    __shared__ unsigned long long ssum[4];
-    __shared__ unsigned long long sneg[4];
-    __shared__ int smax[4];
-    unsigned long long s = 0, neg = 0;
-    int mx = 0;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        const int v = counts[k];
-        if (v < 0) neg += 1;
-        else s += (unsigned long long)(unsigned)v;
-        mx = v > mx ? v : mx;
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        s += __shfl_xor(s, o);
-        neg += __shfl_xor(neg, o);
-        const int t = __shfl_xor(mx, o);
-        mx = t > mx ? t : mx;
-    }
-    const int w = threadIdx.x / kLanes;
-    if ((threadIdx.x % kLanes) == 0) { ssum[w] = s; sneg[w] = neg; smax[w] = mx; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long bs = 0, bn = 0;
-        int bm = 0;
-        for (int i = 0; i < (int)(blockDim.x / kLanes); ++i) {
-            bs += ssum[i];
-            bn += sneg[i];
-            bm = smax[i] > bm ? smax[i] : bm;
-        }
-        atomicAdd(&out[0], bs);
-        atomicMax(&out[1], (unsigned long long)bm);
-        if (bn) atomicAdd(&out[2], bn);
-    }
-}
-
 __global__ void fill_u32_kernel(unsigned int* p, int64_t n, unsigned int v) {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
          k += (int64_t)gridDim.x * blockDim.x)
@@ -801,22 +755,6 @@ hipError_t launch_bin_positions(const double* y1, const double* y2, int64_t n, i
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(bin_positions_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, y1, y2, n,
                        p1, p2, lo1, lo2, inv1, inv2, counts, escaped);
-    return hipGetLastError();
-}
-
-hipError_t launch_normalise(const int32_t* counts, int64_t n, double n_avg, float* mu,
-                            hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(normalise_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, counts, n,
-                       n_avg, mu);
-    return hipGetLastError();
-}
-
-hipError_t launch_count_stats(const int32_t* counts, int64_t n, unsigned long long* out,
-                              hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(count_stats_kernel, dim3(grid_for(n, 256 * 8, 1024)), dim3(256), 0, s, counts, n,
-                       out);
     return hipGetLastError();
 }
 
