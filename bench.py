@@ -375,8 +375,15 @@ def main():
                      spec.c1, spec.c2, spec.h1, spec.h2, spec.p1, spec.p2, spec.w1, spec.w2,
                      spec.W1, spec.W2, r0, r0 + rows)
         tcpu = time.perf_counter() - tc
+        # one thread on a few rows: the per-core rate
+        r1 = max(1, int(2.0 / max(per_row * nthreads, 1e-9)))
+        t1 = time.perf_counter()
+        oracle.shoot(field.x1, field.x2, field.m, spec.kappa, spec.gamma, spec.s, spec.n1, spec.n2,
+                     spec.c1, spec.c2, spec.h1, spec.h2, spec.p1, spec.p2, spec.w1, spec.w2,
+                     spec.W1, spec.W2, r0, r0 + r1, nthreads=1)
+        per_core = r1 * spec.n1 * spec.n_lens / (time.perf_counter() - t1)
         cpu = {"value": rows * spec.n1 * spec.n_lens / tcpu, "unit": "evals/s", "cores": nthreads,
-               "kind": "oracle",
+               "per_core_evals_per_s": per_core, "kind": "oracle",
                "sample": f"ray rows [{r0}, {r0 + rows}) of the {spec.n1}x{spec.n2} grid "
                          f"({rows * spec.n1} rays x {spec.n_lens} lenses, FP64, OpenMP), "
                          f"{tcpu:.1f} s"}

@@ -1,0 +1,31 @@
+"""The oracle's C code under AddressSanitizer and UndefinedBehaviorSanitizer
+(host code only): a C driver calls every oracle function on small and
+edge-case inputs (singular rays, non-finite positions, empty ranges, invalid
+arguments, codec widths 1-32 and ragged sizes); any out-of-bounds access,
+signed overflow or invalid conversion aborts the run."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
+def test_oracle_under_asan_and_ubsan(tmp_path):
+    exe = str(tmp_path / "oracle_sanitize")
+    cmd = ["gcc", "-std=c11", "-O1", "-g", "-fno-omit-frame-pointer", "-fopenmp", "-ffp-contract=off",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+           "-I", os.path.join(ROOT, "oracle"),
+           os.path.join(ROOT, "oracle", "oracle.c"),
+           os.path.join(ROOT, "tests", "native", "oracle_sanitize.c"), "-o", exe, "-lm"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    env = dict(os.environ, OMP_NUM_THREADS="2",
+               ASAN_OPTIONS="detect_leaks=0:abort_on_error=0",
+               UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "runtime error" not in r.stderr and "AddressSanitizer" not in r.stderr
+    assert "oracle sanitizer run ok" in r.stdout
