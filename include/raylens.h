@@ -109,6 +109,8 @@ typedef enum {
      * plain sequential FP64 evaluation of eq. 1 with no contraction). */
     RL_FP64_PLAIN = 1
 } rl_precision;
+/* Entry points take the precision as an int32_t holding one of these values
+ * (any other value is refused with RL_E_INVALID). */
 
 /* Map statistics (mapmeta.dat of Section 3.2.1, eq. 4). */
 typedef struct {
@@ -150,7 +152,7 @@ rl_status rl_n_avg(const rl_raygrid* grid, const rl_window* win, double* h_out);
  * both axes (lo = window centre - width/2); rays outside, with a non-finite
  * position, or exactly on a lens are escaped. Asynchronous on `stream`. */
 rl_status rl_shoot(rl_context* ctx, const rl_lenses* lenses, const rl_macro* macro,
-                   const rl_raygrid* grid, const rl_window* win, rl_precision precision,
+                   const rl_raygrid* grid, const rl_window* win, int32_t precision,
                    int64_t row_begin, int64_t row_end,
                    int32_t* d_counts, int64_t* d_escaped, hipStream_t stream);
 
@@ -178,7 +180,7 @@ rl_status rl_bin_positions(rl_context* ctx, const double* d_y1, const double* d_
  * row_begin) x n1 each), computed exactly as rl_shoot computes it for the
  * given precision. Asynchronous. */
 rl_status rl_ray_positions(rl_context* ctx, const rl_lenses* lenses, const rl_macro* macro,
-                           const rl_raygrid* grid, rl_precision precision,
+                           const rl_raygrid* grid, int32_t precision,
                            int64_t row_begin, int64_t row_end,
                            double* d_y1, double* d_y2, hipStream_t stream);
 
@@ -201,7 +203,7 @@ typedef struct {
  * sizes share the GPU. Results equal per-map rl_shoot calls bit for bit.
  * n_maps >= 0. Asynchronous; the descriptors are copied before return. */
 rl_status rl_shoot_batch(rl_context* ctx, const rl_map_desc* h_maps, int32_t n_maps,
-                         rl_precision precision, hipStream_t stream);
+                         int32_t precision, hipStream_t stream);
 
 /* Kernel shape. None of these knobs changes any result bit: they only decide
  * how rays are spread over lanes and waves and how lenses are staged.
@@ -229,9 +231,9 @@ typedef struct {
  * masses, 3, 4, 5 for the same lens counts with masses (rl_lenses.m != NULL;
  * a batch uses the class of its largest lens count, with masses if any map
  * has them). Host only. */
-rl_status rl_get_tuning(rl_context* ctx, rl_precision precision, int32_t n_class,
+rl_status rl_get_tuning(rl_context* ctx, int32_t precision, int32_t n_class,
                         rl_tuning* h_out);
-rl_status rl_set_tuning(rl_context* ctx, rl_precision precision, int32_t n_class,
+rl_status rl_set_tuning(rl_context* ctx, int32_t precision, int32_t n_class,
                         const rl_tuning* h_tuning);
 
 /* Autotuner (the "timed probes" tuning of the kernel shape; the method itself,

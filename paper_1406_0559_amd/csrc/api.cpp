@@ -87,7 +87,7 @@ rl_status check_lenses(const rl_lenses* l) {
     return RL_OK;
 }
 
-rl_status check_precision(rl_precision p) {
+rl_status check_precision(int32_t p) {
     if (p != RL_FP32_COMP && p != RL_FP64_PLAIN) return fail(RL_E_INVALID, "unknown precision");
     return RL_OK;
 }
@@ -376,7 +376,7 @@ rl_status rl_n_avg(const rl_raygrid* grid, const rl_window* win, double* h_out) 
     return RL_OK;
 }
 
-rl_status rl_get_tuning(rl_context* ctx, rl_precision precision, int32_t n_cls, rl_tuning* h_out) {
+rl_status rl_get_tuning(rl_context* ctx, int32_t precision, int32_t n_cls, rl_tuning* h_out) {
     g_error.clear();
     if (!ctx) return fail(RL_E_INVALID, "context is NULL");
     RL_TRY(check_precision(precision));
@@ -388,7 +388,7 @@ rl_status rl_get_tuning(rl_context* ctx, rl_precision precision, int32_t n_cls, 
     return RL_OK;
 }
 
-rl_status rl_set_tuning(rl_context* ctx, rl_precision precision, int32_t n_cls, const rl_tuning* t) {
+rl_status rl_set_tuning(rl_context* ctx, int32_t precision, int32_t n_cls, const rl_tuning* t) {
     g_error.clear();
     if (!ctx) return fail(RL_E_INVALID, "context is NULL");
     RL_TRY(check_precision(precision));
@@ -404,7 +404,7 @@ rl_status rl_set_tuning(rl_context* ctx, rl_precision precision, int32_t n_cls, 
 }
 
 rl_status rl_shoot(rl_context* ctx, const rl_lenses* lenses, const rl_macro* macro,
-                   const rl_raygrid* grid, const rl_window* win, rl_precision precision,
+                   const rl_raygrid* grid, const rl_window* win, int32_t precision,
                    int64_t row_begin, int64_t row_end, int32_t* d_counts, int64_t* d_escaped,
                    hipStream_t stream) {
     g_error.clear();
@@ -445,7 +445,7 @@ rl_status rl_shoot(rl_context* ctx, const rl_lenses* lenses, const rl_macro* mac
 }
 
 rl_status rl_ray_positions(rl_context* ctx, const rl_lenses* lenses, const rl_macro* macro,
-                           const rl_raygrid* grid, rl_precision precision, int64_t row_begin,
+                           const rl_raygrid* grid, int32_t precision, int64_t row_begin,
                            int64_t row_end, double* d_y1, double* d_y2, hipStream_t stream) {
     g_error.clear();
     if (!ctx) return fail(RL_E_INVALID, "context is NULL");
@@ -567,7 +567,7 @@ rl_status rl_stats_get(rl_context* ctx, const int32_t* d_counts, const int64_t* 
 }
 
 rl_status rl_shoot_batch(rl_context* ctx, const rl_map_desc* h_maps, int32_t n_maps,
-                         rl_precision precision, hipStream_t stream) {
+                         int32_t precision, hipStream_t stream) {
     g_error.clear();
     if (!ctx) return fail(RL_E_INVALID, "context is NULL");
     if (n_maps < 0) return fail(RL_E_INVALID, "n_maps must be >= 0");

@@ -301,7 +301,7 @@ struct Tuner {
             if (e == hipSuccess) e = hipMemsetAsync(pr.escaped.p, 0, sizeof(int64_t), nullptr);
             if (e == hipSuccess) e = hipEventRecord(tm.a, nullptr);
             if (e != hipSuccess) return rl::set_error(RL_E_DEVICE, hipGetErrorString(e));
-            rl_status st = rl_shoot(ctx, &pr.lenses, &pr.macro, &pr.grid, &pr.win, (rl_precision)prec,
+            rl_status st = rl_shoot(ctx, &pr.lenses, &pr.macro, &pr.grid, &pr.win, prec,
                                     0, pr.grid.n2, static_cast<int32_t*>(pr.counts.p),
                                     static_cast<int64_t*>(pr.escaped.p), nullptr);
             if (st != RL_OK) return st;
@@ -340,7 +340,7 @@ struct Tuner {
                 if (same_shape(r.t, t)) return RL_OK;
             // shapes this build does not support (e.g. a tile that is not a
             // whole number of compensation blocks) are skipped
-            if (rl_set_tuning(ctx, (rl_precision)prec, cls, &t) != RL_OK) return RL_OK;
+            if (rl_set_tuning(ctx, prec, cls, &t) != RL_OK) return RL_OK;
             double ms;
             const rl_status st = time_shoot(pr, prec, tm, &ms, &got);
             if (st != RL_OK) return st;
@@ -391,7 +391,7 @@ struct Tuner {
             for (int item : {4, 16, 64}) {
                 rl_tuning t = best;
                 t.item_cells = item;
-                RL_TRY(rl_set_tuning(ctx, (rl_precision)prec, cls, &t));
+                RL_TRY(rl_set_tuning(ctx, prec, cls, &t));
                 rl_map_desc d[3];
                 for (int i = 0; i < 3; ++i)
                     d[i] = rl_map_desc{bp[i].lenses, bp[i].macro, bp[i].grid, bp[i].win, 0, bp[i].grid.n2,
@@ -406,7 +406,7 @@ struct Tuner {
                     }
                     if ((e = hipEventRecord(tm.a, nullptr)) != hipSuccess)
                         return rl::set_error(RL_E_DEVICE, hipGetErrorString(e));
-                    RL_TRY(rl_shoot_batch(ctx, d, 3, (rl_precision)prec, nullptr));
+                    RL_TRY(rl_shoot_batch(ctx, d, 3, prec, nullptr));
                     e = hipEventRecord(tm.b, nullptr);
                     if (e == hipSuccess) e = hipEventSynchronize(tm.b);
                     float t2 = 0.0f;
@@ -421,7 +421,7 @@ struct Tuner {
             }
         }
         best.item_cells = item_best;
-        RL_TRY(rl_set_tuning(ctx, (rl_precision)prec, cls, &best));
+        RL_TRY(rl_set_tuning(ctx, prec, cls, &best));
 
         char head[512];
         std::snprintf(head, sizeof head,
@@ -487,11 +487,11 @@ bool apply_cache(rl_context* ctx, const char* path, const std::string& arch) {
     std::vector<rl_tuning> saved;
     for (const auto& t : todo) {
         rl_tuning cur;
-        if (rl_get_tuning(ctx, (rl_precision)t.first.first, t.first.second, &cur) != RL_OK) return false;
-        if (rl_set_tuning(ctx, (rl_precision)t.first.first, t.first.second, &t.second) != RL_OK) {
+        if (rl_get_tuning(ctx, t.first.first, t.first.second, &cur) != RL_OK) return false;
+        if (rl_set_tuning(ctx, t.first.first, t.first.second, &t.second) != RL_OK) {
             // undo what was applied so far
             for (size_t i = 0; i < saved.size(); ++i)
-                (void)rl_set_tuning(ctx, (rl_precision)todo[i].first.first, todo[i].first.second, &saved[i]);
+                (void)rl_set_tuning(ctx, todo[i].first.first, todo[i].first.second, &saved[i]);
             return false;
         }
         saved.push_back(cur);
@@ -541,7 +541,7 @@ extern "C" rl_status rl_autotune(rl_context* ctx, const char* cache_path, int32_
             if (st != RL_OK) return st;
             if (log) {
                 rl_tuning t;
-                (void)rl_get_tuning(ctx, (rl_precision)prec, cls, &t);
+                (void)rl_get_tuning(ctx, prec, cls, &t);
                 std::fprintf(stderr, "rl_autotune: %s class %d -> %dx%d tile %d waves %d submap %d item %d (%.1f s)\n",
                              prec_name(prec), cls, t.rays_x, t.rays_y, t.lens_tile, t.waves, t.submap,
                              t.item_cells, std::chrono::duration<double>(Clock::now() - t0).count());
