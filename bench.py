@@ -341,8 +341,15 @@ def main():
                                      size_scale=args.serve_scale)
         mreqs = [serve.MapRequest(r.rid, r.spec, r.spec.lenses(), r.arrival) for r in reqs]
         be = serve.GpuBackend(ctx=ctx)
+        done = [0]
+
+        def progress(res):
+            done[0] += 1
+            if done[0] % 25 == 0:
+                print(f"serving: {done[0]}/{len(mreqs)} requests finished", file=sys.stderr, flush=True)
+
         sch = serve.Scheduler(be, budget_bytes=serve.gpu_budget_bytes(0.5), max_active=16,
-                              chunk_evals=2e11, max_inflight=2)
+                              chunk_evals=2e11, max_inflight=2, on_finish=progress)
         ts = time.perf_counter()
         res = sch.run(mreqs)
         tserve = time.perf_counter() - ts

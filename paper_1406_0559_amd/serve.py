@@ -113,7 +113,8 @@ class Scheduler:
     def __init__(self, backend, budget_bytes: int, max_active: int = 16,
                  chunk_evals: float = 2.0e11, max_inflight: int = 2, aging_s: float = 5.0,
                  clock: Callable[[], float] = time.perf_counter, keep_mu: bool = False,
-                 sleep: Callable[[float], None] = time.sleep):
+                 sleep: Callable[[float], None] = time.sleep,
+                 on_finish: Optional[Callable[["MapResult"], None]] = None):
         self.backend = backend
         self.budget = int(budget_bytes)
         self.max_active = max_active
@@ -123,6 +124,7 @@ class Scheduler:
         self.clock = clock
         self.sleep = sleep
         self.keep_mu = keep_mu
+        self.on_finish = on_finish      # called once per request that reaches a final state
         self.t0 = clock()
         self.queue: collections.deque = collections.deque()
         self.active: Dict[int, _Active] = {}
@@ -145,9 +147,8 @@ class Scheduler:
             raise ValueError(f"request {req.rid} already submitted")
         fp = footprint_bytes(req.spec, req.lenses.n, req.lenses.m is not None)
         if fp > self.budget:
-            self.results[req.rid] = MapResult(req.rid, State.FAILED, arrival=req.arrival,
-                                              finished=self.now(),
-                                              error=f"footprint {fp} B exceeds the budget {self.budget} B")
+            self._record(MapResult(req.rid, State.FAILED, arrival=req.arrival, finished=self.now(),
+                                   error=f"footprint {fp} B exceeds the budget {self.budget} B"))
             return
         self.queue.append(req)
 
@@ -155,8 +156,7 @@ class Scheduler:
         for r in list(self.queue):
             if r.rid == rid:
                 self.queue.remove(r)
-                self.results[rid] = MapResult(rid, State.CANCELLED, arrival=r.arrival,
-                                              finished=self.now())
+                self._record(MapResult(rid, State.CANCELLED, arrival=r.arrival, finished=self.now()))
                 return True
         a = self.active.get(rid)
         if a is not None:
@@ -212,6 +212,11 @@ class Scheduler:
         return self.results
 
     # -------------------------------------------------------------- internals
+    def _record(self, res: "MapResult") -> None:
+        self.results[res.rid] = res
+        if self.on_finish is not None:
+            self.on_finish(res)
+
     def _rows_per_chunk(self, spec) -> int:
         per_row = max(1, spec.n1 * max(spec.n_lens, 1))
         rows = int(self.chunk_evals // per_row)
@@ -233,8 +238,8 @@ class Scheduler:
             try:
                 handle = self.backend.admit(req)
             except Exception as exc:   # allocation or upload failure
-                self.results[req.rid] = MapResult(req.rid, State.FAILED, arrival=req.arrival,
-                                                  finished=self.now(), error=repr(exc))
+                self._record(MapResult(req.rid, State.FAILED, arrival=req.arrival,
+                                       finished=self.now(), error=repr(exc)))
                 continue
             start = 0
             if req.resume is not None:
@@ -316,15 +321,14 @@ class Scheduler:
             res = MapResult(a.req.rid, State.FAILED, arrival=a.req.arrival, admitted=a.admitted,
                             finished=self.now(), error=repr(exc))
         self._release(a)
-        self.results[a.req.rid] = res
+        self._record(res)
 
     def _retire_if_idle(self, a: _Active) -> None:
         if a.inflight or not (a.cancelled or a.failed) or a.req.rid not in self.active:
             return      # still running, memory still referenced by a queued launch, or gone
         state = State.CANCELLED if a.cancelled else State.FAILED
-        self.results[a.req.rid] = MapResult(a.req.rid, state, arrival=a.req.arrival,
-                                            admitted=a.admitted, finished=self.now(),
-                                            error=a.failed)
+        self._record(MapResult(a.req.rid, state, arrival=a.req.arrival,
+                               admitted=a.admitted, finished=self.now(), error=a.failed))
         self._release(a)
 
     def _release(self, a: _Active) -> None:

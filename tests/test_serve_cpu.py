@@ -241,3 +241,13 @@ def test_duplicate_submission_is_rejected():
     sch.submit(r)
     with pytest.raises(ValueError):
         sch.submit(r)
+
+
+def test_on_finish_is_called_once_per_request():
+    seen = []
+    clock = Clock()
+    sch = make(clock, CpuBackend(clock), on_finish=lambda r: seen.append((r.rid, r.state)))
+    reqs = [small_request(i, 64, 128, 10, arrival=0.001 * i, p=16) for i in range(5)]
+    res = sch.run(reqs)
+    assert sorted(rid for rid, _ in seen) == sorted(res) == list(range(5))
+    assert all(st is State.DONE for _, st in seen)
