@@ -41,14 +41,6 @@ __device__ __forceinline__ cplx conj(cplx a) { return cplx{a.x, -a.y}; }
 // sg * i * a, sg = +1 or -1
 __device__ __forceinline__ cplx rot(cplx a, double sg) { return cplx{-sg * a.y, sg * a.x}; }
 
-// tw[k] = exp(-2 pi i k / n), k < n
-__global__ void twiddle_kernel(cplx* __restrict__ tw, int n) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    double s, c;
-    sincospi(2.0 * (double)k / (double)n, &s, &c);
-    tw[k] = cplx{c, -s};
-}
 
 // In-place DFTs of 2, 3, 4, 5, 8 and 16 points:
 // y_k = sum_q a_q exp(sg 2 pi i k q / r), sg = -1 forward, +1 inverse.
@@ -224,28 +216,55 @@ __device__ __forceinline__ int digit_pos(int i, const FftPlan& P) {
     return p;
 }
 
-// One stage over `rows` consecutive LDS rows of length n. DIT: twiddle, then
-// DFT; DIF: DFT, then twiddle. tw is exp(-2 pi i k / n); inverse conjugates.
+// LDS slot of element e of a row: the low four bits are XORed with the higher
+// nibbles, a bijection inside every 16-element block (16 complex doubles are
+// the 256 bytes of one pass over the 64 banks). Digit-reversed loads and the
+// first stages access elements at large power-of-two strides, which would
+// otherwise land on the same banks. Rows are padded to multiples of 16, so
+// the slot stays inside the row's region.
+__device__ __forceinline__ int swz(int e) { return e ^ (((e >> 4) ^ (e >> 8) ^ (e >> 12)) & 15); }
+
+// Twiddles in stage order: stage s stores w^(j q) = exp(-2 pi i j q / L[s+1])
+// for j < L[s], q = 1 .. r_s - 1 at tw[(L[s] - 1) + j (r_s - 1) + q - 1], so the
+// butterflies of consecutive j read consecutive entries. The stages hold
+// sum_s L[s] (r_s - 1) = n - 1 entries.
+__global__ void stage_twiddle_kernel(cplx* __restrict__ tw, FftPlan P) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= P.n - 1) return;
+    int s = 0;
+    while (s + 1 < P.ns && e >= P.L[s + 1] - 1) ++s;
+    const int local = e - (P.L[s] - 1);
+    const int r1 = P.r[s] - 1;
+    const int j = local / r1, q = local - j * r1 + 1;
+    double sn, cs;
+    sincospi(2.0 * (double)((int64_t)j * q) / (double)P.L[s + 1], &sn, &cs);
+    tw[e] = cplx{cs, -sn};
+}
+
+// One stage over `rows` LDS rows of length n, ld elements apart. DIT: twiddle,
+// then DFT; DIF: DFT, then twiddle; tw is the plan's stage-ordered twiddle
+// table, conjugated for the inverse.
 template <int R, bool DIF>
-__device__ __forceinline__ void stage(cplx* buf, const FftPlan& P, int s, int rows,
+__device__ __forceinline__ void stage(cplx* buf, const FftPlan& P, int s, int rows, int ld,
                                       const cplx* __restrict__ tw, bool inverse) {
     const int n = P.n, Ls = P.L[s], Ln = P.L[s + 1];
-    const int tstep = n / Ln;
     const int nb = n / R;
+    const cplx* __restrict__ tws = tw + (Ls - 1);
     const double sg = inverse ? 1.0 : -1.0;
     for (int b = threadIdx.x; b < rows * nb; b += blockDim.x) {
         int bb = b, row = 0;
         while (bb >= nb) { bb -= nb; ++row; }
         const int g = Ls == 1 ? bb : (int)__umulhi((unsigned)bb, P.div[s]);
         const int j = bb - g * Ls;
-        cplx* base = buf + row * n + g * Ln + j;
+        cplx* rb = buf + row * ld;
+        const int e0 = g * Ln + j;
         cplx a[R];
 #pragma unroll
-        for (int q = 0; q < R; ++q) a[q] = base[q * Ls];
+        for (int q = 0; q < R; ++q) a[q] = rb[swz(e0 + q * Ls)];
         if (!DIF) {
 #pragma unroll
             for (int q = 1; q < R; ++q) {
-                cplx w = tw[j * q * tstep];
+                cplx w = tws[j * (R - 1) + q - 1];
                 if (inverse) w.y = -w.y;
                 a[q] = cmul(a[q], w);
             }
@@ -254,40 +273,41 @@ __device__ __forceinline__ void stage(cplx* buf, const FftPlan& P, int s, int ro
         if (DIF) {
 #pragma unroll
             for (int q = 1; q < R; ++q) {
-                cplx w = tw[j * q * tstep];
+                cplx w = tws[j * (R - 1) + q - 1];
                 if (inverse) w.y = -w.y;
                 a[q] = cmul(a[q], w);
             }
         }
 #pragma unroll
-        for (int q = 0; q < R; ++q) base[q * Ls] = a[q];
+        for (int q = 0; q < R; ++q) rb[swz(e0 + q * Ls)] = a[q];
     }
 }
 
 template <bool DIF>
-__device__ void run_stage(cplx* buf, const FftPlan& P, int s, int rows, const cplx* tw, bool inverse) {
+__device__ void run_stage(cplx* buf, const FftPlan& P, int s, int rows, int ld, const cplx* tw,
+                          bool inverse) {
     switch (P.r[s]) {
-        case 16: stage<16, DIF>(buf, P, s, rows, tw, inverse); break;
-        case 8: stage<8, DIF>(buf, P, s, rows, tw, inverse); break;
-        case 4: stage<4, DIF>(buf, P, s, rows, tw, inverse); break;
-        case 2: stage<2, DIF>(buf, P, s, rows, tw, inverse); break;
-        case 3: stage<3, DIF>(buf, P, s, rows, tw, inverse); break;
-        default: stage<5, DIF>(buf, P, s, rows, tw, inverse); break;
+        case 16: stage<16, DIF>(buf, P, s, rows, ld, tw, inverse); break;
+        case 8: stage<8, DIF>(buf, P, s, rows, ld, tw, inverse); break;
+        case 4: stage<4, DIF>(buf, P, s, rows, ld, tw, inverse); break;
+        case 2: stage<2, DIF>(buf, P, s, rows, ld, tw, inverse); break;
+        case 3: stage<3, DIF>(buf, P, s, rows, ld, tw, inverse); break;
+        default: stage<5, DIF>(buf, P, s, rows, ld, tw, inverse); break;
     }
 }
 
 // Digit-reversed input -> natural-order transform.
-__device__ void dit(cplx* buf, const FftPlan& P, int rows, const cplx* tw, bool inverse) {
+__device__ void dit(cplx* buf, const FftPlan& P, int rows, int ld, const cplx* tw, bool inverse) {
     for (int s = 0; s < P.ns; ++s) {
-        run_stage<false>(buf, P, s, rows, tw, inverse);
+        run_stage<false>(buf, P, s, rows, ld, tw, inverse);
         __syncthreads();
     }
 }
 
 // Natural-order input -> digit-reversed transform (the transpose of dit).
-__device__ void dif(cplx* buf, const FftPlan& P, int rows, const cplx* tw, bool inverse) {
+__device__ void dif(cplx* buf, const FftPlan& P, int rows, int ld, const cplx* tw, bool inverse) {
     for (int s = P.ns - 1; s >= 0; --s) {
-        run_stage<true>(buf, P, s, rows, tw, inverse);
+        run_stage<true>(buf, P, s, rows, ld, tw, inverse);
         __syncthreads();
     }
 }
@@ -311,19 +331,19 @@ row_fft_kernel(const int32_t* __restrict__ counts, const double* __restrict__ ke
         const double sk = MODE == kFwdPack ? bal[0] : 1.0;
         for (int i = threadIdx.x; i < n; i += THREADS) {
             const int p = digit_pos(i, P);
-            if (MODE == kFwdPack) buf[p] = cplx{(double)counts[off + i], kern[off + i] * sk};
-            else buf[p] = z[off + i];
+            if (MODE == kFwdPack) buf[swz(p)] = cplx{(double)counts[off + i], kern[off + i] * sk};
+            else buf[swz(p)] = z[off + i];
         }
         __syncthreads();
-        dit(buf, P, 1, tw, false);
-        for (int i = threadIdx.x; i < n; i += THREADS) z[off + i] = buf[i];
+        dit(buf, P, 1, MAXN, tw, false);
+        for (int i = threadIdx.x; i < n; i += THREADS) z[off + i] = buf[swz(i)];
     } else {
-        for (int i = threadIdx.x; i < n; i += THREADS) buf[i] = z[off + i];
+        for (int i = threadIdx.x; i < n; i += THREADS) buf[swz(i)] = z[off + i];
         __syncthreads();
-        dif(buf, P, 1, tw, true);
+        dif(buf, P, 1, MAXN, tw, true);
         const double su = MODE == kInvOut ? bal[1] : 1.0;
         for (int i = threadIdx.x; i < n; i += THREADS) {
-            const cplx v = buf[digit_pos(i, P)];
+            const cplx v = buf[swz(digit_pos(i, P))];
             if (MODE == kInvOut) out[off + i] = (v.x * scale) * su;
             else z[off + i] = v;
         }
@@ -415,31 +435,32 @@ pair_kernel(cplx* __restrict__ t, int p1, FftPlan P, const cplx* __restrict__ tw
     const bool self = ua == ub;
     const int rows = self ? 1 : 2;
     cplx* A = buf;
-    cplx* B = buf + n;
+    cplx* B = buf + MAXN;
     for (int i = threadIdx.x; i < rows * n; i += THREADS) {
         const int r = i >= n, k = i - r * n;
-        buf[r * n + digit_pos(k, P)] = t[(int64_t)(r ? ub : ua) * n + k];
+        buf[r * MAXN + swz(digit_pos(k, P))] = t[(int64_t)(r ? ub : ua) * n + k];
     }
     __syncthreads();
-    dit(buf, P, rows, tw, false);
+    dit(buf, P, rows, MAXN, tw, false);
     for (int u = threadIdx.x; u < n; u += THREADS) {
         const int m = (n - u) % n;
+        const int su = swz(u), sm = swz(m);
         if (self) {
             if (m < u) continue;
-            const cplx pr = spectrum_product(A[u], A[m]);
-            A[u] = pr;
-            if (m != u) A[m] = conj(pr);
+            const cplx pr = spectrum_product(A[su], A[sm]);
+            A[su] = pr;
+            if (m != u) A[sm] = conj(pr);
         } else {
-            const cplx pr = spectrum_product(A[u], B[m]);
-            A[u] = pr;
-            B[m] = conj(pr);
+            const cplx pr = spectrum_product(A[su], B[sm]);
+            A[su] = pr;
+            B[sm] = conj(pr);
         }
     }
     __syncthreads();
-    dif(buf, P, rows, tw, true);
+    dif(buf, P, rows, MAXN, tw, true);
     for (int i = threadIdx.x; i < rows * n; i += THREADS) {
         const int r = i >= n, k = i - r * n;
-        t[(int64_t)(r ? ub : ua) * n + k] = buf[r * n + digit_pos(k, P)];
+        t[(int64_t)(r ? ub : ua) * n + k] = buf[r * MAXN + swz(digit_pos(k, P))];
     }
 }
 
@@ -606,7 +627,7 @@ bool fft_side_supported(int n) {
 
 size_t convolve_scratch_bytes(int p1, int p2) {
     const size_t plane = (size_t)p1 * p2 * sizeof(cplx);
-    return 2 * plane + (size_t)(p1 + p2) * sizeof(cplx) + (2 * kNormBlocks + 2) * sizeof(double) + 256;
+    return 2 * plane + (size_t)(p1 + 2 * p2) * sizeof(cplx) + (2 * kNormBlocks + 2) * sizeof(double) + 256;
 }
 
 hipError_t launch_convolve(const int32_t* counts, const double* kernel, int p1, int p2, double n_avg,
@@ -620,12 +641,14 @@ hipError_t launch_convolve(const int32_t* counts, const double* kernel, int p1, 
     const int64_t n = (int64_t)p1 * p2;
     cplx* z = static_cast<cplx*>(scratch);              // p2 x p1
     cplx* t = z + n;                                    // p1 x p2
-    cplx* tw1 = t + n;                                  // p1 twiddles
-    cplx* tw2 = tw1 + p1;                               // p2 twiddles
-    double* part = reinterpret_cast<double*>(tw2 + p2); // kNormBlocks x {|M|^2, |K|^2}
+    cplx* tw1 = t + n;                                  // stage twiddles of P1
+    cplx* tw2 = tw1 + p1;                               // ... of P2 (row pairs)
+    cplx* tw2r = tw2 + p2;                              // ... of P2r (rows)
+    double* part = reinterpret_cast<double*>(tw2r + p2); // kNormBlocks x {|M|^2, |K|^2}
     double* bal = part + 2 * kNormBlocks;               // {2^e, 2^-e}
-    hipLaunchKernelGGL(twiddle_kernel, dim3((p1 + 255) / 256), dim3(256), 0, s, tw1, p1);
-    hipLaunchKernelGGL(twiddle_kernel, dim3((p2 + 255) / 256), dim3(256), 0, s, tw2, p2);
+    hipLaunchKernelGGL(stage_twiddle_kernel, dim3((p1 + 255) / 256), dim3(256), 0, s, tw1, P1);
+    hipLaunchKernelGGL(stage_twiddle_kernel, dim3((p2 + 255) / 256), dim3(256), 0, s, tw2, P2);
+    hipLaunchKernelGGL(stage_twiddle_kernel, dim3((p2 + 255) / 256), dim3(256), 0, s, tw2r, P2r);
     hipLaunchKernelGGL(norms_kernel, dim3(kNormBlocks), dim3(256), 0, s, counts, kernel, n, part);
     hipLaunchKernelGGL(balance_kernel, dim3(1), dim3(256), 0, s, part, bal);
     // forward along x1 (rows of the map), Z = M + i 2^e K packed on the way in
@@ -635,12 +658,12 @@ hipError_t launch_convolve(const int32_t* counts, const double* kernel, int p1, 
     if (p2 <= kMaxFftSide / 2) {
         e = pairs(t, p1, P2, tw2, s);                               // x2 forward, product, x2 inverse
     } else {
-        e = rows<kFwd>(nullptr, nullptr, t, nullptr, p1, P2r, tw2, 1.0, bal, s);
+        e = rows<kFwd>(nullptr, nullptr, t, nullptr, p1, P2r, tw2r, 1.0, bal, s);
         if (e == hipSuccess) {
             hipLaunchKernelGGL(product_kernel, dim3(grid_of(n, 8192)), dim3(256), 0, s, t, p1, p2);
             e = hipGetLastError();
         }
-        if (e == hipSuccess) e = rows<kInv>(nullptr, nullptr, t, nullptr, p1, P2r, tw2, 1.0, bal, s);
+        if (e == hipSuccess) e = rows<kInv>(nullptr, nullptr, t, nullptr, p1, P2r, tw2r, 1.0, bal, s);
     }
     if (e == hipSuccess) e = transpose(t, z, p1, p2, s);            // z: p2 x p1
     if (e == hipSuccess)
