@@ -329,6 +329,46 @@ def main():
                           "evals_per_s": sp.evals / (best / 1e3)})
             del Ls_, cs, es
 
+    # ---- realisation batch: 15 lens fields of one macro model -> mean MPD +- sigma --
+    reals = None
+    if not args.no_batch:
+        from paper_1406_0559_amd import realisations
+        base = inputs.config_realisation_base()
+        rspecs = realisations.realisation_specs(base, 15)
+        rL = [rl.DeviceLenses(*(lambda f: (f.x1, f.x2, f.m))(sp.lenses())) for sp in rspecs]
+        routs = [ctx.new_map(sp) for sp in rspecs]
+        mu_th_r = abs(1.0 / ((1.0 - base.kappa) ** 2 - base.gamma ** 2))
+        navg_r = rl.rl_n_avg(rl.grid_of(base), rl.window_of(base))
+        rbins = torch.zeros((15, 102), dtype=torch.int64, device="cuda")
+
+        def run_reals():
+            for c, e in routs:
+                c.zero_()
+                e.zero_()
+            rbins.zero_()
+            ctx.shoot_batch([(Lr, sp, c, e) for Lr, sp, (c, e) in zip(rL, rspecs, routs)], "fp32c",
+                            stream=stream)
+            for r, (sp, (c, _)) in enumerate(zip(rspecs, routs)):
+                ctx.mpd(c, sp, mu_th_r, -1.5, 1.5, 100, n_avg=navg_r, bins=rbins[r], stream=stream)
+            return ctx.mpd_moments(rbins, base.p1 * base.p2, stream=stream)
+
+        run_reals()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        rmean, rstd = run_reals()
+        b.record(stream)
+        b.synchronize()
+        tr = a.elapsed_time(b) / 1e3
+        revals = sum(sp.evals for sp in rspecs)
+        reals = {"workload": f"realisations-15x{base.p1}sq-{base.n_lens}", "maps": 15,
+                 "lenses": base.n_lens, "seconds": tr, "evals_per_s": revals / tr,
+                 "maps_per_hour": 15 * 3600.0 / tr,
+                 "mean_mpd_peak_bin": int(torch.argmax(rmean).item()),
+                 "max_relative_sigma": float((rstd / rmean.clamp_min(1e-12))[rmean > 1e-3].max().item())}
+        del rL, routs
+
     # ---- serving: Poisson stream of map requests, continuous batching -------------
     serving = None
     if not args.no_serve:
@@ -456,6 +496,7 @@ def main():
         "batch": batch,
         "post_processing": post,
         "mixed_workload": mixed,
+        "realisations": reals,
         "nstar_sweep": sweep,
         "serving": serving,
         "tuning": "autotuned cache" if tuned else "defaults",

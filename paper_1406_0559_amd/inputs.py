@@ -221,6 +221,15 @@ def config_batch(n_maps: int = 64, pixels: int = 1024, seed0: int = 4) -> List[M
     return out
 
 
+def config_realisation_base(pixels: int = 1024) -> MapSpec:
+    """Base map of the realisation batches (Section 4's meanMPD tool: maps that
+    differ only in the random lens positions): the GERLUMPH-like macro model
+    (kappa = 0.41, gamma = 0.38, s = 0) on a 1024^2 map over 25 Einstein radii,
+    ~30 lensed rays per pixel, unit masses; realisations vary the seed."""
+    return _survey_geometry(0.41, 0.38, 0.0, pixels, 25.0, 30.0, 1.1, 1.2, 200, 20000, 6,
+                            "realisation-base")
+
+
 @dataclasses.dataclass
 class Request:
     rid: int

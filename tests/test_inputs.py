@@ -67,3 +67,12 @@ def test_generators_are_seeded():
     assert [r.spec.n_lens for r in r1] == [r.spec.n_lens for r in r2]
     assert all(500 <= r.spec.n_lens <= 50000 for r in r1)
     assert all(r1[i].arrival < r1[i + 1].arrival for i in range(19))
+
+
+def test_realisation_base_geometry():
+    b = inputs.config_realisation_base()
+    assert (b.kappa, b.gamma, b.s, b.p1, b.p2, b.W1) == (0.41, 0.38, 0.0, 1024, 1024, 25.0)
+    mu_th = abs(1.0 / ((1.0 - b.kappa) ** 2 - b.gamma ** 2))
+    n_avg = b.n1 * b.n2 / (4.0 * b.h1 * b.h2) * (b.W1 / b.p1) ** 2
+    assert abs(n_avg * mu_th - 30.0) < 0.5           # ~30 lensed rays per pixel
+    assert abs(b.disc_radius ** 2 * b.kappa_star - b.n_lens) < 1e-6 * b.n_lens
