@@ -67,7 +67,7 @@ typedef struct {
 /* Regular ray grid (Fig. 1): n1 x n2 rays at the centres of the cells of
  * [c1 - half1, c1 + half1) x [c2 - half2, c2 + half2), i.e. ray (i, j) sits at
  * x1 = (c1 - half1) + (i + 1/2) * 2 half1 / n1 and likewise for x2.
- * n1, n2 > 0; half-widths finite and > 0. */
+ * 0 < n1, n2 <= 2^40 and n1 n2 <= 2^50; half-widths finite and > 0. */
 typedef struct {
     int64_t n1;
     int64_t n2;
