@@ -288,7 +288,13 @@ class DeviceLenses:
     def n(self):
         return int(self.x1.numel())
 
-    def struct(self) -> rl_lenses:
+    def struct(self, device=None) -> rl_lenses:
+        """The C descriptor; with `device` given, the tensors must live there."""
+        if device is not None and self.n:
+            torch = _torch()
+            for name, t in (("x1", self.x1), ("x2", self.x2), ("m", self.m)):
+                if t is not None:
+                    _dev(t, torch.float64, self.n, f"lens {name}", device)
         return rl_lenses(self.x1.data_ptr() if self.n else None,
                          self.x2.data_ptr() if self.n else None,
                          None if self.m is None else self.m.data_ptr(), self.n)
@@ -332,8 +338,8 @@ class Context:
               row_begin=0, row_end=None, stream=None):
         if counts is None or escaped is None:
             counts, escaped = self.new_map(spec)
-        _check_map_tensors(counts, escaped, spec)
-        rl_shoot(self.handle, lenses.struct(), macro_of(spec), grid_of(spec), window_of(spec),
+        _check_map_tensors(counts, escaped, spec, self.device)
+        rl_shoot(self.handle, lenses.struct(self.device), macro_of(spec), grid_of(spec), window_of(spec),
                  PRECISIONS[precision], row_begin, spec.n2 if row_end is None else row_end,
                  counts.data_ptr(), escaped.data_ptr(), _stream_ptr(stream))
         return counts, escaped
@@ -346,7 +352,7 @@ class Context:
         dev = f"cuda:{self.device}"
         y1 = torch.empty((rows, spec.n1), dtype=torch.float64, device=dev)
         y2 = torch.empty((rows, spec.n1), dtype=torch.float64, device=dev)
-        rl_ray_positions(self.handle, lenses.struct(), macro_of(spec), grid_of(spec),
+        rl_ray_positions(self.handle, lenses.struct(self.device), macro_of(spec), grid_of(spec),
                          PRECISIONS[precision], row_begin, row_end, y1.data_ptr(), y2.data_ptr(),
                          _stream_ptr(stream))
         return y1, y2
@@ -355,11 +361,11 @@ class Context:
         torch = _torch()
         if counts is None or escaped is None:
             counts, escaped = self.new_map(spec)
-        _check_map_tensors(counts, escaped, spec)
+        _check_map_tensors(counts, escaped, spec, self.device)
         y1 = y1.contiguous()
         y2 = y2.contiguous()
-        if y1.dtype != torch.float64 or y2.dtype != torch.float64 or y1.numel() != y2.numel():
-            raise ValueError("positions must be float64 tensors of equal size")
+        _dev(y1, torch.float64, y1.numel(), "y1", self.device)
+        _dev(y2, torch.float64, y1.numel(), "y2", self.device)
         rl_bin_positions(self.handle, y1.data_ptr(), y2.data_ptr(), y1.numel(), window_of(spec),
                          counts.data_ptr(), escaped.data_ptr(), _stream_ptr(stream))
         return counts, escaped
@@ -370,15 +376,14 @@ class Context:
             n_avg = rl_n_avg(grid_of(spec), window_of(spec))
         if mu is None:
             mu = torch.empty((spec.p2, spec.p1), dtype=torch.float32, device=counts.device)
-        if counts.dtype != torch.int32 or counts.numel() != spec.p1 * spec.p2 or not counts.is_contiguous():
-            raise ValueError("counts must be a contiguous int32 p2 x p1 tensor")
-        if mu.dtype != torch.float32 or mu.numel() != spec.p1 * spec.p2 or not mu.is_contiguous():
-            raise ValueError("mu must be a contiguous float32 p2 x p1 tensor")
+        _dev(counts, torch.int32, spec.p1 * spec.p2, "counts", self.device)
+        _dev(mu, torch.float32, spec.p1 * spec.p2, "mu", self.device)
         rl_normalise(self.handle, counts.data_ptr(), window_of(spec), n_avg, mu.data_ptr(),
                      _stream_ptr(stream))
         return mu
 
     def stats(self, counts, escaped, spec, stream=None):
+        _check_map_tensors(counts, escaped, spec, self.device)
         st = rl_stats_get(self.handle, counts.data_ptr(), escaped.data_ptr(), macro_of(spec),
                           grid_of(spec), window_of(spec), _stream_ptr(stream))
         return {f: getattr(st, f) for f, _ in rl_stats._fields_}
@@ -390,17 +395,18 @@ class Context:
             lenses, spec, counts, escaped = it[:4]
             rb = it[4] if len(it) > 4 else 0
             re = it[5] if len(it) > 5 else spec.n2
-            _check_map_tensors(counts, escaped, spec)
-            descs.append(rl_map_desc(lenses.struct(), macro_of(spec), grid_of(spec), window_of(spec),
+            _check_map_tensors(counts, escaped, spec, self.device)
+            descs.append(rl_map_desc(lenses.struct(self.device), macro_of(spec), grid_of(spec), window_of(spec),
                                      rb, re, counts.data_ptr(), escaped.data_ptr()))
         rl_shoot_batch(self.handle, descs, PRECISIONS[precision], _stream_ptr(stream))
 
     # ---- magnification probability distributions ----------------------------
     def count_histogram(self, counts, spec, n_values, hist=None, stream=None):
         torch = _torch()
-        _check_counts(counts, spec)
+        _check_counts(counts, spec, self.device)
         if hist is None:
             hist = torch.zeros(int(n_values), dtype=torch.int64, device=counts.device)
+        _dev(hist, torch.int64, int(n_values), "hist", self.device)
         rl_count_histogram(self.handle, counts.data_ptr(), window_of(spec), int(n_values),
                            hist.data_ptr(), _stream_ptr(stream))
         return hist
@@ -408,17 +414,18 @@ class Context:
     def mpd(self, counts, spec, mu_ref, log_lo, log_hi, nbins, n_avg=None, bins=None, stream=None):
         """[underflow, nbins bins of log10(mu / mu_ref) over [log_lo, log_hi), overflow]."""
         torch = _torch()
-        _check_counts(counts, spec)
+        _check_counts(counts, spec, self.device)
         if n_avg is None:
             n_avg = rl_n_avg(grid_of(spec), window_of(spec))
         if bins is None:
             bins = torch.zeros(int(nbins) + 2, dtype=torch.int64, device=counts.device)
+        _dev(bins, torch.int64, int(nbins) + 2, "bins", self.device)
         rl_mpd(self.handle, counts.data_ptr(), window_of(spec), n_avg, mu_ref, log_lo, log_hi,
                int(nbins), bins.data_ptr(), _stream_ptr(stream))
         return bins
 
     def probability_sums(self, counts, spec, mu_lim, n_avg=None, stream=None):
-        _check_counts(counts, spec)
+        _check_counts(counts, spec, self.device)
         if n_avg is None:
             n_avg = rl_n_avg(grid_of(spec), window_of(spec))
         return rl_probability_sums(self.handle, counts.data_ptr(), window_of(spec), n_avg, mu_lim,
@@ -428,8 +435,9 @@ class Context:
         """bins: int64 tensor (n_maps, n_bins). Returns (mean, std) float64 tensors."""
         torch = _torch()
         bins = bins.contiguous()
-        if bins.dtype != torch.int64 or bins.dim() != 2:
+        if bins.dim() != 2:
             raise ValueError("bins must be a 2-D int64 tensor")
+        _dev(bins, torch.int64, bins.numel(), "bins", self.device)
         mean = torch.empty(bins.shape[1], dtype=torch.float64, device=bins.device)
         std = torch.empty_like(mean)
         rl_mpd_moments(self.handle, bins.data_ptr(), bins.shape[0], bins.shape[1], int(n_pix),
@@ -440,7 +448,7 @@ class Context:
     def encode(self, counts, spec, stream=None):
         """Returns (values int32[n_distinct], bits, packed uint32 words) on the device."""
         torch = _torch()
-        _check_counts(counts, spec)
+        _check_counts(counts, spec, self.device)
         nd, bits = rl_codec_encode(self.handle, counts.data_ptr(), window_of(spec), None, 0, None, 0,
                                    _stream_ptr(stream))
         words = (spec.p1 * spec.p2 * bits + 31) // 32
@@ -455,8 +463,12 @@ class Context:
         torch = _torch()
         if counts is None:
             counts = torch.empty((spec.p2, spec.p1), dtype=torch.int32, device=packed.device)
-        if packed.numel() < (spec.p1 * spec.p2 * bits + 31) // 32:
-            raise ValueError("packed stream too short for the map")
+        words = (spec.p1 * spec.p2 * int(bits) + 31) // 32
+        if packed.dtype not in (torch.int32, torch.uint32):
+            raise ValueError("packed must hold 32-bit words")
+        _dev(packed, packed.dtype, words, "packed", self.device, exact=False)
+        _dev(values, torch.int32, values.numel(), "values", self.device)
+        _dev(counts, torch.int32, spec.p1 * spec.p2, "counts", self.device)
         rl_codec_decode(self.handle, packed.data_ptr(), int(bits), values.data_ptr(), values.numel(),
                         window_of(spec), counts.data_ptr(), _stream_ptr(stream))
         return counts
@@ -466,17 +478,18 @@ class Context:
         torch = _torch()
         if kernel is None:
             kernel = torch.empty((spec.p2, spec.p1), dtype=torch.float64, device=f"cuda:{self.device}")
+        _dev(kernel, torch.float64, spec.p1 * spec.p2, "kernel", self.device)
         rl_source_kernel(self.handle, rl_profile(PROFILES[shape], radius, hole), window_of(spec),
                          kernel.data_ptr(), _stream_ptr(stream))
         return kernel
 
     def convolve(self, counts, kernel, spec, n_avg=1.0, out=None, stream=None):
         torch = _torch()
-        _check_counts(counts, spec)
-        if kernel.dtype != torch.float64 or kernel.numel() != spec.p1 * spec.p2 or not kernel.is_contiguous():
-            raise ValueError("kernel must be a contiguous float64 p2 x p1 tensor")
+        _check_counts(counts, spec, self.device)
+        _dev(kernel, torch.float64, spec.p1 * spec.p2, "kernel", self.device)
         if out is None:
             out = torch.empty((spec.p2, spec.p1), dtype=torch.float64, device=counts.device)
+        _dev(out, torch.float64, spec.p1 * spec.p2, "out", self.device)
         rl_convolve(self.handle, counts.data_ptr(), kernel.data_ptr(), window_of(spec), n_avg,
                     out.data_ptr(), _stream_ptr(stream))
         return out
@@ -494,22 +507,32 @@ class Context:
         rl_set_tuning(self.handle, PRECISIONS[precision], n_class, rl_tuning(**cur))
 
 
-def _check_map_tensors(counts, escaped, spec):
+def _dev(t, dtype, numel, name, device, exact=True):
+    """A contiguous tensor of `dtype` on HIP device `device` with `numel`
+    elements (at least `numel` if not exact): anything else is refused before
+    its pointer reaches the library."""
     torch = _torch()
-    if counts.dtype != torch.int32 or counts.numel() != spec.p1 * spec.p2 or not counts.is_contiguous():
-        raise ValueError("counts must be a contiguous int32 tensor of p2 x p1 elements")
-    if escaped.dtype != torch.int64 or escaped.numel() < 1:
-        raise ValueError("escaped must be an int64 tensor")
-    if not counts.is_cuda or not escaped.is_cuda:
-        raise ValueError("counts and escaped must be device tensors")
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    if not t.is_cuda or (t.device.index if t.device.index is not None else 0) != device:
+        raise ValueError(f"{name} must live on cuda:{device}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if (t.numel() != numel) if exact else (t.numel() < numel):
+        raise ValueError(f"{name} must hold {'' if exact else 'at least '}{numel} elements")
+    return t
 
 
-def _check_counts(counts, spec):
+def _check_map_tensors(counts, escaped, spec, device=0):
     torch = _torch()
-    if counts.dtype != torch.int32 or counts.numel() != spec.p1 * spec.p2 or not counts.is_contiguous():
-        raise ValueError("counts must be a contiguous int32 tensor of p2 x p1 elements")
-    if not counts.is_cuda:
-        raise ValueError("counts must be a device tensor")
+    _dev(counts, torch.int32, spec.p1 * spec.p2, "counts", device)
+    _dev(escaped, torch.int64, 1, "escaped", device, exact=False)
+
+
+def _check_counts(counts, spec, device=0):
+    _dev(counts, _torch().int32, spec.p1 * spec.p2, "counts", device)
 
 
 def n_class(n: int) -> int:

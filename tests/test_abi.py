@@ -247,3 +247,37 @@ def test_convolution_entry_points_validate_on_the_host():
         assert lib.rl_convolve(ctx, fake, None, C.byref(w), 1.0, fake, None) == rl.RL_E_INVALID
     finally:
         rl.rl_destroy(ctx)
+
+
+def test_binding_refuses_host_tensors_before_any_library_call():
+    """Host (CPU) tensors, wrong dtypes and short outputs are refused by the
+    binding: their pointers never reach a kernel."""
+    import torch
+    from paper_1406_0559_amd import inputs
+    ctx = rl.Context(0)
+    try:
+        spec = inputs.MapSpec(name="t", kappa=0.4, gamma=0.3, s=0.0, n1=8, n2=8, h1=1.0, h2=1.0,
+                              p1=4, p2=4, W1=2.0, W2=2.0)
+        c = torch.zeros((4, 4), dtype=torch.int32)
+        e = torch.zeros(1, dtype=torch.int64)
+        L = rl.DeviceLenses([0.1], [0.2], device="cpu")
+        calls = [
+            lambda: ctx.shoot(L, spec, "fp32c", c, e),
+            lambda: ctx.normalise(c, spec),
+            lambda: ctx.stats(c, e, spec),
+            lambda: ctx.count_histogram(c, spec, 8),
+            lambda: ctx.mpd(c, spec, 1.0, -1.0, 1.0, 10),
+            lambda: ctx.probability_sums(c, spec, 1.0),
+            lambda: ctx.encode(c, spec),
+            lambda: ctx.convolve(c, torch.zeros((4, 4), dtype=torch.float64), spec),
+            lambda: ctx.bin_positions(torch.zeros(3, dtype=torch.float64),
+                                      torch.zeros(3, dtype=torch.float64), spec, c, e),
+            lambda: ctx.mpd_moments(torch.zeros((2, 3), dtype=torch.int64), 16),
+            lambda: ctx.decode(torch.zeros(4, dtype=torch.int32), 4,
+                               torch.zeros(2, dtype=torch.int32), spec),
+        ]
+        for call in calls:
+            with pytest.raises(ValueError):
+                call()
+    finally:
+        ctx.close()
