@@ -276,7 +276,7 @@ rl_status prepare_lenses_f32(rl_context* ctx, const rl_lenses* L, bool force_mas
     e = rl::launch_prep_lenses(L->x1, L->x2, L->m, n, xy, masses ? mf : nullptr, true, s);
     if (e != hipSuccess) return hip_fail(e, "prep_lenses launch");
     P->lens32 = xy;
-    P->mass32 = masses ? mf : nullptr;
+    P->imass32 = masses ? mf : nullptr;
     P->n_lens = n;
     return RL_OK;
 }
@@ -644,7 +644,7 @@ rl_status rl_shoot_batch(rl_context* ctx, const rl_map_desc* h_maps, int32_t n_m
                                        stream);
             if (e != hipSuccess) return hip_fail(e, "prep_lenses launch");
             params[i].lens32 = xy + off;
-            params[i].mass32 = masses ? mf + off : nullptr;
+            params[i].imass32 = masses ? mf + off : nullptr;
             off += L.n;
         }
     } else {

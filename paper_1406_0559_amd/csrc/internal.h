@@ -66,7 +66,7 @@ struct MapParams {
     // lenses
     int64_t n_lens;
     const float4* lens32;      // FP32 path: {x1 hi, x1 lo, x2 hi, x2 lo}
-    const float* mass32;       // FP32 path masses (nullptr = unit)
+    const float* imass32;      // FP32 path inverse masses 1/m (0: massless; nullptr = unit)
     const double* lx1;         // FP64 path
     const double* lx2;
     const double* lm;          // FP64 path masses (nullptr = unit)

@@ -9,9 +9,11 @@
 //     chosen from the grid spacing so it is roughly square on the sky). One
 //     wave of 64 lanes processes one cell, each lane holding a KX x KY block
 //     of 16 rays in registers, or two cells, each on half of the lanes with
-//     32 rays per lane (fewer per-lens differences per ray, more registers). Rays of a lane share their x1 (per column) and
-//     x2 (per row) offsets, so per lens a lane computes KX + KY differences
-//     and then one fma + one v_rcp_f32 + two fma per ray.
+//     32 rays per lane (fewer per-lens differences per ray, more
+//     registers). Rays of a lane share their x1 (per column) and x2 (per
+//     row) offsets, so per lens a lane computes KX + KY differences and then
+//     per ray one fma for r^2, half a v_rcp_f32 and 1.5 multiplies (two rays
+//     share one reciprocal) and two fma.
 //   * Lenses are staged per wave into LDS in tiles and read back as
 //     broadcasts (every lane reads the same address). For the FP32 path each
 //     lens is rebased to the cell centre while staging, from an FP32 hi/lo
@@ -87,33 +89,32 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
 // deflection sums
 // ----------------------------------------------------------------------------
 
-// Differences of the lane's rays to lens k: dx per column, dy and dy^2 per row,
-// and the mass-weighted numerators.
+// Differences of the lane's rays to lens k: dx per column, dy and dy^2 per
+// row. With masses the differences are divided by the lens mass: for
+// d' = d / m and r'^2 = r^2 / m^2, d' / r'^2 = m d / r^2, so the mass costs
+// nothing per ray. The staged entry holds (x_k / m, y_k / m, 1 / m), and
+// d' = x (1/m) - x_k / m is one fma per column or row, as d = x - x_k is.
 template <int KX, int KY, bool MASS>
 struct LensTerms {
-    float dx[KX], wx[KX], dy2[KY], wy[KY];
+    float dx[KX], dy[KY], dy2[KY];
 
     __device__ __forceinline__ LensTerms(const float* __restrict__ wl, int k, const float (&ox)[KX],
                                          const float (&oy)[KY]) {
-        float lx, ly, lm = 1.0f;
         if constexpr (MASS) {
             const float4 v = reinterpret_cast<const float4*>(wl)[k];
-            lx = v.x; ly = v.y; lm = v.z;
+#pragma unroll
+            for (int a = 0; a < KX; ++a) dx[a] = __builtin_fmaf(ox[a], v.z, -v.x);
+#pragma unroll
+            for (int b = 0; b < KY; ++b) dy[b] = __builtin_fmaf(oy[b], v.z, -v.y);
         } else {
             const float2 v = reinterpret_cast<const float2*>(wl)[k];
-            lx = v.x; ly = v.y;
+#pragma unroll
+            for (int a = 0; a < KX; ++a) dx[a] = ox[a] - v.x;
+#pragma unroll
+            for (int b = 0; b < KY; ++b) dy[b] = oy[b] - v.y;
         }
 #pragma unroll
-        for (int a = 0; a < KX; ++a) {
-            dx[a] = ox[a] - lx;
-            wx[a] = MASS ? lm * dx[a] : dx[a];
-        }
-#pragma unroll
-        for (int b = 0; b < KY; ++b) {
-            const float d = oy[b] - ly;
-            dy2[b] = d * d;
-            wy[b] = MASS ? lm * d : d;
-        }
+        for (int b = 0; b < KY; ++b) dy2[b] = dy[b] * dy[b];
     }
 };
 
@@ -155,10 +156,10 @@ __device__ __forceinline__ void lens_step_f32(const float* __restrict__ wl, int 
             const int r = g0 + 2 * u, a = r / KY, b = r % KY;
             const float ia = r2[2 * u + 1] * q[u];
             const float ib = r2[2 * u] * q[u];
-            p1[r] = __builtin_fmaf(T.wx[a], ia, p1[r]);
-            p2[r] = __builtin_fmaf(T.wy[b], ia, p2[r]);
-            p1[r + 1] = __builtin_fmaf(T.wx[a], ib, p1[r + 1]);
-            p2[r + 1] = __builtin_fmaf(T.wy[b + 1], ib, p2[r + 1]);
+            p1[r] = __builtin_fmaf(T.dx[a], ia, p1[r]);
+            p2[r] = __builtin_fmaf(T.dy[b], ia, p2[r]);
+            p1[r + 1] = __builtin_fmaf(T.dx[a], ib, p1[r + 1]);
+            p2[r + 1] = __builtin_fmaf(T.dy[b + 1], ib, p2[r + 1]);
         }
     }
 }
@@ -177,8 +178,8 @@ __device__ __forceinline__ void lens_step_f32_single(const float* __restrict__ w
         const int a = r / KY, b = r % KY;
         const float inv = __builtin_amdgcn_rcpf(__builtin_fmaf(T.dx[a], T.dx[a], T.dy2[b]));
         if ((redo >> (r / 2)) & 1u) {
-            p1[r] = __builtin_fmaf(T.wx[a], inv, p1[r]);
-            p2[r] = __builtin_fmaf(T.wy[b], inv, p2[r]);
+            p1[r] = __builtin_fmaf(T.dx[a], inv, p1[r]);
+            p2[r] = __builtin_fmaf(T.dy[b], inv, p2[r]);
         }
     }
 }
@@ -220,7 +221,12 @@ __device__ __forceinline__ void deflect_f32(const MapParams& P, int64_t i0, int6
             const float r1 = rebase(h.x, h.y, C1h, C1l);
             const float r2 = rebase(h.z, h.w, C2h, C2l);
             if constexpr (MASS) {
-                reinterpret_cast<float4*>(wh)[q] = make_float4(r1, r2, P.mass32[t0 + q], 0.0f);
+                // a massless lens (inverse 0) is staged 2^62 away in both
+                // coordinates: r'^2 products overflow, the shared reciprocal
+                // is 0 and its terms are exactly zero
+                const float im = P.imass32[t0 + q];
+                reinterpret_cast<float4*>(wh)[q] = im != 0.0f ? make_float4(r1 * im, r2 * im, im, 0.0f)
+                                                              : make_float4(-0x1p62f, -0x1p62f, 0.0f, 0.0f);
             } else {
                 reinterpret_cast<float2*>(wh)[q] = make_float2(r1, r2);
             }
@@ -483,11 +489,11 @@ __device__ __forceinline__ void process_cell(const MapParams& P, int64_t cell, b
 constexpr int kHdrBytes = 64;
 
 // Occupancy floor in waves per SIMD: 2 holds the 32-ray shapes to 256
-// registers; the 16-ray FP32 shapes with masses run fastest at 4 (measured:
-// the few registers that then spill belong to the per-block compensation,
-// which is touched once per kBlock lenses).
+// registers; the 16-ray FP32 shapes with masses are held at 3, where they fit
+// without spilling (the unit-mass ones reach 3 by themselves; measured on
+// gfx950, 4 with a few spilled registers ran ~1 % slower).
 template <bool MASS, int CPW, int PREC>
-constexpr int min_waves() { return (MASS && CPW == 1 && PREC == kFP32Comp) ? 4 : 2; }
+constexpr int min_waves() { return (MASS && CPW == 1 && PREC == kFP32Comp) ? 3 : 2; }
 
 template <int KX, int KY, bool MASS, int SUBMAP, bool OUT_Y, int PREC, int CPW>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(min_waves<MASS, CPW, PREC>())))
@@ -547,7 +553,8 @@ shoot_batch_kernel(const MapParams* __restrict__ maps,
 // ----------------------------------------------------------------------------
 
 // FP64 lens coordinates -> FP32 hi/lo splits (hi = nearest float, lo = the
-// nearest float of the exact remainder) and FP32 masses.
+// nearest float of the exact remainder) and FP32 inverse masses, 1/m rounded
+// once from FP64; a lens with |m| < 2^-40 is massless (inverse 0).
 __global__ void prep_lenses_kernel(const double* __restrict__ x1, const double* __restrict__ x2,
                                    const double* __restrict__ m, int64_t n, float4* __restrict__ xy,
                                    float* __restrict__ mo, int write_unit) {
@@ -556,7 +563,10 @@ __global__ void prep_lenses_kernel(const double* __restrict__ x1, const double* 
         const double a = x1[k], b = x2[k];
         const float ah = (float)a, bh = (float)b;
         xy[k] = make_float4(ah, (float)(a - (double)ah), bh, (float)(b - (double)bh));
-        if (mo) mo[k] = m ? (float)m[k] : (write_unit ? 1.0f : 0.0f);
+        if (mo) {
+            const double mk = m ? m[k] : (write_unit ? 1.0 : 0.0);
+            mo[k] = fabs(mk) >= 0x1p-40 ? (float)(1.0 / mk) : 0.0f;
+        }
     }
 }
 
@@ -711,7 +721,7 @@ size_t shoot_lds_bytes(Precision prec, bool masses, const KernelShape& ks) {
 hipError_t launch_shoot(const MapParams& P, Precision prec, const KernelShape& ks, bool out_y,
                         int num_cus, hipStream_t s) {
     (void)num_cus;
-    const bool masses = prec == kFP32Comp ? (P.mass32 != nullptr) : (P.lm != nullptr);
+    const bool masses = prec == kFP32Comp ? (P.imass32 != nullptr) : (P.lm != nullptr);
     KernelShape k = fit_lds(prec, masses, ks);
     if (out_y) k.submap = 0;
     const size_t lds = shoot_lds_bytes(prec, masses, k);

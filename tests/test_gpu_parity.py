@@ -207,6 +207,39 @@ def test_fp32_mixed_masses_near_critical_line_at_scale(ctx):
     assert worst <= TOL_Y
 
 
+def test_fp32_degenerate_masses(ctx):
+    """Lenses of zero, negligible (below 2^-40, taken as massless), heavy and
+    negative mass. The FP32 path divides differences by the mass, so these are
+    its edge cases; the oracle applies eq. 1 as written. Massless lenses
+    appended after the others change no bit of the FP32 map: their terms are
+    exactly zero and the blocks of the other lenses do not move."""
+    spec = spec_custom("odd-masses", 0.5, 0.2, 0.3, 640, 320, 6.0, 3.0, 48, 40, 5.0, 4.0, 300, 9.0,
+                       "salpeter", 31)
+    f = spec.lenses()
+    m = f.m.copy()
+    sel = np.random.default_rng(31).permutation(f.n)
+    m[sel[:40]] = 0.0
+    m[sel[40:50]] = 1e-14
+    m[sel[50:55]] = 25.0
+    m[sel[55:60]] = -0.5
+    g = inputs.LensField(f.x1, f.x2, m)
+    check_fp32_positions(ctx, spec, g, 0, spec.n2)
+    check_fp32_map(ctx, spec, g)
+
+    extra = 70
+    zx = np.random.default_rng(32).uniform(-3.0, 3.0, (2, extra))
+    zm = np.where(np.arange(extra) % 2 == 0, 0.0, 1e-15)
+    z = inputs.LensField(np.concatenate([f.x1, zx[0]]), np.concatenate([f.x2, zx[1]]),
+                         np.concatenate([f.m, zm]))
+    a, ea = ctx.shoot(dev_lenses(f), spec, "fp32c")
+    b, eb = ctx.shoot(dev_lenses(z), spec, "fp32c")
+    assert (a.cpu().numpy() == b.cpu().numpy()).all() and int(ea.item()) == int(eb.item())
+    ya = ctx.ray_positions(dev_lenses(f), spec, "fp32c", 0, 64)
+    yb = ctx.ray_positions(dev_lenses(z), spec, "fp32c", 0, 64)
+    assert same_bits(ya[0].cpu().numpy(), yb[0].cpu().numpy())
+    assert same_bits(ya[1].cpu().numpy(), yb[1].cpu().numpy())
+
+
 # ---------------------------------------------------------------------------
 # schedule independence: kernel shapes, chunks, batching, repeats
 # ---------------------------------------------------------------------------
