@@ -92,7 +92,9 @@ typedef struct {
 /* Point lenses as a device structure of arrays (the lenspos.dat content of
  * Section 3.2.1): positions x1[n], x2[n] and masses m[n] in FP64.
  * m == NULL means unit masses. n >= 0 (n == 0 is a pure sheet); with n > 0
- * x1 and x2 must be non-NULL. */
+ * x1 and x2 must be non-NULL. Masses may be zero or negative; RL_FP32_COMP
+ * takes a lens with |m| < 2^-40 as massless (its terms are exactly zero).
+ * The arrays are read on the device and not checked for finiteness. */
 typedef struct {
     const double* x1;
     const double* x2;
