@@ -284,7 +284,9 @@ rl_status rl_mpd(rl_context* ctx, const int32_t* d_counts, const rl_window* win,
 
 /* Probability sums for mu < mu_lim and mu > mu_lim (Section 4, MPDs tool;
  * the two add up to one): *h_below = number of pixels with N / N_avg < mu_lim
- * (one FP64 division per pixel), *h_above = p1 p2 - *h_below. mu_lim not NaN.
+ * (the FP64 quotient, compared in FP64; the quotient is monotone in N, so the
+ * decision is taken once on the host as a count threshold), *h_above =
+ * p1 p2 - *h_below. mu_lim not NaN.
  * Synchronises the stream. */
 rl_status rl_probability_sums(rl_context* ctx, const int32_t* d_counts, const rl_window* win,
                               double n_avg, double mu_lim, int64_t* h_below, int64_t* h_above,

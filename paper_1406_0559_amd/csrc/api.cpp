@@ -4,6 +4,7 @@
 #include "raylens.h"
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -47,6 +48,19 @@ rl_status hip_fail(hipError_t e, const char* what) {
 }
 
 bool is_finite(double v) { return std::isfinite(v); }
+
+// Folds the reduction slots copied back from the device (launch_count_stats,
+// launch_prob_sum): out[0] and out[2] sum words 0 and 2, out[1] is the
+// largest word 1.
+void fold_slots(const std::vector<unsigned long long>& h, unsigned long long out[3]) {
+    out[0] = out[1] = out[2] = 0;
+    for (int i = 0; i < rl::kRedSlots; ++i) {
+        const unsigned long long* w = h.data() + (size_t)i * rl::kSlotWords;
+        out[0] += w[0];
+        out[1] = w[1] > out[1] ? w[1] : out[1];
+        out[2] += w[2];
+    }
+}
 
 // ---------------------------------------------------------------------------
 // validation (host only, before any HIP call)
@@ -537,20 +551,25 @@ rl_status rl_stats_get(rl_context* ctx, const int32_t* d_counts, const int64_t* 
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return hip_fail(dg.err, "hipSetDevice");
     RL_TRY(ensure_ready(ctx));
-    hipError_t e = ctx->stats.acquire(4 * sizeof(unsigned long long), stream);
+    // the reduction slots, then the escaped count in one more word
+    const size_t words = rl::kRedBytes / sizeof(unsigned long long);
+    hipError_t e = ctx->stats.acquire(rl::kRedBytes + sizeof(unsigned long long), stream);
     if (e != hipSuccess) return hip_fail(e, "stats scratch");
     unsigned long long* acc = static_cast<unsigned long long*>(ctx->stats.ptr);
-    e = rl::launch_fill_u32(reinterpret_cast<unsigned int*>(acc), 8, 0u, stream);
+    e = rl::launch_count_stats(d_counts, (int64_t)win->p1 * win->p2, acc, stream);
     if (e == hipSuccess)
-        e = rl::launch_count_stats(d_counts, (int64_t)win->p1 * win->p2, acc, stream);
+        e = hipMemcpyAsync(acc + words, d_escaped, sizeof(int64_t), hipMemcpyDeviceToDevice, stream);
+    std::vector<unsigned long long> slots(words + 1, 0);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(acc + 3, d_escaped, sizeof(int64_t), hipMemcpyDeviceToDevice, stream);
-    unsigned long long host[4] = {0, 0, 0, 0};
-    if (e == hipSuccess) e = hipMemcpyAsync(host, acc, sizeof(host), hipMemcpyDeviceToHost, stream);
+        e = hipMemcpyAsync(slots.data(), acc, slots.size() * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     hipError_t e2 = ctx->stats.release(stream);
     if (e == hipSuccess) e = e2;
     if (e != hipSuccess) return hip_fail(e, "stats");
+    unsigned long long host[4];
+    fold_slots(slots, host);
+    host[3] = slots[words];
     double n_avg = 0.0;
     RL_TRY(rl_n_avg(grid, win, &n_avg));
     rl_stats st;
@@ -748,18 +767,30 @@ rl_status rl_probability_sums(rl_context* ctx, const int32_t* d_counts, const rl
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return hip_fail(dg.err, "hipSetDevice");
     RL_TRY(ensure_ready(ctx));
-    hipError_t e = ctx->stats.acquire(4 * sizeof(unsigned long long), stream);
+    hipError_t e = ctx->stats.acquire(rl::kRedBytes, stream);
     if (e != hipSuccess) return hip_fail(e, "stats scratch");
     unsigned long long* acc = static_cast<unsigned long long*>(ctx->stats.ptr);
     const int64_t n = (int64_t)win->p1 * win->p2;
-    e = rl::launch_fill_u32(reinterpret_cast<unsigned int*>(acc), 2, 0u, stream);
-    if (e == hipSuccess) e = rl::launch_prob_sum(d_counts, n, n_avg, mu_lim, acc, stream);
-    unsigned long long below = 0;
-    if (e == hipSuccess) e = hipMemcpyAsync(&below, acc, sizeof(below), hipMemcpyDeviceToHost, stream);
+    // N / N_avg in FP64 is non-decreasing in the integer N (IEEE division by a
+    // positive number is monotone), so "N / N_avg < mu_lim" holds exactly for
+    // N below the first int32 count where it fails: find that count by
+    // bisection with the same division (2^31 if it never fails).
+    int64_t lo = INT32_MIN, hi = (int64_t)INT32_MAX + 1;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if ((double)mid / n_avg < mu_lim) lo = mid + 1;
+        else hi = mid;
+    }
+    e = rl::launch_prob_sum(d_counts, n, lo, acc, stream);
+    std::vector<unsigned long long> slots(rl::kRedBytes / sizeof(unsigned long long), 0);
+    if (e == hipSuccess) e = hipMemcpyAsync(slots.data(), acc, rl::kRedBytes, hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     hipError_t e2 = ctx->stats.release(stream);
     if (e == hipSuccess) e = e2;
     if (e != hipSuccess) return hip_fail(e, "probability sums");
+    unsigned long long folded[3];
+    fold_slots(slots, folded);
+    const unsigned long long below = folded[0];
     *h_below = (int64_t)below;
     *h_above = n - (int64_t)below;
     return RL_OK;
@@ -796,17 +827,18 @@ rl_status rl_codec_encode(rl_context* ctx, const int32_t* d_counts, const rl_win
     RL_TRY(ensure_ready(ctx));
     const int64_t n_pix = (int64_t)win->p1 * win->p2;
     // 1. largest count and negatives
-    hipError_t e = ctx->stats.acquire(4 * sizeof(unsigned long long), stream);
+    hipError_t e = ctx->stats.acquire(rl::kRedBytes, stream);
     if (e != hipSuccess) return hip_fail(e, "stats scratch");
     unsigned long long* acc = static_cast<unsigned long long*>(ctx->stats.ptr);
-    e = rl::launch_fill_u32(reinterpret_cast<unsigned int*>(acc), 8, 0u, stream);
-    if (e == hipSuccess) e = rl::launch_count_stats(d_counts, n_pix, acc, stream);
-    unsigned long long host[3] = {0, 0, 0};
-    if (e == hipSuccess) e = hipMemcpyAsync(host, acc, sizeof(host), hipMemcpyDeviceToHost, stream);
+    e = rl::launch_count_stats(d_counts, n_pix, acc, stream);
+    std::vector<unsigned long long> slots(rl::kRedBytes / sizeof(unsigned long long), 0);
+    if (e == hipSuccess) e = hipMemcpyAsync(slots.data(), acc, rl::kRedBytes, hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     hipError_t e2 = ctx->stats.release(stream);
     if (e == hipSuccess) e = e2;
     if (e != hipSuccess) return hip_fail(e, "codec statistics");
+    unsigned long long host[3];
+    fold_slots(slots, host);
     if (host[2]) return fail(RL_E_INVALID, "counts must be >= 0 (%llu negative)", host[2]);
     const int64_t n_values = (int64_t)host[1] + 1;
     // 2. histogram of values, distinct flags and their ranks

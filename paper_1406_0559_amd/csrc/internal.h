@@ -107,9 +107,17 @@ hipError_t launch_bin_positions(const double* y1, const double* y2, int64_t n, i
                                 int32_t* counts, unsigned long long* escaped, hipStream_t stream);
 hipError_t launch_normalise(const int32_t* counts, int64_t n, double n_avg, float* mu,
                             hipStream_t stream);
-// out[0] = sum of the non-negative counts, out[1] = max count, out[2] += number of
-// negative counts (all u64; out[0..2] caller-zeroed)
-hipError_t launch_count_stats(const int32_t* counts, int64_t n, unsigned long long* out,
+// Scalar reductions over a map (count statistics, probability sums) end in
+// one device-scope atomic per workgroup per word. The workgroups spread them
+// over kRedSlots slots, 128 bytes apart, which the host folds after copying
+// them back (fold_slots).
+constexpr int kRedSlots = 64;
+constexpr int kSlotWords = 16;   // u64 words per slot
+constexpr size_t kRedBytes = (size_t)kRedSlots * kSlotWords * sizeof(unsigned long long);
+// slots (kRedBytes of device memory, zeroed by the launcher): word 0 of a slot
+// sums the non-negative counts, word 1 is the largest count, word 2 counts the
+// negative ones
+hipError_t launch_count_stats(const int32_t* counts, int64_t n, unsigned long long* slots,
                               hipStream_t stream);
 hipError_t launch_fill_u32(unsigned int* p, int64_t n, unsigned int v, hipStream_t stream);
 hipError_t launch_count_hist(const int32_t* counts, int64_t n, int64_t n_values,
@@ -117,8 +125,9 @@ hipError_t launch_count_hist(const int32_t* counts, int64_t n, int64_t n_values,
 // lut: device scratch of kMpdLut uint16 (the bin of every count below kMpdLut)
 hipError_t launch_mpd(const int32_t* counts, int64_t n, const double* thr, int nthr, uint16_t* lut,
                       unsigned long long* bins, hipStream_t stream);
-hipError_t launch_prob_sum(const int32_t* counts, int64_t n, double n_avg, double mu_lim,
-                           unsigned long long* out, hipStream_t stream);
+// slots as for launch_count_stats; word 0 counts the pixels below t_below
+hipError_t launch_prob_sum(const int32_t* counts, int64_t n, int64_t t_below,
+                           unsigned long long* slots, hipStream_t s);
 hipError_t launch_mpd_moments(const unsigned long long* bins, int n_maps, int n_bins, double n_pix,
                               double* mean, double* stdev, hipStream_t stream);
 

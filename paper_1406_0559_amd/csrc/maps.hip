@@ -12,9 +12,14 @@
 namespace rl {
 namespace {
 
+constexpr int kInFlight = 4;   // 16-byte loads in flight per thread
+constexpr int kReduceBlocks = 2048;   // workgroups of the scalar reductions
+
 // Calls f(v) for every count of c[0 .. n) once, over the whole grid: 16-byte
-// vector loads for the aligned body, scalar loads for the few counts before
-// and after it.
+// vector loads for the aligned body, kInFlight of them in flight per thread
+// (the grids are a few waves per SIMD, so the loads of one thread must overlap),
+// and scalar loads for the few counts before and after it. The order of the
+// calls is unspecified; the callers only count and compare.
 template <typename F>
 __device__ __forceinline__ void grid_counts(const int32_t* __restrict__ c, int64_t n, F&& f) {
     const uintptr_t addr = reinterpret_cast<uintptr_t>(c);
@@ -25,7 +30,20 @@ __device__ __forceinline__ void grid_counts(const int32_t* __restrict__ c, int64
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
     const int4* __restrict__ v = reinterpret_cast<const int4*>(c + head);
-    for (int64_t k = tid; k < nv; k += nth) {
+    int64_t k = tid;
+    for (; k + (kInFlight - 1) * nth < nv; k += kInFlight * nth) {
+        int4 q[kInFlight];
+#pragma unroll
+        for (int u = 0; u < kInFlight; ++u) q[u] = v[k + u * nth];
+#pragma unroll
+        for (int u = 0; u < kInFlight; ++u) {
+            f(q[u].x);
+            f(q[u].y);
+            f(q[u].z);
+            f(q[u].w);
+        }
+    }
+    for (; k < nv; k += nth) {
         const int4 q = v[k];
         f(q.x);
         f(q.y);
@@ -78,9 +96,10 @@ __global__ void __launch_bounds__(256) count_stats_kernel(const int32_t* __restr
             bn += sneg[i];
             bm = smax[i] > bm ? smax[i] : bm;
         }
-        atomicAdd(&out[0], bs);
-        atomicMax(&out[1], (unsigned long long)bm);
-        if (bn) atomicAdd(&out[2], bn);
+        unsigned long long* o = out + (blockIdx.x % kRedSlots) * kSlotWords;
+        atomicAdd(&o[0], bs);
+        atomicMax(&o[1], (unsigned long long)bm);
+        if (bn) atomicAdd(&o[2], bn);
     }
 }
 
@@ -154,13 +173,15 @@ __global__ void __launch_bounds__(256) mpd_kernel(const int32_t* __restrict__ co
         if (sb[e]) atomicAdd(&bins[e], (unsigned long long)sb[e]);
 }
 
-// Pixels with N / N_avg < mu_lim (one FP64 division each, as the definition).
+// Pixels with N < t_below: the host finds t_below as the first count whose
+// FP64 quotient N / N_avg is not below mu_lim (the quotient is monotone in N),
+// so this is the definition's decision, taken once per count value.
 __global__ void __launch_bounds__(256) prob_sum_kernel(const int32_t* __restrict__ counts, int64_t n,
-                                                       double n_avg, double mu_lim,
+                                                       int64_t t_below,
                                                        unsigned long long* __restrict__ out) {
     __shared__ unsigned long long part[4];
     unsigned long long below = 0;
-    grid_counts(counts, n, [&](int cv) { below += ((double)cv / n_avg < mu_lim) ? 1ull : 0ull; });
+    grid_counts(counts, n, [&](int cv) { below += ((int64_t)cv < t_below) ? 1ull : 0ull; });
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) below += __shfl_xor(below, o);
     if ((threadIdx.x % kLanes) == 0) part[threadIdx.x / kLanes] = below;
@@ -168,7 +189,7 @@ __global__ void __launch_bounds__(256) prob_sum_kernel(const int32_t* __restrict
     if (threadIdx.x == 0) {
         unsigned long long t = 0;
         for (int i = 0; i < (int)(blockDim.x / kLanes); ++i) t += part[i];
-        atomicAdd(out, t);
+        atomicAdd(out + (blockIdx.x % kRedSlots) * kSlotWords, t);
     }
 }
 
@@ -340,12 +361,12 @@ hipError_t launch_normalise(const int32_t* counts, int64_t n, double n_avg, floa
     return hipGetLastError();
 }
 
-hipError_t launch_count_stats(const int32_t* counts, int64_t n, unsigned long long* out,
+hipError_t launch_count_stats(const int32_t* counts, int64_t n, unsigned long long* slots,
                               hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    // few blocks: every block ends in device-scope atomics on the same three words
-    hipLaunchKernelGGL(count_stats_kernel, dim3(grid_for(n, 256 * 64, 512)), dim3(256), 0, s, counts, n,
-                       out);
+    hipError_t e = launch_fill_u32(reinterpret_cast<unsigned int*>(slots), (int64_t)(kRedBytes / 4), 0u, s);
+    if (e != hipSuccess || n <= 0) return e;
+    hipLaunchKernelGGL(count_stats_kernel, dim3(grid_for(n, 256 * 16, kReduceBlocks)), dim3(256), 0, s,
+                       counts, n, slots);
     return hipGetLastError();
 }
 
@@ -369,11 +390,12 @@ hipError_t launch_mpd(const int32_t* counts, int64_t n, const double* thr, int n
     return hipGetLastError();
 }
 
-hipError_t launch_prob_sum(const int32_t* counts, int64_t n, double n_avg, double mu_lim,
-                           unsigned long long* out, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(prob_sum_kernel, dim3(grid_for(n, 256 * 64, 512)), dim3(256), 0, s, counts, n,
-                       n_avg, mu_lim, out);
+hipError_t launch_prob_sum(const int32_t* counts, int64_t n, int64_t t_below,
+                           unsigned long long* slots, hipStream_t s) {
+    hipError_t e = launch_fill_u32(reinterpret_cast<unsigned int*>(slots), (int64_t)(kRedBytes / 4), 0u, s);
+    if (e != hipSuccess || n <= 0) return e;
+    hipLaunchKernelGGL(prob_sum_kernel, dim3(grid_for(n, 256 * 16, kReduceBlocks)), dim3(256), 0, s,
+                       counts, n, t_below, slots);
     return hipGetLastError();
 }
 

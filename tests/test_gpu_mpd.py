@@ -36,9 +36,25 @@ def check_all(ctx, counts_np, spec, n_avg, mu_ref):
     for lo, hi, nb in ((-1.0, 1.0, 100), (-1.5, 1.5, 400), (0.0, 1.0, 1), (-3.0, 2.0, 4096)):
         b = ctx.mpd(counts, spec, mu_ref, lo, hi, nb, n_avg=n_avg).cpu().numpy()
         assert (b == oracle.mpd(counts_np, n_avg, mu_ref, lo, hi, nb)).all(), (lo, hi, nb)
-    for mu_lim in (0.3 * mu_ref, 1.25 * mu_ref, 3.0 * mu_ref, 1.0, 0.0, -1.0, np.inf):
+    edge = 100.0 / n_avg          # the quotient of a count present in the maps
+    for mu_lim in (0.3 * mu_ref, 1.25 * mu_ref, 3.0 * mu_ref, 1.0, 0.0, -1.0, np.inf, -np.inf,
+                   edge, np.nextafter(edge, np.inf), np.nextafter(edge, -np.inf)):
         got = ctx.probability_sums(counts, spec, mu_lim, n_avg=n_avg)
         assert got == oracle.probability_sums(counts_np, n_avg, mu_lim), mu_lim
+
+
+def test_probability_sums_extreme_counts(ctx):
+    """Negative counts (an overflowed pixel) and the int32 limits: the count
+    threshold taken on the host covers the whole int32 range."""
+    spec = spec_of(67, 3)
+    rng = np.random.default_rng(13)
+    c = rng.integers(0, 300, size=(3, 67)).astype(np.int32)
+    c[0, :6] = [np.iinfo(np.int32).min, -5, -1, np.iinfo(np.int32).max, 2**30, 0]
+    counts = torch.from_numpy(c).cuda()
+    for n_avg in (10.0, 7.3, 1e-300, 1e300):
+        for mu_lim in (-1e9, -0.5, 0.0, 1.0, 29.9, 1e8, 3e8, np.inf, -np.inf, 5e-324):
+            got = ctx.probability_sums(counts, spec, mu_lim, n_avg=n_avg)
+            assert got == oracle.probability_sums(c, n_avg, mu_lim), (n_avg, mu_lim)
 
 
 def test_random_and_adversarial_counts(ctx):
