@@ -108,27 +108,45 @@ __global__ void __launch_bounds__(256) count_stats_kernel(const int32_t* __restr
 // magnification probability distributions (Section 3.2.1 and Section 4)
 // ----------------------------------------------------------------------------
 
-constexpr int kHistLds = 8192;   // count values histogrammed in LDS per workgroup
+constexpr int kHistLds = 8192;   // LDS words for the per-workgroup histogram copies
+constexpr int kMaxReps = 32;     // copies of a histogram in LDS
+
+// Copies of an LDS histogram of `slots` entries that fit in kHistLds words
+// (a power of two, at most kMaxReps). Lane l adds into copy l % reps, stored
+// interleaved (entry e of copy r at e * reps + r): lanes that hit the same
+// entry then hit different words in different banks, so the LDS atomics of
+// the few entries most pixels share do not serialise.
+int hist_reps(int64_t slots, int64_t words = kHistLds) {
+    int r = kMaxReps;
+    while (r > 1 && slots * r > words) r >>= 1;
+    return r;
+}
 
 // Frequency of each count value; values >= n_values - 1 share the last entry.
-// Low values (where almost every pixel lies) go to an LDS copy first.
+// Values below kHistLds / reps (where almost every pixel lies) go to LDS
+// copies first, the rest straight to global atomics.
 __global__ void __launch_bounds__(256) count_hist_kernel(const int32_t* __restrict__ counts,
-                                                         int64_t n, int64_t n_values,
+                                                         int64_t n, int64_t n_values, int reps,
                                                          unsigned long long* __restrict__ hist) {
-    __shared__ unsigned int sh[kHistLds];
-    const int nl = (int)(n_values < kHistLds ? n_values : kHistLds);
-    for (int e = threadIdx.x; e < nl; e += blockDim.x) sh[e] = 0;
+    extern __shared__ __align__(16) unsigned int sh[];
+    const int cap = kHistLds / reps;
+    const int nl = (int)(n_values < cap ? n_values : cap);
+    for (int e = threadIdx.x; e < nl * reps; e += blockDim.x) sh[e] = 0;
     __syncthreads();
     const int64_t last = n_values - 1;
+    const int r = threadIdx.x & (reps - 1);
     grid_counts(counts, n, [&](int cv) {
         const int64_t c = cv < 0 ? 0 : cv;
         const int64_t v = c < last ? c : last;
-        if (v < nl) atomicAdd(&sh[v], 1u);
+        if (v < nl) atomicAdd(&sh[v * reps + r], 1u);
         else atomicAdd(&hist[v], 1ull);
     });
     __syncthreads();
-    for (int e = threadIdx.x; e < nl; e += blockDim.x)
-        if (sh[e]) atomicAdd(&hist[e], (unsigned long long)sh[e]);
+    for (int e = threadIdx.x; e < nl; e += blockDim.x) {
+        unsigned long long t = 0;
+        for (int q = 0; q < reps; ++q) t += sh[e * reps + q];
+        if (t) atomicAdd(&hist[e], t);
+    }
 }
 
 // Bin of a count: the number of thresholds <= N (thresholds ascending), so
@@ -150,27 +168,32 @@ __global__ void mpd_lut_kernel(const double* __restrict__ thr, int nthr, uint16_
     if (v < kMpdLut) lut[v] = (uint16_t)mpd_bin(thr, nthr, (double)v);
 }
 
-// Binned MPD. Thresholds, the value table and the bins live in LDS; counts
-// outside [0, kMpdLut) are searched directly.
+// Binned MPD. Thresholds, the value table and `reps` interleaved copies of the
+// bins (as in count_hist_kernel) live in LDS; counts outside [0, kMpdLut) are
+// searched directly.
 __global__ void __launch_bounds__(256) mpd_kernel(const int32_t* __restrict__ counts, int64_t n,
-                                                  const double* __restrict__ thr, int nthr,
+                                                  const double* __restrict__ thr, int nthr, int reps,
                                                   const uint16_t* __restrict__ lut,
                                                   unsigned long long* __restrict__ bins) {
     extern __shared__ __align__(16) char smem[];
     double* st = reinterpret_cast<double*>(smem);
     unsigned int* sb = reinterpret_cast<unsigned int*>(st + nthr);
-    uint16_t* sl = reinterpret_cast<uint16_t*>(sb + nthr + 1);
+    uint16_t* sl = reinterpret_cast<uint16_t*>(sb + (nthr + 1) * reps);
     for (int e = threadIdx.x; e < nthr; e += blockDim.x) st[e] = thr[e];
-    for (int e = threadIdx.x; e <= nthr; e += blockDim.x) sb[e] = 0;
+    for (int e = threadIdx.x; e < (nthr + 1) * reps; e += blockDim.x) sb[e] = 0;
     for (int e = threadIdx.x; e < kMpdLut; e += blockDim.x) sl[e] = lut[e];
     __syncthreads();
+    const int r = threadIdx.x & (reps - 1);
     grid_counts(counts, n, [&](int cv) {
         const int b = (unsigned)cv < (unsigned)kMpdLut ? (int)sl[cv] : mpd_bin(st, nthr, (double)cv);
-        atomicAdd(&sb[b], 1u);
+        atomicAdd(&sb[b * reps + r], 1u);
     });
     __syncthreads();
-    for (int e = threadIdx.x; e <= nthr; e += blockDim.x)
-        if (sb[e]) atomicAdd(&bins[e], (unsigned long long)sb[e]);
+    for (int e = threadIdx.x; e <= nthr; e += blockDim.x) {
+        unsigned long long t = 0;
+        for (int q = 0; q < reps; ++q) t += sb[e * reps + q];
+        if (t) atomicAdd(&bins[e], t);
+    }
 }
 
 // Pixels with N < t_below: the host finds t_below as the first count whose
@@ -374,8 +397,9 @@ hipError_t launch_count_hist(const int32_t* counts, int64_t n, int64_t n_values,
                              unsigned long long* hist, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     // fewer, longer blocks: each one zeroes and flushes its LDS histogram once
-    hipLaunchKernelGGL(count_hist_kernel, dim3(grid_for(n, 256 * 64, 512)), dim3(256), 0, s, counts,
-                       n, n_values, hist);
+    const int reps = hist_reps(n_values < kHistLds ? n_values : kHistLds);
+    hipLaunchKernelGGL(count_hist_kernel, dim3(grid_for(n, 256 * 64, 512)), dim3(256),
+                       (size_t)kHistLds * sizeof(unsigned int), s, counts, n, n_values, reps, hist);
     return hipGetLastError();
 }
 
@@ -383,10 +407,14 @@ hipError_t launch_mpd(const int32_t* counts, int64_t n, const double* thr, int n
                       unsigned long long* bins, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(mpd_lut_kernel, dim3((kMpdLut + 255) / 256), dim3(256), 0, s, thr, nthr, lut);
-    const size_t lds = (size_t)nthr * sizeof(double) + (size_t)(nthr + 1) * sizeof(unsigned int) +
+    // the copies get what the thresholds and the table leave of 64 KiB, at most kHistLds words
+    const int64_t fixed = (int64_t)nthr * (int64_t)sizeof(double) + (int64_t)kMpdLut * (int64_t)sizeof(uint16_t);
+    const int64_t spare = (65536 - fixed) / (int64_t)sizeof(unsigned int);
+    const int reps = hist_reps(nthr + 1, spare < kHistLds ? spare : kHistLds);
+    const size_t lds = (size_t)nthr * sizeof(double) + (size_t)(nthr + 1) * reps * sizeof(unsigned int) +
                        (size_t)kMpdLut * sizeof(uint16_t);
     hipLaunchKernelGGL(mpd_kernel, dim3(grid_for(n, 256 * 64, 512)), dim3(256), lds, s, counts, n,
-                       thr, nthr, lut, bins);
+                       thr, nthr, reps, lut, bins);
     return hipGetLastError();
 }
 
