@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "maps.h"
 
 namespace {
 thread_local std::string g_error;

@@ -24,7 +24,7 @@
 // pass 3 as forward rows, a product pass and inverse rows.
 #include <climits>
 
-#include "internal.h"
+#include "maps.h"
 
 namespace rl {
 namespace {

@@ -1,0 +1,63 @@
+// Internal declarations of the kernels on finished maps (maps.hip: statistics,
+// MPDs, probability sums, codec) and of the finite-source convolution
+// (convolve.hip), for the C-ABI layer. Not part of the public interface.
+#pragma once
+
+#include "internal.h"
+
+namespace rl {
+
+// Launchers; each returns the hipError_t of the launch.
+hipError_t launch_normalise(const int32_t* counts, int64_t n, double n_avg, float* mu,
+                            hipStream_t stream);
+// Scalar reductions over a map (count statistics, probability sums) end in
+// one device-scope atomic per workgroup per word. The workgroups spread them
+// over kRedSlots slots, 128 bytes apart, which the host folds after copying
+// them back (fold_slots).
+constexpr int kRedSlots = 64;
+constexpr int kSlotWords = 16;   // u64 words per slot
+constexpr size_t kRedBytes = (size_t)kRedSlots * kSlotWords * sizeof(unsigned long long);
+// slots (kRedBytes of device memory, zeroed by the launcher): word 0 of a slot
+// sums the non-negative counts, word 1 is the largest count, word 2 counts the
+// negative ones
+hipError_t launch_count_stats(const int32_t* counts, int64_t n, unsigned long long* slots,
+                              hipStream_t stream);
+hipError_t launch_count_hist(const int32_t* counts, int64_t n, int64_t n_values,
+                             unsigned long long* hist, hipStream_t stream);
+// lut: device scratch of kMpdLut uint16 (the bin of every count below kMpdLut)
+hipError_t launch_mpd(const int32_t* counts, int64_t n, const double* thr, int nthr, uint16_t* lut,
+                      unsigned long long* bins, hipStream_t stream);
+// slots as for launch_count_stats; word 0 counts the pixels below t_below
+hipError_t launch_prob_sum(const int32_t* counts, int64_t n, int64_t t_below,
+                           unsigned long long* slots, hipStream_t s);
+hipError_t launch_mpd_moments(const unsigned long long* bins, int n_maps, int n_bins, double n_pix,
+                              double* mean, double* stdev, hipStream_t stream);
+
+constexpr int kMaxMpdBins = 4096;
+constexpr int kMpdLut = 4096;   // count values binned through a table
+
+// Indexed-map codec: flag/rank the distinct values of a count histogram
+// (exclusive scan; *total = number of distinct values), then pack / unpack.
+int64_t scan_blocks(int64_t n);
+hipError_t launch_distinct_ranks(const unsigned long long* hist, int64_t n_values, int32_t* flag,
+                                 int32_t* rank, int32_t* block_sums, int64_t* total,
+                                 hipStream_t stream);
+hipError_t launch_codec_pack(const int32_t* counts, int64_t n_pix, const int32_t* flag,
+                             const int32_t* rank, int64_t n_values, int bits, int32_t* values,
+                             uint32_t* packed, hipStream_t stream);
+hipError_t launch_codec_unpack(const uint32_t* packed, int64_t n_pix, int bits, const int32_t* values,
+                               int64_t n_values, int32_t* counts, hipStream_t stream);
+
+// Finite-source convolution (convolve.hip). Sides: products of 2, 3 and 5 in
+// [2, kMaxFftSide].
+bool fft_side_supported(int n);
+size_t convolve_scratch_bytes(int p1, int p2);
+hipError_t launch_convolve(const int32_t* counts, const double* kernel, int p1, int p2, double n_avg,
+                           double* out, void* scratch, hipStream_t stream);
+size_t source_scratch_bytes(int h1, int h2);
+hipError_t launch_source_kernel(int shape, double radius, double hole, double pix1, double pix2,
+                                int h1, int h2, int p1, int p2, double* kernel, double* scratch,
+                                hipStream_t stream);
+constexpr int kMaxFftSide = 10240;
+
+}  // namespace rl

@@ -7,7 +7,7 @@
 // made the same way as in a plain sequential evaluation.
 #include <climits>
 
-#include "internal.h"
+#include "maps.h"
 
 namespace rl {
 namespace {
