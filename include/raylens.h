@@ -218,7 +218,10 @@ rl_status rl_shoot_batch(rl_context* ctx, const rl_map_desc* h_maps, int32_t n_m
  *                    workgroup's binned rays; 2 = an LDS-privatised 64 x 64 sub-map
  *                    around their mean pixel. In modes 1 and 2 each touched pixel
  *                    gets one global atomic; rays outside the sub-map go global.
- *   item_cells     : ray cells per work item in rl_shoot_batch (>= 1) */
+ *   item_cells     : work-item size in rl_shoot_batch (>= 1): a map with N
+ *                    lenses is cut into items of about item_cells * 2048 /
+ *                    (N + 8) ray cells (whole workgroup passes, at most
+ *                    4096), so items carry similar work */
 typedef struct {
     int32_t rays_x;
     int32_t rays_y;

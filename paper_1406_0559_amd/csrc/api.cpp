@@ -357,8 +357,8 @@ rl_status rl_create(int32_t hip_device, rl_context** out) {
     // 8 x 2 rays per lane, mass-weighted lenses 4 x 4; FP64 4 x 4
     for (int p = 0; p < 2; ++p)
         for (int k = 0; k < rl::kTuningClasses; ++k)
-            c->tuning[p][k] = (p == RL_FP32_COMP && k < 3) ? rl::KernelShape{8, 2, 256, 4, 1, 16}
-                                                           : rl::KernelShape{4, 4, 256, 4, 1, 16};
+            c->tuning[p][k] = (p == RL_FP32_COMP && k < 3) ? rl::KernelShape{8, 2, 256, 4, 1, 64}
+                                                           : rl::KernelShape{4, 4, 256, 4, 1, 64};
     *out = c;
     return RL_OK;
 }
@@ -628,8 +628,17 @@ rl_status rl_shoot_batch(rl_context* ctx, const rl_map_desc* h_maps, int32_t n_m
         params[i].counts = d.d_counts;
         params[i].escaped = reinterpret_cast<unsigned long long*>(d.d_escaped);
         params[i].n_lens = d.lenses.n;
-        for (int64_t c = 0; c < params[i].n_cells; c += ks.item_cells) {
-            const int64_t nc = std::min<int64_t>(ks.item_cells, params[i].n_cells - c);
+        // cells per item: item_cells cells' worth of work at 2048 lenses, so
+        // items carry about the same work whatever the lens count (short
+        // items for large fields keep the tail of the launch short, long
+        // items for small fields amortise the fetch of the next item), in
+        // whole workgroup passes
+        const int64_t pass = (int64_t)ks.waves * ((ks.rays_x * ks.rays_y) / rl::kRaysPerLane);
+        int64_t per = (int64_t)std::llround((double)ks.item_cells * 2048.0 / (double)(d.lenses.n + 8));
+        per = std::min<int64_t>(std::max<int64_t>(per, pass), 4096);
+        per = (per + pass - 1) / pass * pass;
+        for (int64_t c = 0; c < params[i].n_cells; c += per) {
+            const int64_t nc = std::min<int64_t>(per, params[i].n_cells - c);
             items.push_back(rl::WorkItem{i, 0, c, nc});
         }
     }

@@ -89,7 +89,7 @@ struct KernelShape {
     int32_t lens_tile;         // lenses per LDS pass (multiple of kBlock)
     int32_t waves;             // waves per workgroup
     int32_t submap;            // 0 global atomics, 1 bounding-box LDS sub-map, 2 64x64 LDS window
-    int32_t item_cells;        // cells per batch work item
+    int32_t item_cells;        // batch work-item size: cells at 2048 lenses
 };
 
 // Launchers of shoot.hip. Each returns the hipError_t of the launch. The

@@ -494,6 +494,11 @@ constexpr int kHdrBytes = 64;
 // gfx950, 4 with a few spilled registers ran ~1 % slower).
 template <bool MASS, int CPW, int PREC>
 constexpr int min_waves() { return (MASS && CPW == 1 && PREC == kFP32Comp) ? 3 : 2; }
+// The persistent batch kernel holds its work-item state as well; left to
+// itself the compiler gives the 16-ray FP32 shapes 2 waves per SIMD there, so
+// they are held at 3 like the single-map kernel.
+template <bool MASS, int CPW, int PREC>
+constexpr int min_waves_batch() { return (CPW == 1 && PREC == kFP32Comp) ? 3 : 2; }
 
 template <int KX, int KY, bool MASS, int SUBMAP, bool OUT_Y, int PREC, int CPW>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(min_waves<MASS, CPW, PREC>())))
@@ -517,7 +522,7 @@ shoot_kernel(MapParams P, int L) {
 // global counter until the list is exhausted; every workgroup reaches the
 // exit because the counter only grows.
 template <int KX, int KY, bool MASS, int SUBMAP, int PREC, int CPW>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(min_waves<MASS, CPW, PREC>())))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(min_waves_batch<MASS, CPW, PREC>())))
 shoot_batch_kernel(const MapParams* __restrict__ maps,
                                                           const WorkItem* __restrict__ items,
                                                           int64_t n_items, unsigned int* counter,

@@ -379,7 +379,7 @@ struct Tuner {
 
         // work-item size of the batched launch with the best shape: three maps
         // of a quarter of the rays with N / 4, N and 3 N lenses
-        int item_best = 16;
+        int item_best = 64;
         double item_ms = -1.0;
         if (time_left()) {
             Probe bp[3];
@@ -388,7 +388,7 @@ struct Tuner {
                 e = bp[i].make(nl[i], masses, std::max<int64_t>(min_rays / 4, rays / 4), 0xBA7C0000ull + i);
                 if (e != hipSuccess) return rl::set_error(RL_E_NOMEM, "probe allocation failed");
             }
-            for (int item : {4, 16, 64}) {
+            for (int item : {16, 64, 256}) {
                 rl_tuning t = best;
                 t.item_cells = item;
                 RL_TRY(rl_set_tuning(ctx, prec, cls, &t));
