@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-scale", type=float, default=0.25,
                     help="map-size scale of the served requests (1.0 = 1024^2-4096^2 maps)")
+    ap.add_argument("--serve-saturate", action="store_true",
+                    help="queue every serving request at t = 0 (the server's saturated rate)")
     ap.add_argument("--no-tuning-cache", action="store_true")
     ap.add_argument("--no-post", action="store_true", help="skip the MPD and codec legs")
     ap.add_argument("--no-mixed", action="store_true",
@@ -379,7 +381,10 @@ def main():
         lam = 0.7 * value / mean_evals          # 70 % of the saturated request rate
         reqs = inputs.serve_requests(args.serve_requests, rate=lam, seed=5,
                                      size_scale=args.serve_scale)
-        mreqs = [serve.MapRequest(r.rid, r.spec, r.spec.lenses(), r.arrival) for r in reqs]
+        if args.serve_saturate:                 # every request queued at t = 0
+            lam = None
+        mreqs = [serve.MapRequest(r.rid, r.spec, r.spec.lenses(), 0.0 if args.serve_saturate else r.arrival)
+                 for r in reqs]
         be = serve.GpuBackend(ctx=ctx)
         done = [0]
 
@@ -395,7 +400,8 @@ def main():
         tserve = time.perf_counter() - ts
         summ = serve.latency_summary(res)
         sizes = sorted({r.spec.p1 for r in reqs})
-        serving = {"workload": f"serve-{args.serve_requests}req-maps{sizes[0]}-{sizes[-1]}",
+        serving = {"workload": f"serve-{args.serve_requests}req-maps{sizes[0]}-{sizes[-1]}"
+                               + ("-saturated" if args.serve_saturate else ""),
                    "arrival_rate_per_s": lam, "mean_evals_per_request": mean_evals,
                    "launches": sch.launches, "peak_active": sch.peak_active,
                    "wall_s": tserve, **summ,
