@@ -85,8 +85,11 @@ def measured_traffic(workload):
         return None
     fetch = float(vals["fetch bytes per launch"])
     write = float(vals["write bytes per launch"])
+    ex = vals.get("executed FP32 flops per evaluation")
     return {"bytes": fetch + write, "fetch_bytes": fetch, "write_bytes": write,
-            "binning_mode": vals.get("binning mode"), "source": os.path.relpath(path, ROOT)}
+            "binning_mode": vals.get("binning mode"),
+            "executed_flops_per_eval": float(ex) if ex else None,
+            "source": os.path.relpath(path, ROOT)}
 
 
 def percentile(xs, q):
@@ -489,6 +492,8 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
                      "traffic": traffic["bytes"] if traffic else None,
                      "traffic_detail": traffic,
+                     "executed_tflops": (traffic["executed_flops_per_eval"] * evals / kern_avg_s / 1e12
+                                         if traffic and traffic.get("executed_flops_per_eval") else None),
                      "kernel": "shoot_kernel (FP32-compensated)",
                      "kernel_ms": kern_avg_s * 1e3,
                      "algorithmic_flops_per_launch": FLOPS_PER_EVAL * evals},
