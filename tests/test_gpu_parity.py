@@ -345,6 +345,32 @@ def test_batch_with_two_cells_per_wave_equals_alone(ctx):
             ctx.set_tuning("fp32c", c, **saved[c])
 
 
+def test_batch_of_uneven_lens_counts_equals_alone(ctx):
+    """Work items are sized by work (about item_cells cells at 2048 lenses):
+    a batch mixing 0, 1, 300 and 20000 lenses, with and without masses, cut
+    into items of a few cells for the large field and whole maps for the
+    small ones, gives the same bits as each map shot alone."""
+    specs = [spec_custom(f"uneven-{n}", 0.45, 0.3, 0.2, 700, 520, 6.0, 3.0, 96, 64, 5.0, 4.0, n,
+                         max(1.0, (n / 0.36) ** 0.5), m, 40 + n % 97)
+             for n, m in ((20000, "unit"), (0, "unit"), (1, "unit"), (300, "salpeter"), (20000, "salpeter"))]
+    fields = [s.lenses() for s in specs]
+    Ls = [dev_lenses(f) for f in fields]
+    saved = {c: ctx.get_tuning("fp32c", c) for c in range(rl.TUNING_CLASSES)}
+    try:
+        alone = [ctx.shoot(L, s, "fp32c") for L, s in zip(Ls, specs)]
+        for item in (1, 64, 100000):
+            for c in range(rl.TUNING_CLASSES):
+                ctx.set_tuning("fp32c", c, item_cells=item)
+            outs = [ctx.new_map(s) for s in specs]
+            ctx.shoot_batch([(L, s, c, e) for L, s, (c, e) in zip(Ls, specs, outs)], "fp32c")
+            for (c, e), (ca, ea), s in zip(outs, alone, specs):
+                assert torch.equal(c, ca), (s.name, item)
+                assert int(e.item()) == int(ea.item()), (s.name, item)
+    finally:
+        for c in range(rl.TUNING_CLASSES):
+            ctx.set_tuning("fp32c", c, **saved[c])
+
+
 def test_stats_match_the_oracle(ctx):
     spec = SMALL
     f = spec.lenses()
