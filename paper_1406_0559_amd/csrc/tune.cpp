@@ -338,7 +338,7 @@ struct Tuner {
         auto run = [&](rl_tuning t) -> rl_status {
             for (const Result& r : results)
                 if (same_shape(r.t, t)) return RL_OK;
-            // shapes this build does not support (e.g. a tile that is not a
+            // shapes the library does not support (e.g. a tile that is not a
             // whole number of compensation blocks) are skipped
             if (rl_set_tuning(ctx, prec, cls, &t) != RL_OK) return RL_OK;
             double ms;

@@ -1,7 +1,7 @@
 """The native autotuner (rl_autotune) times the kernel shapes on probes,
 checks that none of them changes the counts, and its table round-trips
-through the JSON cache: a cache written by this build is applied without
-probing, one written by another build is ignored."""
+through the JSON cache: a cache written by the same library version is applied without
+probing, one written by another library version is ignored."""
 import json
 import time
 

@@ -400,7 +400,7 @@ def bench_ctx():
     try:
         c.autotune(autotune.DEFAULT_CACHE, 0)
     except rl.RaylensError:
-        pass                      # no table for this build: defaults, as in bench.py
+        pass                      # no table for this library version: defaults, as in bench.py
     yield c
     c.close()
 

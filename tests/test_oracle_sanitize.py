@@ -1,5 +1,5 @@
 """The oracle's C code under AddressSanitizer and UndefinedBehaviorSanitizer
-(host code only): a C driver calls every oracle function on small and
+(host code only): a C program calls every oracle function on small and
 edge-case inputs (singular rays, non-finite positions, empty ranges, invalid
 arguments, codec widths 1-32 and ragged sizes); any out-of-bounds access,
 signed overflow or invalid conversion aborts the run."""
