@@ -217,6 +217,26 @@ def test_lens_order_only_changes_rounding():
     assert np.max(np.abs(a[1] - b[1]) / scale) < 1e-11
 
 
+def test_massless_and_opposite_lenses():
+    """Eq. 1 weights each lens by its mass: massless lenses added after the
+    others change no bit of any position, and a lens set plus the same set
+    with opposite masses deflects nothing, leaving y = diag(a1, a2) x."""
+    x1, x2, m = _random_field(30, 9)
+    args = (0.5, 0.2, 0.3, 48, 40, 0.05, -0.1, 2.0, 1.5)
+    base = oracle.ray_positions(x1, x2, m, *args)
+    zx = np.random.default_rng(10).uniform(-2.0, 2.0, (2, 12))
+    more = oracle.ray_positions(np.concatenate([x1, zx[0]]), np.concatenate([x2, zx[1]]),
+                                np.concatenate([m, np.zeros(12)]), *args)
+    for k in (0, 1):
+        assert (base[k].view(np.int64) == more[k].view(np.int64)).all()
+    both = oracle.ray_positions(np.concatenate([x1, x1]), np.concatenate([x2, x2]),
+                                np.concatenate([m, -m]), *args)
+    ks = 0.3 * 0.5
+    X1, X2 = np.meshgrid(grid_coords(48, 0.05, 2.0), grid_coords(40, -0.1, 1.5))
+    assert np.allclose(both[0].reshape(X1.shape), (1.0 - 0.2 - ks) * X1, rtol=0, atol=1e-12)
+    assert np.allclose(both[1].reshape(X2.shape), (1.0 + 0.2 - ks) * X2, rtol=0, atol=1e-12)
+
+
 def test_mass_scaling_of_the_einstein_radius():
     """Lenses of common mass m: with x = sqrt(m) x', eq. 1 (no sheet, no shear)
     gives y = sqrt(m) y'(x'), y' computed with unit masses at x_k / sqrt(m)."""
