@@ -496,6 +496,7 @@ def main():
                                          if traffic and traffic.get("executed_flops_per_eval") else None),
                      "kernel": "shoot_kernel (FP32-compensated)",
                      "kernel_ms": kern_avg_s * 1e3,
+                     "kernel_ms_min_max": [float(np.min(kern_ms)), float(np.max(kern_ms))],
                      "algorithmic_flops_per_launch": FLOPS_PER_EVAL * evals},
         "cpu_baseline": cpu,
         "fp64_plain": fp64,
