@@ -76,3 +76,58 @@ def test_convolve_at_agrees_with_the_direct_sum():
     full = cv.convolve_direct(M, K, 2.0)
     pts = [(0, 0), (23, 35), (5, 30), (12, 0)]
     assert np.allclose(cv.convolve_at(M, K, pts, 2.0), [full[j, i] for j, i in pts], rtol=1e-14)
+
+
+def _signed(n):
+    """Signed offsets of the wrapped indices 0..n-1 (n - k stands for -k)."""
+    k = np.arange(n)
+    return np.where(k <= n // 2, k, k - n)
+
+
+@pytest.mark.parametrize("shape", ["uniform", "gaussian", "power"])
+@pytest.mark.parametrize("pix1,pix2,R,hole", [(1.0, 1.0, 3.3, 0.0), (0.7, 1.3, 4.1, 0.0),
+                                               (1.0, 1.0, 5.2, 1.7), (0.25, 0.4, 2.05, 0.0)])
+def test_source_kernel_is_centred_on_pixel_zero(shape, pix1, pix2, R, hole):
+    """A circular profile centred on pixel (0, 0) (Section 2.4: the kernel is the
+    binned profile; centred, the convolved map is not shifted): the kernel is
+    unchanged under x1 -> -x1 and x2 -> -x2 separately, its centroid in wrapped
+    pixel offsets is (0, 0), and without a hole its largest value sits at
+    (0, 0). A kernel whose sub-samples or pixels are offset breaks all three."""
+    p1, p2 = 40, 36
+    K = cv.source_kernel(shape, p1, p2, pix1, pix2, R, hole)
+    flip1 = K[:, (-np.arange(p1)) % p1]
+    flip2 = K[(-np.arange(p2)) % p2, :]
+    assert np.allclose(K, flip1, rtol=1e-13, atol=1e-16)
+    assert np.allclose(K, flip2, rtol=1e-13, atol=1e-16)
+    s1, s2 = _signed(p1), _signed(p2)
+    assert abs(float(np.sum(K * s1[None, :]))) < 1e-13
+    assert abs(float(np.sum(K * s2[:, None]))) < 1e-13
+    if hole == 0.0:
+        assert K[0, 0] == K.max()
+    # the support reaches ceil(R / pix) pixels from the centre on each side
+    n1, n2 = int(np.ceil(R / pix1)), int(np.ceil(R / pix2))
+    nz_b, nz_a = np.nonzero(K)
+    assert np.abs(s1[nz_a]).max() <= n1 and np.abs(s2[nz_b]).max() <= n2
+
+
+def test_convolution_with_an_offset_delta_shifts_the_map():
+    """Eq. 6 is a convolution, not a correlation: a unit kernel at offset (b, a)
+    moves every pixel by (+b, +a), C[j, i] = M[j - b, i - a] (wrapped)."""
+    rng = np.random.default_rng(5)
+    M = rng.integers(0, 1000, size=(24, 40)).astype(np.float64)
+    K = np.zeros_like(M)
+    K[3, 5] = 1.0
+    want = np.roll(M, (3, 5), axis=(0, 1))
+    assert np.allclose(cv.convolve(M, K), want, rtol=0, atol=1e-9)
+    assert np.array_equal(cv.convolve_direct(M, K), want)
+    assert np.array_equal(cv.convolve_at(M.astype(np.int32), K, [(0, 0), (7, 39)]),
+                          [want[0, 0], want[7, 39]])
+
+
+def test_fft_convolution_with_an_asymmetric_kernel_equals_the_defining_sum():
+    rng = np.random.default_rng(6)
+    M = rng.integers(0, 50, size=(30, 20)).astype(np.float64)
+    K = np.zeros_like(M)
+    K[:4, :3] = rng.random((4, 3))
+    K[-2:, -1] = rng.random(2)
+    assert np.allclose(cv.convolve(M, K, 3.0), cv.convolve_direct(M, K, 3.0), rtol=0, atol=1e-10)

@@ -41,6 +41,12 @@ MUTANTS = {
     "codec-bits-off-by-one": ("while (b < 32 && ((int64_t)1 << b) < nd) ++b;",
                               "while (b < 32 && ((int64_t)1 << b) <= nd) ++b;"),
     "codec-unsorted-index": ("qsort(values, (size_t)n_pix, sizeof(int32_t), cmp_i32);", ""),
+    "normalise-float32-division": ("mu[k] = (float)((double)counts[k] / n_avg);",
+                                   "mu[k] = (float)counts[k] / (float)n_avg;"),
+    "normalise-reciprocal-multiply": ("mu[k] = (float)((double)counts[k] / n_avg);",
+                                      "mu[k] = (float)((double)counts[k] * (1.0 / n_avg));"),
+    "normalise-count-through-float": ("mu[k] = (float)((double)counts[k] / n_avg);",
+                                      "mu[k] = (float)((float)counts[k] / n_avg);"),
     "row-offset": ("const double x2 = base2 + ((double)j + 0.5) * d2;\n        for (int64_t i = 0; i < n1; ++i) {\n            const double x1 = base1 + ((double)i + 0.5) * d1;\n            double y1, y2;",
                    "const double x2 = base2 + ((double)(j - row_begin) + 0.5) * d2;\n        for (int64_t i = 0; i < n1; ++i) {\n            const double x1 = base1 + ((double)i + 0.5) * d1;\n            double y1, y2;"),
 }
@@ -68,3 +74,61 @@ def test_planted_mistake_is_caught(name, tmp_path):
                         os.path.join(ROOT, "tests", "test_oracle_codec.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutant {name} passed every pin:\n{r.stdout[-2000:]}"
+
+
+# Planted mistakes in the Python part of the oracle (finite-source kernels and
+# the convolution of Section 2.4, oracle/convolve.py): the mutated module is
+# loaded in place of oracle.convolve in a subprocess that runs its pin suite.
+CONVOLVE_SRC = os.path.join(ROOT, "oracle", "convolve.py")
+PY_MUTANTS = {
+    "kernel-subsamples-off-centre": ("off = (np.arange(subsamples) + 0.5) / subsamples - 0.5",
+                                     "off = np.arange(subsamples) / subsamples - 0.5"),
+    "kernel-pixel-shifted": ("K[j % p2, i % p1] = brightness(", "K[(j + 1) % p2, i % p1] = brightness("),
+    "kernel-not-normalised": ("return K / total", "return K"),
+    "correlation-not-convolution": ("C = np.fft.ifft2(np.fft.fft2(M) * np.fft.fft2(K)).real",
+                                    "C = np.fft.ifft2(np.fft.fft2(M) * np.conj(np.fft.fft2(K))).real"),
+    "gaussian-sigma": ("sigma = radius / 3.0", "sigma = radius / 2.0"),
+    "power-slope": ("I = (np.maximum(r, core) / radius) ** (-0.75)",
+                    "I = (np.maximum(r, core) / radius) ** (-0.5)"),
+    "hole-ignored": ("return np.where((r < radius) & (r >= hole), I, 0.0)",
+                     "return np.where(r < radius, I, 0.0)"),
+}
+
+_BOOT = """
+import importlib.util, sys
+sys.path.insert(0, {root!r})
+import oracle
+spec = importlib.util.spec_from_file_location("oracle.convolve", {path!r})
+mod = importlib.util.module_from_spec(spec)
+spec.loader.exec_module(mod)
+sys.modules["oracle.convolve"] = mod
+oracle.convolve = mod
+import pytest
+sys.exit(pytest.main(["-x", "-q", "-p", "no:cacheprovider", {tests!r}]))
+"""
+
+
+@pytest.mark.parametrize("name", sorted(PY_MUTANTS))
+def test_planted_mistake_in_convolution_oracle_is_caught(name, tmp_path):
+    old, new = PY_MUTANTS[name]
+    src = open(CONVOLVE_SRC).read()
+    assert src.count(old) == 1, f"mutation site for {name} not found"
+    path = tmp_path / "convolve_mutant.py"
+    path.write_text(src.replace(old, new))
+    code = _BOOT.format(root=ROOT, path=str(path),
+                        tests=os.path.join(ROOT, "tests", "test_oracle_convolve.py"))
+    r = subprocess.run([sys.executable, "-c", code], cwd=str(tmp_path), capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode not in (0, 4, 5), f"bad run for {name}:\n{r.stdout[-2000:]}{r.stderr[-2000:]}"
+    assert r.returncode != 0, f"mutant {name} passed every pin:\n{r.stdout[-2000:]}"
+
+
+def test_unmutated_convolution_oracle_passes_through_the_same_harness(tmp_path):
+    """The harness itself: the unchanged module loaded the same way passes."""
+    path = tmp_path / "convolve_copy.py"
+    path.write_text(open(CONVOLVE_SRC).read())
+    code = _BOOT.format(root=ROOT, path=str(path),
+                        tests=os.path.join(ROOT, "tests", "test_oracle_convolve.py"))
+    r = subprocess.run([sys.executable, "-c", code], cwd=str(tmp_path), capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]

@@ -120,6 +120,69 @@ def test_identity_map_gives_unit_magnification_everywhere():
     assert (oracle.normalise(counts, navg) == 1.0).all()
 
 
+def _nearest_f32(x):
+    """x (a Fraction) rounded to the nearest float32, ties to the even
+    significand, decided by exact rational comparisons."""
+    from fractions import Fraction as F
+    g = np.float32(float(x))
+    lo = g if F(float(g)) <= x else np.nextafter(g, np.float32(-np.inf))
+    hi = np.nextafter(lo, np.float32(np.inf))
+    if not np.isfinite(hi):
+        return lo
+    mid = (F(float(lo)) + F(float(hi))) / 2
+    if x < mid:
+        return lo
+    if x > mid:
+        return hi
+    return lo if (int(lo.view(np.uint32)) & 1) == 0 else hi
+
+
+def _mu_reference(c, n_avg):
+    """Eq. 4's mu = N / N_avg as this build reads it: the quotient rounded once
+    to the nearest double (CPython's int / int true division is correctly
+    rounded), then once to float32."""
+    from fractions import Fraction as F
+    q = F(int(c)) / F(n_avg)
+    return _nearest_f32(F(q.numerator / q.denominator))
+
+
+def test_normalisation_is_one_double_division_rounded_to_float32():
+    """mu_ij = N_ij / N_avg (eq. 4) per pixel: one FP64 division, rounded to
+    float32 for the output, checked against exact rational arithmetic on random
+    counts (0, 1, the int32 limits, odd counts above 2^24 that float32 cannot
+    hold), awkward and exact N_avg, and quotients built to sit within a double
+    ulp of a float32 rounding midpoint, where a reciprocal multiply or a
+    float32 division would round the other way."""
+    from fractions import Fraction as F
+    rng = np.random.default_rng(21)
+    counts = [0, 1, 2, 3, 7, 2**24 - 1, 2**24 + 1, 2**24 + 3, 2**31 - 1, 2**31 - 2, 123456789]
+    counts += [int(v) for v in rng.integers(0, 2**31 - 1, size=60)]
+    counts += [int(v) for v in rng.integers(0, 5000, size=60)]
+    n_avgs = [9.083601813271546, 0.9889717102050781, 16.0, 3.0, 1.0 / 3.0, 1e-3, 1e6,
+              float(rng.uniform(0.1, 100.0)), math.pi]
+    cases = [(c, n) for c in counts for n in n_avgs]
+    n_plain = len(cases)
+    # near-midpoint quotients: N_avg = c / m for a float32 midpoint m
+    for _ in range(400):
+        e = int(rng.integers(-8, 12))
+        f = np.float32(rng.uniform(1.0, 2.0) * 2.0**e)
+        m = (F(float(f)) + F(float(np.nextafter(f, np.float32(np.inf))))) / 2
+        c = int(rng.integers(1, 2**31 - 1))
+        q = F(c) / m
+        cases.append((c, q.numerator / q.denominator))
+    c_arr = np.array([c for c, _ in cases], np.int32)
+    for n in sorted(set(n for _, n in cases)):
+        sel = [k for k, (_, nn) in enumerate(cases) if nn == n]
+        got = oracle.normalise(c_arr[sel], n)
+        for k, g in zip(sel, got):
+            want = _mu_reference(cases[k][0], n)
+            assert g == want, (cases[k], float(g), float(want))
+            # away from float32 ties (the ordinary cases), the two roundings
+            # equal one rounding of the exact quotient
+            if k < n_plain:
+                assert want == _nearest_f32(F(int(cases[k][0])) / F(n))
+
+
 @pytest.mark.parametrize("kappa,gamma,s", [
     (0.5, 0.2, 1.0),    # a1=0.3, a2=0.7
     (0.5, 0.7, 1.0),    # a1<0: negative parity along x1
