@@ -67,7 +67,8 @@ typedef struct {
 /* Regular ray grid (Fig. 1): n1 x n2 rays at the centres of the cells of
  * [c1 - half1, c1 + half1) x [c2 - half2, c2 + half2), i.e. ray (i, j) sits at
  * x1 = (c1 - half1) + (i + 1/2) * 2 half1 / n1 and likewise for x2.
- * 0 < n1, n2 <= 2^40 and n1 n2 <= 2^50; half-widths finite and > 0. */
+ * 0 < n1 <= 2^26, 0 < n2 <= 2^40 and n1 n2 <= 2^50; half-widths finite and
+ * > 0. */
 typedef struct {
     int64_t n1;
     int64_t n2;
@@ -128,15 +129,23 @@ typedef struct {
 
 typedef struct rl_context rl_context;
 
-/* Creates a context bound to HIP device `hip_device`. No HIP call is made
- * here; the device is touched on first use, so creation never fails for
- * want of a GPU. *out receives the context. */
+/* Creates a context bound to HIP device `hip_device` (the "initialise the GPU
+ * device" step of the driver flow in Appendix A, Fig. "gpud_flow"). No HIP
+ * call is made here; the device is touched on the first call that uses it,
+ * so creation never fails for want of a GPU. *out receives the context, which
+ * the caller owns and releases with rl_destroy. RL_E_INVALID if out is NULL or
+ * hip_device < 0; RL_E_NOMEM if the host allocation fails. */
 rl_status rl_create(int32_t hip_device, rl_context** out);
 
-/* Releases the context and the device memory it owns. NULL is accepted. */
+/* Releases the context and the device and pinned host memory it owns (the
+ * memory the driver flow of Appendix A, Fig. "gpud_flow", allocates before
+ * running the kernel). Waits for the device first. NULL is accepted. */
 rl_status rl_destroy(rl_context* ctx);
 
-/* Message for the last failing call on this thread ("" if none). */
+/* Message for the last failing call on this thread ("" if none); the
+ * returned string is owned by the library and valid until the next rl_* call
+ * on the same thread. (Error reporting of this interface; the paper defines
+ * no error behaviour.) */
 const char* rl_last_error(void);
 
 /* Library version string. */
@@ -170,9 +179,13 @@ rl_status rl_stats_get(rl_context* ctx, const int32_t* d_counts, const int64_t* 
                        const rl_macro* macro, const rl_raygrid* grid, const rl_window* win,
                        rl_stats* h_out, hipStream_t stream);
 
-/* Parity hook for the binning step alone: bins n given FP64 source-plane
- * positions d_y1[n], d_y2[n] with the rule of rl_shoot, accumulating into
- * d_counts and *d_escaped. n >= 0. Asynchronous. */
+/* Parity hook for the binning step alone (the pixellated source plane of
+ * Section 2.1 and Fig. 1, whose pixel counts eq. 4 turns into
+ * magnifications): bins n given FP64 source-plane positions d_y1[n], d_y2[n]
+ * (device, caller-owned) with the rule of rl_shoot, accumulating into the
+ * caller-zeroed d_counts (int32, p2 x p1) and *d_escaped (int64). n >= 0;
+ * RL_E_INVALID for n < 0 or NULL pointers (positions may be NULL when n == 0).
+ * Asynchronous. */
 rl_status rl_bin_positions(rl_context* ctx, const double* d_y1, const double* d_y2, int64_t n,
                            const rl_window* win, int32_t* d_counts, int64_t* d_escaped,
                            hipStream_t stream);
@@ -200,10 +213,13 @@ typedef struct {
 } rl_map_desc;
 
 /* Shoots every map of h_maps[0 .. n_maps-1] (host array of descriptors) in
- * ONE persistent launch: workgroups pull (map, ray-cell range) items from a
- * shared counter until the list is empty, so maps of uneven lens counts and
- * sizes share the GPU. Results equal per-map rl_shoot calls bit for bit.
- * n_maps >= 0. Asynchronous; the descriptors are copied before return. */
+ * ONE persistent launch, the single-GPU form of the batches of map jobs that
+ * GERLUMPH submits to its job queue (Section 3.2.5, the `job' table):
+ * workgroups pull (map, ray-cell range) items from a shared counter until the
+ * list is empty, so maps of uneven lens counts and sizes share the GPU.
+ * Results equal per-map rl_shoot calls bit for bit. n_maps >= 0; each
+ * descriptor is validated as rl_shoot validates its arguments (the message
+ * names the map). Asynchronous; the descriptors are copied before return. */
 rl_status rl_shoot_batch(rl_context* ctx, const rl_map_desc* h_maps, int32_t n_maps,
                          int32_t precision, hipStream_t stream);
 

@@ -70,10 +70,12 @@ void fold_slots(const std::vector<unsigned long long>& h, unsigned long long out
 rl_status check_grid(const rl_raygrid* g) {
     if (!g) return fail(RL_E_INVALID, "ray grid is NULL");
     if (g->n1 <= 0 || g->n2 <= 0) return fail(RL_E_INVALID, "ray grid needs n1, n2 > 0");
-    // each side and the ray count stay far inside int64 (ray, cell and escape counts)
-    if (g->n1 > (int64_t)1 << 40 || g->n2 > (int64_t)1 << 40 ||
+    // the ray count stays far inside int64 (ray, cell and escape counts); one
+    // row of ray cells (>= 8 rays across) fits one launch of the shoot kernel
+    if (g->n1 > (int64_t)1 << 26 || g->n2 > (int64_t)1 << 40 ||
         (double)g->n1 * (double)g->n2 > (double)((int64_t)1 << 50))
-        return fail(RL_E_INVALID, "ray grid too large (at most 2^40 per side and 2^50 rays)");
+        return fail(RL_E_INVALID, "ray grid too large (at most 2^26 rays along x1, 2^40 along x2 "
+                    "and 2^50 rays)");
     if (!is_finite(g->c1) || !is_finite(g->c2)) return fail(RL_E_INVALID, "ray grid centre not finite");
     if (!is_finite(g->half1) || !is_finite(g->half2) || !(g->half1 > 0.0) || !(g->half2 > 0.0))
         return fail(RL_E_INVALID, "ray grid half-widths must be finite and > 0");

@@ -615,15 +615,33 @@ int grid_for(int64_t n, int threads, int cap) {
 template <int KX, int KY>
 constexpr int cells_per_wave() { return KX * KY / kRaysPerLane; }
 
+// Workgroups per launch of the single-map kernel: at most 2^23 (2^31
+// work-items with 4 waves, inside the 32-bit size of one dispatch). A longer
+// row range goes out as several launches over whole cell rows; a cell's rays
+// and lenses do not depend on the launch it is in, so no result changes. The
+// host refuses grids wider than 2^26 rays, so one cell row (at most 2^23
+// cells of >= 8 rays across) always fits one launch.
+constexpr int64_t kMaxBlocks = (int64_t)1 << 23;
+
 template <int KX, int KY, bool MASS, int SUBMAP, bool OUT_Y, int PREC>
 hipError_t launch_one(const MapParams& P, const KernelShape& ks, size_t lds, hipStream_t s) {
     constexpr int CPW = cells_per_wave<KX, KY>();
-    const int W = ks.waves;
-    const int64_t blocks = (P.n_cells + (int64_t)W * CPW - 1) / ((int64_t)W * CPW);
-    if (blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL((shoot_kernel<KX, KY, MASS, SUBMAP, OUT_Y, PREC, CPW>), dim3((unsigned)blocks),
-                       dim3(W * kLanes), lds, s, P, ks.lens_tile);
-    return hipGetLastError();
+    const int64_t per_block = (int64_t)ks.waves * CPW;
+    if (P.n_cells <= 0) return hipSuccess;
+    const int64_t rows = P.n_cells / P.cells_x;   // n_cells covers whole cell rows
+    const int64_t rows_per_launch = kMaxBlocks * per_block / P.cells_x;
+    if (rows_per_launch < 1 || rows * P.cells_x != P.n_cells) return hipErrorInvalidValue;
+    for (int64_t r0 = 0; r0 < rows; r0 += rows_per_launch) {
+        MapParams Q = P;
+        Q.cell_row0 = P.cell_row0 + r0;
+        Q.n_cells = (rows - r0 < rows_per_launch ? rows - r0 : rows_per_launch) * P.cells_x;
+        const int64_t blocks = (Q.n_cells + per_block - 1) / per_block;
+        hipLaunchKernelGGL((shoot_kernel<KX, KY, MASS, SUBMAP, OUT_Y, PREC, CPW>), dim3((unsigned)blocks),
+                           dim3(ks.waves * kLanes), lds, s, Q, ks.lens_tile);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <int KX, int KY, bool MASS, int SUBMAP, int PREC>

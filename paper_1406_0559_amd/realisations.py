@@ -28,7 +28,10 @@ def mean_mpd(ctx: "rl.Context", base, n: int = 15, nbins: int = 100, log_lo: flo
     Ls = [rl.DeviceLenses(f.x1, f.x2, f.m) for f in fields]
     maps = [ctx.new_map(s) for s in specs]
     ctx.shoot_batch([(L, s, c, e) for L, s, (c, e) in zip(Ls, specs, maps)], precision, stream=stream)
-    mu_th = abs(1.0 / ((1.0 - base.kappa) ** 2 - base.gamma ** 2))
+    # |mu_th| = |1 / ((1 - kappa)^2 - gamma^2)|, the macro-magnification that
+    # Section 4's MPD tools measure mu against, from the library's map
+    # statistics (every realisation shares kappa and gamma)
+    mu_th = abs(ctx.stats(maps[0][0], maps[0][1], specs[0], stream=stream)["mu_th"])
     bins = torch.zeros((n, nbins + 2), dtype=torch.int64, device=maps[0][0].device)
     for r, (s, (c, _)) in enumerate(zip(specs, maps)):
         ctx.mpd(c, s, mu_th, log_lo, log_hi, nbins, bins=bins[r], stream=stream)

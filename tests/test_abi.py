@@ -48,6 +48,7 @@ def test_invalid_arguments_are_rejected_on_the_host():
         cases = [
             ("n1 = 0", dict(g=rl.rl_raygrid(0, 64, 0.0, 0.0, 1.0, 1.0))),
             ("2^51 rays", dict(g=rl.rl_raygrid(1 << 26, 1 << 25, 0.0, 0.0, 1.0, 1.0))),
+            ("2^26 + 1 rays along x1", dict(g=rl.rl_raygrid((1 << 26) + 1, 2, 0.0, 0.0, 1.0, 1.0))),
             ("negative half-width", dict(g=rl.rl_raygrid(64, 64, 0.0, 0.0, -1.0, 1.0))),
             ("nan half-width", dict(g=rl.rl_raygrid(64, 64, 0.0, 0.0, math.nan, 1.0))),
             ("p2 = 0", dict(w=rl.rl_window(16, 0, 0.0, 0.0, 2.0, 2.0))),

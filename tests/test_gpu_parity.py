@@ -391,6 +391,40 @@ def test_stats_match_the_oracle(ctx):
 # full-size workloads in the benchmark's launch configuration, sampled rows
 # ---------------------------------------------------------------------------
 
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+def test_map_wider_than_one_launch(ctx, prec):
+    """A grid of 2^17 x 600000 rays (7.9e10; more cells than one launch of the
+    shoot kernel takes in any shape, 2^23 workgroups of at most 8 cells) is
+    shot as several launches over whole cell rows. With no lenses eq. 1 is
+    y = diag(a1, a2) x, so the map is the outer product of the per-axis
+    counts (the uniform-sheet pin), which the oracle gives from one row and
+    one column of rays."""
+    from paper_1406_0559_amd.inputs import MapSpec
+    spec = MapSpec(name="sheet-131072x600000", kappa=0.3, gamma=0.2, s=1.0, n1=1 << 17,
+                   n2=600000, h1=8.0, h2=8.0, p1=512, p2=512, W1=12.0, W2=12.0, n_lens=0)
+    assert spec.rays // 1024 > (1 << 23) * 8
+    empty = np.zeros(0)
+    counts, esc = ctx.shoot(rl.DeviceLenses(empty, empty), spec, prec)
+    print(f"  {spec.name} {prec}: shot", flush=True)
+    # x1 of every column from one row, x2 of every row from one column (the
+    # positions of a sheet do not depend on the other coordinate's count)
+    y1, _, _, _ = oracle.ray_positions(empty, empty, None, spec.kappa, spec.gamma, spec.s,
+                                       spec.n1, spec.n2, 0.0, 0.0, spec.h1, spec.h2, 0, 1)
+    _, y2, _, _ = oracle.ray_positions(empty, empty, None, spec.kappa, spec.gamma, spec.s,
+                                       1, spec.n2, 0.0, 0.0, spec.h1, spec.h2, 0, spec.n2)
+    col, _ = oracle.bin_positions(y1.ravel(), np.zeros(y1.size), spec.p1, spec.p2, 0.0, 0.0,
+                                  spec.W1, spec.W2)
+    row, _ = oracle.bin_positions(np.zeros(y2.size), y2.ravel(), spec.p1, spec.p2, 0.0, 0.0,
+                                  spec.W1, spec.W2)
+    n1_per_pixel = col.sum(axis=0).astype(np.int64)
+    n2_per_pixel = row.sum(axis=1).astype(np.int64)
+    want = np.outer(n2_per_pixel, n1_per_pixel)
+    got = counts.cpu().numpy().astype(np.int64)
+    assert want.sum() > 0 and want.max() < 2 ** 31
+    assert np.array_equal(got, want)
+    assert int(esc.item()) == spec.rays - int(want.sum())
+
+
 @pytest.fixture(scope="module")
 def bench_ctx():
     """A context in bench.py's launch configuration: the tuned shapes of the
