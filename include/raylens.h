@@ -167,6 +167,26 @@ rl_status rl_shoot(rl_context* ctx, const rl_lenses* lenses, const rl_macro* mac
                    int64_t row_begin, int64_t row_end,
                    int32_t* d_counts, int64_t* d_escaped, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): rl_shoot
+ * with the same arguments, validation and results (bit for bit the counts
+ * and escaped count rl_shoot gives with the same context), but it allocates
+ * nothing, neither device, host nor pinned memory, and creates no HIP object.
+ * The FP32 lens copies it stages go to one fixed array of the library per
+ * GPU, RL_NOALLOC_MAX_LENSES entries of 20 bytes (2.5 MiB), which each GPU
+ * the library runs on holds until the process ends; its device address is
+ * looked up on the first call on that device. RL_E_INVALID if lenses->n >
+ * RL_NOALLOC_MAX_LENSES. Every call on one GPU shares that array and it keeps
+ * the last call's contents (each call overwrites the entries it reads before
+ * reading them): calls that overlap on one GPU (other streams, threads or
+ * contexts) race and must be ordered by the caller. RL_FP64_PLAIN uses no
+ * staging. Asynchronous on `stream`. */
+#define RL_NOALLOC_MAX_LENSES 131072
+rl_status rl_shoot_noalloc(rl_context* ctx, const rl_lenses* lenses, const rl_macro* macro,
+                           const rl_raygrid* grid, const rl_window* win, int32_t precision,
+                           int64_t row_begin, int64_t row_end,
+                           int32_t* d_counts, int64_t* d_escaped, hipStream_t stream);
+
 /* Eq. 4: d_mu[k] = (float)((double)d_counts[k] / n_avg) for the p1 x p2
  * pixels of `win`. n_avg finite and > 0. Asynchronous. */
 rl_status rl_normalise(rl_context* ctx, const int32_t* d_counts, const rl_window* win,

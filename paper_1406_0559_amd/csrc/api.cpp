@@ -463,6 +463,38 @@ rl_status rl_shoot(rl_context* ctx, const rl_lenses* lenses, const rl_macro* mac
     return RL_OK;
 }
 
+rl_status rl_shoot_noalloc(rl_context* ctx, const rl_lenses* lenses, const rl_macro* macro,
+                           const rl_raygrid* grid, const rl_window* win, int32_t precision,
+                           int64_t row_begin, int64_t row_end, int32_t* d_counts,
+                           int64_t* d_escaped, hipStream_t stream) {
+    g_error.clear();
+    if (!ctx) return fail(RL_E_INVALID, "context is NULL");
+    RL_TRY(check_lenses(lenses));
+    RL_TRY(check_macro(macro));
+    RL_TRY(check_grid(grid));
+    RL_TRY(check_window(win));
+    RL_TRY(check_precision(precision));
+    RL_TRY(check_rows(grid, row_begin, row_end));
+    if (!d_counts || !d_escaped) return fail(RL_E_INVALID, "output pointers are NULL");
+    if (lenses->n > RL_NOALLOC_MAX_LENSES)
+        return fail(RL_E_INVALID, "rl_shoot_noalloc takes at most %d lenses (%lld given); "
+                    "use rl_shoot for larger fields", RL_NOALLOC_MAX_LENSES, (long long)lenses->n);
+    if (row_end == row_begin) return RL_OK;
+
+    rl::MapParams P;
+    build_params(macro, grid, win, row_begin, row_end, &P);
+    P.counts = d_counts;
+    P.escaped = reinterpret_cast<unsigned long long*>(d_escaped);
+    // no ensure_ready: that creates a HIP event on a context's first use
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return hip_fail(dg.err, "hipSetDevice");
+    const rl::KernelShape& ks = ctx->tuning[precision][rl::tuning_class(lenses->n, lenses->m != nullptr)];
+    const hipError_t e = rl::launch_shoot_noalloc(P, lenses->x1, lenses->x2, lenses->m, lenses->n,
+                                                  (rl::Precision)precision, ks, ctx->device, stream);
+    if (e != hipSuccess) return hip_fail(e, "shoot launch (no allocation)");
+    return RL_OK;
+}
+
 rl_status rl_ray_positions(rl_context* ctx, const rl_lenses* lenses, const rl_macro* macro,
                            const rl_raygrid* grid, int32_t precision, int64_t row_begin,
                            int64_t row_end, double* d_y1, double* d_y2, hipStream_t stream) {

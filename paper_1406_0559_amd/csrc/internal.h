@@ -106,6 +106,13 @@ hipError_t launch_bin_positions(const double* y1, const double* y2, int64_t n, i
                                 int32_t p2, double lo1, double lo2, double inv1, double inv2,
                                 int32_t* counts, unsigned long long* escaped, hipStream_t stream);
 hipError_t launch_fill_u32(unsigned int* p, int64_t n, unsigned int v, hipStream_t stream);
+// rl_shoot_noalloc's staging: the FP32 lens copies of P's lenses (FP64 x1,
+// x2, m; n <= RL_NOALLOC_MAX_LENSES, checked by the caller) go to the
+// library's fixed per-device array instead of context memory, then P is shot.
+// The device must be current.
+hipError_t launch_shoot_noalloc(MapParams P, const double* x1, const double* x2, const double* m,
+                                int64_t n, Precision prec, const KernelShape& ks, int device,
+                                hipStream_t stream);
 
 bool shape_supported(Precision prec, const KernelShape& ks);
 size_t shoot_lds_bytes(Precision prec, bool masses, const KernelShape& ks);

@@ -34,6 +34,7 @@
 //     on the sky, hence adjacent on the source plane) go to workgroups that
 //     run on the same XCD, so their atomics meet in the same L2.
 #include <climits>
+#include <mutex>
 
 #include "internal.h"
 
@@ -795,6 +796,66 @@ hipError_t launch_fill_u32(unsigned int* p, int64_t n, unsigned int v, hipStream
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// staging that allocates nothing (rl_shoot_noalloc)
+// ----------------------------------------------------------------------------
+
+namespace {
+
+// FP32 lens copies of rl_shoot_noalloc: RL_NOALLOC_MAX_LENSES float4 entries
+// {x1 hi, x1 lo, x2 hi, x2 lo}, then as many FP32 inverse masses. Each GPU
+// holds its own copy from the library's load until the process ends. Host
+// code never passes the array's name to a kernel (on the host it is only a
+// stand-in for the symbol): the device address comes from
+// hipGetSymbolAddress, once per device, with that device current.
+constexpr size_t kNoAllocXyBytes = (size_t)RL_NOALLOC_MAX_LENSES * sizeof(float4);
+constexpr size_t kNoAllocBytes = kNoAllocXyBytes + (size_t)RL_NOALLOC_MAX_LENSES * sizeof(float);
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_address(int device, unsigned char** out) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = p;
+    }
+    *out = static_cast<unsigned char*>(g_scratch_ptr[device]);
+    return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_shoot_noalloc(MapParams P, const double* x1, const double* x2, const double* m,
+                                int64_t n, Precision prec, const KernelShape& ks, int device,
+                                hipStream_t s) {
+    if (n < 0 || n > RL_NOALLOC_MAX_LENSES) return hipErrorInvalidValue;
+    if (prec == kFP32Comp) {
+        unsigned char* base = nullptr;
+        const hipError_t e = scratch_address(device, &base);
+        if (e != hipSuccess) return e;
+        float4* xy = reinterpret_cast<float4*>(base);
+        float* mf = reinterpret_cast<float*>(base + kNoAllocXyBytes);
+        // every entry the shoot kernel reads ([0, n)) is written here first
+        const hipError_t e2 = launch_prep_lenses(x1, x2, m, n, xy, m ? mf : nullptr, true, s);
+        if (e2 != hipSuccess) return e2;
+        P.lens32 = xy;
+        P.imass32 = m ? mf : nullptr;
+    } else {
+        P.lx1 = x1;
+        P.lx2 = x2;
+        P.lm = m;
+    }
+    P.n_lens = n;
+    return launch_shoot(P, prec, ks, false, 0, s);
 }
 
 }  // namespace rl

@@ -96,6 +96,8 @@ def load():
         "rl_n_avg": [P(rl_raygrid), P(rl_window), P(dbl)],
         "rl_shoot": [vp, P(rl_lenses), P(rl_macro), P(rl_raygrid), P(rl_window), C.c_int, i64, i64,
                      vp, vp, vp],
+        "rl_shoot_noalloc": [vp, P(rl_lenses), P(rl_macro), P(rl_raygrid), P(rl_window), C.c_int,
+                             i64, i64, vp, vp, vp],
         "rl_normalise": [vp, vp, P(rl_window), dbl, vp, vp],
         "rl_stats_get": [vp, vp, vp, P(rl_macro), P(rl_raygrid), P(rl_window), P(rl_stats), vp],
         "rl_bin_positions": [vp, vp, vp, i64, P(rl_window), vp, vp, vp],
@@ -163,6 +165,16 @@ def rl_shoot(ctx, lenses, macro, grid, win, precision, row_begin, row_end, d_cou
              stream=None):
     _check(load().rl_shoot(ctx, C.byref(lenses), C.byref(macro), C.byref(grid), C.byref(win),
                            precision, row_begin, row_end, d_counts, d_escaped, stream))
+
+
+def rl_shoot_noalloc(ctx, lenses, macro, grid, win, precision, row_begin, row_end, d_counts,
+                     d_escaped, stream=None):
+    _check(load().rl_shoot_noalloc(ctx, C.byref(lenses), C.byref(macro), C.byref(grid),
+                                   C.byref(win), precision, row_begin, row_end, d_counts,
+                                   d_escaped, stream))
+
+
+RL_NOALLOC_MAX_LENSES = 131072   # include/raylens.h
 
 
 def rl_normalise(ctx, d_counts, win, n_avg, d_mu, stream=None):
@@ -342,6 +354,16 @@ class Context:
         rl_shoot(self.handle, lenses.struct(self.device), macro_of(spec), grid_of(spec), window_of(spec),
                  PRECISIONS[precision], row_begin, spec.n2 if row_end is None else row_end,
                  counts.data_ptr(), escaped.data_ptr(), _stream_ptr(stream))
+        return counts, escaped
+
+    def shoot_noalloc(self, lenses: DeviceLenses, spec, precision, counts, escaped, row_begin=0,
+                      row_end=None, stream=None):
+        """rl_shoot_noalloc into caller-made (zeroed) counts and escaped tensors."""
+        _check_map_tensors(counts, escaped, spec, self.device)
+        rl_shoot_noalloc(self.handle, lenses.struct(self.device), macro_of(spec), grid_of(spec),
+                         window_of(spec), PRECISIONS[precision], row_begin,
+                         spec.n2 if row_end is None else row_end, counts.data_ptr(),
+                         escaped.data_ptr(), _stream_ptr(stream))
         return counts, escaped
 
     def ray_positions(self, lenses: DeviceLenses, spec, precision="fp32c", row_begin=0,

@@ -56,6 +56,18 @@ int main(void) {
     EXPECT(rl_shoot(ctx, &L, &M, &G, &W, RL_FP32_COMP, 5, 3, fake_i, fake_l, NULL), RL_E_INVALID);
     EXPECT(rl_shoot(ctx, &L, &M, &G, &W, RL_FP32_COMP, 0, 17, fake_i, fake_l, NULL), RL_E_INVALID);
     EXPECT(rl_shoot(ctx, &L, &M, &G, &W, RL_FP32_COMP, 0, 16, NULL, fake_l, NULL), RL_E_INVALID);
+    {
+        const rl_lenses Lbig = {fake_d, fake_d, NULL, (int64_t)RL_NOALLOC_MAX_LENSES + 1};
+        EXPECT(rl_shoot_noalloc(NULL, &L, &M, &G, &W, RL_FP32_COMP, 0, 16, fake_i, fake_l, NULL), RL_E_INVALID);
+        EXPECT(rl_shoot_noalloc(ctx, &Lbad, &M, &G, &W, RL_FP32_COMP, 0, 16, fake_i, fake_l, NULL), RL_E_INVALID);
+        EXPECT(rl_shoot_noalloc(ctx, &L, &Mnan, &G, &W, RL_FP32_COMP, 0, 16, fake_i, fake_l, NULL), RL_E_INVALID);
+        EXPECT(rl_shoot_noalloc(ctx, &L, &M, &Gbad, &W, RL_FP32_COMP, 0, 16, fake_i, fake_l, NULL), RL_E_INVALID);
+        EXPECT(rl_shoot_noalloc(ctx, &L, &M, &G, &Wbad, RL_FP32_COMP, 0, 16, fake_i, fake_l, NULL), RL_E_INVALID);
+        EXPECT(rl_shoot_noalloc(ctx, &L, &M, &G, &W, 7, 0, 16, fake_i, fake_l, NULL), RL_E_INVALID);
+        EXPECT(rl_shoot_noalloc(ctx, &L, &M, &G, &W, RL_FP32_COMP, 5, 3, fake_i, fake_l, NULL), RL_E_INVALID);
+        EXPECT(rl_shoot_noalloc(ctx, &L, &M, &G, &W, RL_FP32_COMP, 0, 16, fake_i, NULL, NULL), RL_E_INVALID);
+        EXPECT(rl_shoot_noalloc(ctx, &Lbig, &M, &G, &W, RL_FP32_COMP, 0, 16, fake_i, fake_l, NULL), RL_E_INVALID);
+    }
     EXPECT(rl_ray_positions(ctx, &L, &M, &G, RL_FP64_PLAIN, 0, 17, fake_d, fake_d, NULL), RL_E_INVALID);
     EXPECT(rl_ray_positions(ctx, &L, &M, &G, RL_FP64_PLAIN, 0, 1, NULL, fake_d, NULL), RL_E_INVALID);
     EXPECT(rl_normalise(ctx, fake_i, &W, 0.0, fake_f, NULL), RL_E_INVALID);

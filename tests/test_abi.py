@@ -62,13 +62,21 @@ def test_invalid_arguments_are_rejected_on_the_host():
             ("bad precision", dict(prec=7)),
             ("null counts", dict(counts=None)),
         ]
-        for label, kw in cases:
-            st = lib.rl_shoot(ctx, C.byref(kw.get("L", L)), C.byref(kw.get("m", m)),
-                              C.byref(kw.get("g", g)), C.byref(kw.get("w", w)),
-                              kw.get("prec", rl.RL_FP32_COMP), kw.get("rb", 0), kw.get("re", 64),
-                              kw.get("counts", fake), fake, None)
-            assert st == rl.RL_E_INVALID, label
-            assert rl.rl_last_error(), label
+        for fn in (lib.rl_shoot, lib.rl_shoot_noalloc):
+            for label, kw in cases:
+                st = fn(ctx, C.byref(kw.get("L", L)), C.byref(kw.get("m", m)),
+                        C.byref(kw.get("g", g)), C.byref(kw.get("w", w)),
+                        kw.get("prec", rl.RL_FP32_COMP), kw.get("rb", 0), kw.get("re", 64),
+                        kw.get("counts", fake), fake, None)
+                assert st == rl.RL_E_INVALID, label
+                assert rl.rl_last_error(), label
+        # the no-allocation entry point's lens limit, refused before any HIP call
+        big = rl.rl_lenses(fake, fake, None, rl.RL_NOALLOC_MAX_LENSES + 1)
+        assert lib.rl_shoot_noalloc(ctx, C.byref(big), C.byref(m), C.byref(g), C.byref(w), 0, 0,
+                                    64, fake, fake, None) == rl.RL_E_INVALID
+        assert "at most 131072 lenses" in rl.rl_last_error()
+        assert lib.rl_shoot_noalloc(None, C.byref(L), C.byref(m), C.byref(g), C.byref(w), 0, 0,
+                                    64, fake, fake, None) == rl.RL_E_INVALID
         assert lib.rl_shoot(None, C.byref(L), C.byref(m), C.byref(g), C.byref(w), 0, 0, 64, fake,
                             fake, None) == rl.RL_E_INVALID
         assert lib.rl_normalise(ctx, fake, C.byref(w), 0.0, fake, None) == rl.RL_E_INVALID
