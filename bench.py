@@ -48,6 +48,16 @@ def parse():
                     help="map-size scale of the served requests (1.0 = 1024^2-4096^2 maps)")
     ap.add_argument("--serve-saturate", action="store_true",
                     help="queue every serving request at t = 0 (the server's saturated rate)")
+    ap.add_argument("--serve-rate", type=float, default=None,
+                    help="Poisson arrival rate in requests/s (default: 70 %% of the saturated "
+                         "request rate implied by the measured evaluations/s)")
+    ap.add_argument("--serve-log", default=None,
+                    help="append one JSON line per finished request (and a running summary "
+                         "every 50) to this file as the run goes")
+    ap.add_argument("--serve-chunk-evals", type=float, default=2e11,
+                    help="ray-lens evaluations per serving launch")
+    ap.add_argument("--serve-min-launch-rays", type=float, default=2.5e7,
+                    help="rays per serving launch, at least (about 8 ray cells per wave slot)")
     ap.add_argument("--no-tuning-cache", action="store_true")
     ap.add_argument("--no-post", action="store_true", help="skip the MPD and codec legs")
     ap.add_argument("--no-mixed", action="store_true",
@@ -342,8 +352,9 @@ def main():
         rspecs = realisations.realisation_specs(base, 15)
         rL = [rl.DeviceLenses(*(lambda f: (f.x1, f.x2, f.m))(sp.lenses())) for sp in rspecs]
         routs = [ctx.new_map(sp) for sp in rspecs]
-        mu_th_r = abs(1.0 / ((1.0 - base.kappa) ** 2 - base.gamma ** 2))
         navg_r = rl.rl_n_avg(rl.grid_of(base), rl.window_of(base))
+        c0, e0 = routs[0]
+        mu_th_r = abs(ctx.stats(c0, e0, base, stream=stream)["mu_th"])   # the library's mu_th
         rbins = torch.zeros((15, 102), dtype=torch.int64, device="cuda")
 
         def run_reals():
@@ -381,31 +392,61 @@ def main():
         probe = inputs.serve_requests(args.serve_requests, rate=1.0, seed=5,
                                       size_scale=args.serve_scale)
         mean_evals = float(np.mean([r.spec.evals for r in probe]))
-        lam = 0.7 * value / mean_evals          # 70 % of the saturated request rate
+        # 70 % of the saturated request rate unless a rate is given
+        lam = args.serve_rate if args.serve_rate else 0.7 * value / mean_evals
         reqs = inputs.serve_requests(args.serve_requests, rate=lam, seed=5,
                                      size_scale=args.serve_scale)
         if args.serve_saturate:                 # every request queued at t = 0
             lam = None
         mreqs = [serve.MapRequest(r.rid, r.spec, r.spec.lenses(), 0.0 if args.serve_saturate else r.arrival)
                  for r in reqs]
+        by_rid = {r.rid: r for r in reqs}
         be = serve.GpuBackend(ctx=ctx)
-        done = [0]
+        log = open(args.serve_log, "a") if args.serve_log else None
+        lat_done = []
+        evals_done = [0]
+        t_start = [None]
 
         def progress(res):
-            done[0] += 1
-            if done[0] % 25 == 0:
-                print(f"serving: {done[0]}/{len(mreqs)} requests finished", file=sys.stderr, flush=True)
+            spec = by_rid[res.rid].spec
+            if res.state is serve.State.DONE:
+                lat_done.append(res.latency)
+                evals_done[0] += spec.evals
+            if log is not None:
+                log.write(json.dumps({"rid": res.rid, "state": res.state.value,
+                                      "arrival_s": res.arrival, "admitted_s": res.admitted,
+                                      "finished_s": res.finished, "latency_s": res.latency,
+                                      "pixels": spec.p1, "lenses": spec.n_lens,
+                                      "rays": spec.rays, "evals": spec.evals,
+                                      "error": res.error}) + "\n")
+                if len(lat_done) % 50 == 0 and res.state is serve.State.DONE:
+                    el = time.perf_counter() - t_start[0]
+                    log.write(json.dumps({"summary": True, "completed": len(lat_done),
+                                          "elapsed_s": el, "p50_s": percentile(lat_done, 50),
+                                          "p99_s": percentile(lat_done, 99),
+                                          "evals_per_s": evals_done[0] / el}) + "\n")
+                log.flush()
+            res.counts = None               # delivered; not kept for the whole run
+            n = len(lat_done)
+            if res.state is serve.State.DONE and n % 25 == 0:
+                print(f"serving: {n}/{len(mreqs)} requests finished", file=sys.stderr, flush=True)
 
         sch = serve.Scheduler(be, budget_bytes=serve.gpu_budget_bytes(0.5), max_active=16,
-                              chunk_evals=2e11, max_inflight=2, on_finish=progress)
+                              chunk_evals=args.serve_chunk_evals,
+                              min_launch_rays=int(args.serve_min_launch_rays), max_inflight=2,
+                              work_rate=value, on_finish=progress)
         ts = time.perf_counter()
+        t_start[0] = ts
         res = sch.run(mreqs)
         tserve = time.perf_counter() - ts
+        if log is not None:
+            log.close()
         summ = serve.latency_summary(res)
         sizes = sorted({r.spec.p1 for r in reqs})
         serving = {"workload": f"serve-{args.serve_requests}req-maps{sizes[0]}-{sizes[-1]}"
                                + ("-saturated" if args.serve_saturate else ""),
                    "arrival_rate_per_s": lam, "mean_evals_per_request": mean_evals,
+                   "offered_load": (lam * mean_evals / value) if lam else None,
                    "launches": sch.launches, "peak_active": sch.peak_active,
                    "wall_s": tserve, **summ,
                    "p50_ms": summ["p50_s"] * 1e3 if summ["p50_s"] is not None else None,

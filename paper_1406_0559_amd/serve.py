@@ -9,11 +9,18 @@ scheduler:
     and an active slot is free; a request that does not fit may be overtaken
     by later ones that do, but only until it has waited `aging_s`;
   * keeps each admitted request's lens field and partial count map resident;
-  * cuts every request into chunks of ray rows (about `chunk_evals`
-    ray-lens evaluations each, aligned to 128 rows) and, at every tick, packs
-    the next chunk of *every* active request into one batched persistent
-    launch, so requests that arrive while others run join the very next
-    launch and their work overlaps on the device;
+  * cuts requests into chunks of ray rows (multiples of 128 rows) and, at
+    every tick, fills one batched persistent launch with about `chunk_evals`
+    ray-lens evaluations (and at least `min_launch_rays` rays, so a launch
+    holds enough ray cells to fill the device), taking chunks from the active
+    requests in order of smallest remaining work first with an aging bound:
+    a request's key is its remaining work in seconds minus `age_weight` times
+    the time it has waited since arrival. A request that arrives while others
+    run joins the very next launch if its key is smallest, and its work
+    overlaps with theirs on the device; a request is overtaken by a later
+    arrival only while the newcomer's remaining work is smaller than its own
+    key, so after waiting remaining / age_weight seconds nothing that arrives
+    later goes before it;
   * keeps up to `max_inflight` launches queued on the stream so the device
     never waits for the host, and finalises a request (normalisation and
     statistics) as soon as the launch holding its last chunk has finished;
@@ -92,7 +99,6 @@ class _Active:
     handle: object
     footprint: int
     next_row: int
-    rows_per_chunk: int
     admitted: float
     inflight: int = 0             # launches still holding a chunk of this request
     last_token: object = None
@@ -114,11 +120,16 @@ class Scheduler:
                  chunk_evals: float = 2.0e11, max_inflight: int = 2, aging_s: float = 5.0,
                  clock: Callable[[], float] = time.perf_counter, keep_mu: bool = False,
                  sleep: Callable[[float], None] = time.sleep,
-                 on_finish: Optional[Callable[["MapResult"], None]] = None):
+                 on_finish: Optional[Callable[["MapResult"], None]] = None,
+                 min_launch_rays: int = 0, age_weight: float = 0.25,
+                 work_rate: float = 8.0e12):
         self.backend = backend
         self.budget = int(budget_bytes)
         self.max_active = max_active
-        self.chunk_evals = chunk_evals
+        self.chunk_evals = chunk_evals           # ray-lens evaluations per launch
+        self.min_launch_rays = min_launch_rays   # rays per launch, at least (work permitting)
+        self.age_weight = age_weight             # seconds of priority gained per second waited
+        self.work_rate = work_rate               # evaluations/s that turn work into seconds
         self.max_inflight = max_inflight
         self.aging_s = aging_s
         self.clock = clock
@@ -217,11 +228,16 @@ class Scheduler:
         if self.on_finish is not None:
             self.on_finish(res)
 
-    def _rows_per_chunk(self, spec) -> int:
-        per_row = max(1, spec.n1 * max(spec.n_lens, 1))
-        rows = int(self.chunk_evals // per_row)
-        rows = max(ROW_ALIGN, (rows // ROW_ALIGN) * ROW_ALIGN)
-        return rows
+    @staticmethod
+    def _evals_per_row(spec) -> int:
+        return max(1, spec.n1 * max(spec.n_lens, 1))
+
+    def priority(self, a: "_Active", now: float) -> tuple:
+        """Launch order key: remaining work (seconds at work_rate) minus
+        age_weight times the time waited since arrival; ties by arrival."""
+        remaining = (a.req.spec.n2 - a.next_row) * self._evals_per_row(a.req.spec)
+        return (remaining / self.work_rate - self.age_weight * (now - a.req.arrival),
+                a.req.arrival, a.req.rid)
 
     def _admit(self) -> bool:
         did = False
@@ -245,8 +261,7 @@ class Scheduler:
             if req.resume is not None:
                 self.backend.load_partial(handle, req.resume.counts, req.resume.escaped)
                 start = req.resume.next_row
-            self.active[req.rid] = _Active(req, handle, fp, start, self._rows_per_chunk(req.spec),
-                                           now)
+            self.active[req.rid] = _Active(req, handle, fp, start, now)
             self.used += fp
             self.peak_used = max(self.peak_used, self.used)
             self.peak_active = max(self.peak_active, len(self.active))
@@ -254,15 +269,31 @@ class Scheduler:
         return did
 
     def _launch(self) -> bool:
-        by_prec: Dict[str, list] = {}
-        for a in self.active.values():
-            if a.cancelled or a.failed or a.paused or a.next_row >= a.req.spec.n2:
-                continue
-            rb = a.next_row
-            re = min(a.req.spec.n2, rb + a.rows_per_chunk)
-            by_prec.setdefault(a.req.precision, []).append((a, rb, re))
-        if not by_prec:
+        now = self.now()
+        ready = [a for a in self.active.values()
+                 if not (a.cancelled or a.failed or a.paused or a.next_row >= a.req.spec.n2)]
+        if not ready:
             return False
+        ready.sort(key=lambda a: self.priority(a, now))
+        # fill one launch per precision: chunks in key order until the launch
+        # holds chunk_evals evaluations and min_launch_rays rays
+        by_prec: Dict[str, list] = {}
+        filled: Dict[str, list] = {}
+        for a in ready:
+            prec = a.req.precision
+            ev, rays = filled.setdefault(prec, [0, 0])
+            need_ev = self.chunk_evals - ev
+            need_rays = self.min_launch_rays - rays
+            if need_ev <= 0 and need_rays <= 0:
+                continue
+            spec = a.req.spec
+            per_row = self._evals_per_row(spec)
+            rows = max(-(-int(max(need_ev, 0)) // per_row), -(-int(max(need_rays, 0)) // spec.n1))
+            rows = max(ROW_ALIGN, -(-rows // ROW_ALIGN) * ROW_ALIGN)
+            rb = a.next_row
+            re = min(spec.n2, rb + rows)
+            by_prec.setdefault(prec, []).append((a, rb, re))
+            filled[prec] = [ev + (re - rb) * per_row, rays + (re - rb) * spec.n1]
         for prec, chunks in by_prec.items():
             try:
                 token = self.backend.launch([(a.handle, a.req.spec, rb, re) for a, rb, re in chunks],
@@ -357,8 +388,10 @@ def latency_summary(results: Dict[int, MapResult]) -> dict:
 # ---------------------------------------------------------------------------
 
 class GpuBackend:
-    """Device side of the server: one stream for the batched launches, one
-    for finalisation (both at the default priority)."""
+    """Device side of the server, on three streams at the default priority:
+    uploads of admitted requests (lens field, zeroed count map), the batched
+    launches, and finalisation. The launch stream waits on each upload with
+    an event, so an upload never waits for queued launches."""
 
     def __init__(self, ctx=None, device: int = 0):
         import torch
@@ -368,15 +401,19 @@ class GpuBackend:
         self.rl = rl
         self.device = device
         self.ctx = ctx if ctx is not None else rl.Context(device)
+        self.upload_stream = torch.cuda.Stream(device=device)
         self.launch_stream = torch.cuda.Stream(device=device)
         self.final_stream = torch.cuda.Stream(device=device)
 
     def admit(self, req):
         torch = self.torch
-        with torch.cuda.stream(self.launch_stream):
+        with torch.cuda.stream(self.upload_stream):
             L = self.rl.DeviceLenses(req.lenses.x1, req.lenses.x2, req.lenses.m,
                                      device=f"cuda:{self.device}")
             counts, esc = self.ctx.new_map(req.spec)
+            ready = torch.cuda.Event()
+            ready.record(self.upload_stream)
+        self.launch_stream.wait_event(ready)
         return {"L": L, "counts": counts, "esc": esc, "spec": req.spec}
 
     def load_partial(self, h, counts: np.ndarray, escaped: int) -> None:
@@ -410,9 +447,11 @@ class GpuBackend:
         return token.query()
 
     def finalize(self, h, keep_mu: bool = False):
+        """Called once the launch holding the request's last chunk has
+        completed, so the final stream needs no wait on the launch stream (a
+        wait there would also wait for every launch queued after it)."""
         torch = self.torch
         s = self.final_stream
-        s.wait_stream(self.launch_stream)
         spec = h["spec"]
         with torch.cuda.stream(s):
             mu = self.ctx.normalise(h["counts"], spec, stream=s) if keep_mu else None

@@ -106,6 +106,7 @@ def whole(req):
 def make(clock, backend, **kw):
     kw.setdefault("budget_bytes", 1 << 30)
     kw.setdefault("chunk_evals", 128 * 300 * 20)
+    kw.setdefault("work_rate", backend.rate)
     return Scheduler(backend, clock=clock, sleep=clock.advance, **kw)
 
 
@@ -251,3 +252,65 @@ def test_on_finish_is_called_once_per_request():
     res = sch.run(reqs)
     assert sorted(rid for rid, _ in seen) == sorted(res) == list(range(5))
     assert all(st is State.DONE for _, st in seen)
+
+
+def tiny_request(rid, n1, n2, arrival):
+    """A request whose cost is set by its ray count (10 unit lenses, 16^2 map)."""
+    spec = inputs.MapSpec(name=f"t{rid}", kappa=0.45, gamma=0.2, s=0.0, n1=n1, n2=n2, h1=6.0,
+                          h2=3.0, p1=16, p2=16, W1=4.0, W2=4.0, n_lens=10, disc_radius=5.0,
+                          masses="unit", seed=500 + rid)
+    return MapRequest(rid, spec, spec.lenses(), arrival)
+
+
+def test_small_request_behind_large_ones_finishes_within_two_launches():
+    """Smallest remaining work first: a small request that arrives while three
+    large ones are active goes into the next launch that starts after it
+    arrives and finishes with it (at most max_inflight launches later)."""
+    clock = Clock()
+    be = CpuBackend(clock, rate=1e6)
+    bigs = [tiny_request(i, 200, 1280, 0.0) for i in range(3)]          # 2.56 s of work each
+    small = tiny_request(9, 64, 64, 1.0)                                # 0.04 s
+    sch = make(clock, be, chunk_evals=128 * 200 * 10, max_inflight=2)  # 0.256 s per launch
+    res = sch.run(bigs + [small])
+    assert all(r.state is State.DONE for r in res.values())
+    for req in bigs + [small]:
+        c, e = whole(req)
+        assert (res[req.rid].counts == c).all() and res[req.rid].escaped == e
+    after = [t for t, _ in be.launch_log if t >= small.arrival]
+    first = next(t for t, rids in be.launch_log if 9 in rids)
+    assert first == after[0], "the small request missed the first launch after its arrival"
+    assert res[9].latency <= 3 * 0.256 + 1e-9
+    assert all(res[9].finished < res[i].finished for i in range(3))
+
+
+def _stream_with_one_large(age_weight):
+    clock = Clock()
+    be = CpuBackend(clock, rate=1e6)
+    big = tiny_request(0, 200, 1000, 0.0)                               # 2 s of work
+    smalls = [tiny_request(i, 64, 64, 0.05 * i) for i in range(1, 241)]  # 0.041 s each, load 0.82
+    sch = make(clock, be, chunk_evals=0.2e6, age_weight=age_weight)
+    res = sch.run([big] + smalls)
+    assert all(r.state is State.DONE for r in res.values())
+    for req in (big, smalls[0], smalls[-1]):
+        c, e = whole(req)
+        assert (res[req.rid].counts == c).all() and res[req.rid].escaped == e
+    return res, big, smalls
+
+
+def test_aging_bounds_the_wait_of_a_large_request():
+    """Under a steady stream of small requests (82 % load), the large request's
+    key (remaining seconds - age_weight * waited) reaches zero after
+    remaining / age_weight seconds; from then on no newcomer goes first, so
+    it finishes within that time plus its own work plus a launch or two.
+    Pure smallest-remaining-first (age_weight = 0) finishes it later."""
+    work = 200 * 1000 * 10 / 1e6
+    res, big, smalls = _stream_with_one_large(0.25)
+    bound = big.arrival + work / 0.25 + work + 2 * 0.2
+    assert res[0].finished <= bound, (res[0].finished, bound)
+    # while the large request is young the small ones wait for at most the
+    # two queued launches (each about one large chunk of 0.256 s) and their own
+    young = [res[s.rid].latency for s in smalls if s.arrival < 2.0]
+    assert max(young) < 4 * 0.3
+    assert np.median([res[s.rid].latency for s in smalls]) < 1.0
+    pure, _, _ = _stream_with_one_large(0.0)
+    assert pure[0].finished > res[0].finished

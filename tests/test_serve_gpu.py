@@ -32,7 +32,7 @@ def test_served_maps_equal_maps_shot_alone():
     reqs = mixed_requests()
     be = serve.GpuBackend()
     sch = serve.Scheduler(be, budget_bytes=serve.gpu_budget_bytes(0.25), max_active=8,
-                          chunk_evals=2e9, max_inflight=2)
+                          chunk_evals=5e8, max_inflight=2)
     res = sch.run(reqs)
     assert all(r.state is serve.State.DONE for r in res.values()), \
         {k: (r.state, r.error) for k, r in res.items()}
@@ -61,13 +61,16 @@ def test_checkpoint_resume_and_cancel_on_the_gpu():
     target = serve.MapRequest(50, spec, spec.lenses(), 0.0, "fp32c")
     reqs = [target] + base
     be = serve.GpuBackend()
-    # 9 chunks of 128 rows for the target; at most two launches before the checkpoint
+    # 9 chunks of 128 rows for the target; the first launch is the target's
+    # first chunk alone, then the others join; at most two launches before
+    # the checkpoint
     sch = serve.Scheduler(be, budget_bytes=serve.gpu_budget_bytes(0.25),
                           chunk_evals=spec.n1 * spec.n_lens * 128, max_inflight=1)
-    for r in reqs:
+    sch.submit(target)
+    sch.step()
+    for r in base:
         sch.submit(r)
-    for _ in range(2):
-        sch.step()
+    sch.step()
     cp = sch.checkpoint(target.rid)
     assert 0 < cp.next_row < spec.n2
     sch.cancel(base[0].rid)
