@@ -130,6 +130,10 @@ def main():
             tuned = True
         except rl.RaylensError:
             tuned = False
+            table = autotune.load(autotune.DEFAULT_CACHE) or {}
+            print(f"bench: the tuning cache was made for {table.get('library')!r}, not for "
+                  f"{rl.rl_version()!r}: default kernel shapes (run python -m "
+                  "paper_1406_0559_amd.autotune on the GPU to retune)", file=sys.stderr, flush=True)
     L = rl.DeviceLenses(field.x1, field.x2, field.m)
     counts, esc = ctx.new_map(spec)
     mu = torch.empty((spec.p2, spec.p1), dtype=torch.float32, device="cuda")

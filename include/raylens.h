@@ -233,10 +233,11 @@ typedef struct {
 } rl_map_desc;
 
 /* Shoots every map of h_maps[0 .. n_maps-1] (host array of descriptors) in
- * ONE persistent launch, the single-GPU form of the batches of map jobs that
- * GERLUMPH submits to its job queue (Section 3.2.5, the `job' table):
- * workgroups pull (map, ray-cell range) items from a shared counter until the
- * list is empty, so maps of uneven lens counts and sizes share the GPU.
+ * one persistent launch per tuning class present (see rl_get_tuning), the
+ * single-GPU form of the batches of map jobs that GERLUMPH submits to its job
+ * queue (Section 3.2.5, the `job' table): workgroups pull (map, ray-cell
+ * range) items from a shared counter until the list is empty, so maps of
+ * uneven lens counts and sizes share the GPU, each with its class's shape.
  * Results equal per-map rl_shoot calls bit for bit. n_maps >= 0; each
  * descriptor is validated as rl_shoot validates its arguments (the message
  * names the map). Asynchronous; the descriptors are copied before return. */
@@ -270,8 +271,7 @@ typedef struct {
 /* Reads / sets the kernel shape used for `precision` and tuning class
  * `n_class`: 0 (n < 1000 lenses), 1 (n < 10000), 2 (n >= 10000) for unit
  * masses, 3, 4, 5 for the same lens counts with masses (rl_lenses.m != NULL;
- * a batch uses the class of its largest lens count, with masses if any map
- * has them). Host only. */
+ * every map of a batch uses its own class). Host only. */
 rl_status rl_get_tuning(rl_context* ctx, int32_t precision, int32_t n_class,
                         rl_tuning* h_out);
 rl_status rl_set_tuning(rl_context* ctx, int32_t precision, int32_t n_class,

@@ -642,58 +642,62 @@ rl_status rl_shoot_batch(rl_context* ctx, const rl_map_desc* h_maps, int32_t n_m
     }
     if (n_maps == 0) return RL_OK;
 
-    // kernel shape: the class of the largest lens count in the batch
-    int64_t nmax = 0;
-    bool masses = false;
+    // one persistent launch per tuning class present, each with its class's
+    // kernel shape (kernel shapes change no result bit, so every map still
+    // equals the map shot alone)
     int64_t total_lens = 0;
+    std::vector<int> cls((size_t)n_maps);
     for (int32_t i = 0; i < n_maps; ++i) {
-        nmax = std::max(nmax, h_maps[i].lenses.n);
-        masses = masses || h_maps[i].lenses.m != nullptr;
+        cls[i] = rl::tuning_class(h_maps[i].lenses.n, h_maps[i].lenses.m != nullptr);
         total_lens += h_maps[i].lenses.n;
     }
-    const rl::KernelShape ks = ctx->tuning[precision][rl::tuning_class(nmax, masses)];
 
     std::vector<rl::MapParams> params((size_t)n_maps);
-    std::vector<rl::WorkItem> items;
-    std::vector<double> cost;
-    for (int32_t i = 0; i < n_maps; ++i) {
-        const rl_map_desc& d = h_maps[i];
-        build_params(&d.macro, &d.grid, &d.win, d.row_begin, d.row_end, &params[i]);
-        params[i].counts = d.d_counts;
-        params[i].escaped = reinterpret_cast<unsigned long long*>(d.d_escaped);
-        params[i].n_lens = d.lenses.n;
-        // cells per item: item_cells cells' worth of work at 2048 lenses, so
-        // items carry about the same work whatever the lens count (short
-        // items for large fields keep the tail of the launch short, long
-        // items for small fields amortise the fetch of the next item), in
-        // whole workgroup passes
-        const int64_t pass = (int64_t)ks.waves * ((ks.rays_x * ks.rays_y) / rl::kRaysPerLane);
-        int64_t per = (int64_t)std::llround((double)ks.item_cells * 2048.0 / (double)(d.lenses.n + 8));
-        per = std::min<int64_t>(std::max<int64_t>(per, pass), 4096);
-        per = (per + pass - 1) / pass * pass;
-        for (int64_t c = 0; c < params[i].n_cells; c += per) {
-            const int64_t nc = std::min<int64_t>(per, params[i].n_cells - c);
-            items.push_back(rl::WorkItem{i, 0, c, nc});
+    std::vector<rl::WorkItem> sorted;
+    int64_t seg_begin[rl::kTuningClasses + 1] = {0};
+    for (int c = 0; c < rl::kTuningClasses; ++c) {
+        seg_begin[c] = (int64_t)sorted.size();
+        const rl::KernelShape& ks = ctx->tuning[precision][c];
+        std::vector<rl::WorkItem> items;
+        for (int32_t i = 0; i < n_maps; ++i) {
+            if (cls[i] != c) continue;
+            const rl_map_desc& d = h_maps[i];
+            build_params(&d.macro, &d.grid, &d.win, d.row_begin, d.row_end, &params[i]);
+            params[i].counts = d.d_counts;
+            params[i].escaped = reinterpret_cast<unsigned long long*>(d.d_escaped);
+            params[i].n_lens = d.lenses.n;
+            // cells per item: item_cells cells' worth of work at 2048 lenses, so
+            // items carry about the same work whatever the lens count (short
+            // items for large fields keep the tail of the launch short, long
+            // items for small fields amortise the fetch of the next item), in
+            // whole workgroup passes
+            const int64_t pass = (int64_t)ks.waves * ((ks.rays_x * ks.rays_y) / rl::kRaysPerLane);
+            int64_t per = (int64_t)std::llround((double)ks.item_cells * 2048.0 / (double)(d.lenses.n + 8));
+            per = std::min<int64_t>(std::max<int64_t>(per, pass), 4096);
+            per = (per + pass - 1) / pass * pass;
+            for (int64_t cc = 0; cc < params[i].n_cells; cc += per) {
+                const int64_t nc = std::min<int64_t>(per, params[i].n_cells - cc);
+                items.push_back(rl::WorkItem{i, 0, cc, nc});
+            }
         }
+        // most expensive items first so the tail of the launch is made of cheap ones
+        std::stable_sort(items.begin(), items.end(), [&](const rl::WorkItem& a, const rl::WorkItem& b) {
+            const double ca = (double)(params[a.map].n_lens + 8) * a.ncells;
+            const double cb = (double)(params[b.map].n_lens + 8) * b.ncells;
+            return ca > cb;
+        });
+        sorted.insert(sorted.end(), items.begin(), items.end());
     }
-    if (items.empty()) return RL_OK;
-    // most expensive items first so the tail of the launch is made of cheap ones
-    std::vector<size_t> order(items.size());
-    for (size_t k = 0; k < order.size(); ++k) order[k] = k;
-    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
-        const double ca = (double)(params[items[a].map].n_lens + 8) * items[a].ncells;
-        const double cb = (double)(params[items[b].map].n_lens + 8) * items[b].ncells;
-        return ca > cb;
-    });
-    std::vector<rl::WorkItem> sorted(items.size());
-    for (size_t k = 0; k < order.size(); ++k) sorted[k] = items[order[k]];
+    seg_begin[rl::kTuningClasses] = (int64_t)sorted.size();
+    if (sorted.empty()) return RL_OK;
 
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return hip_fail(dg.err, "hipSetDevice");
     RL_TRY(ensure_ready(ctx));
     hipError_t e;
 
-    // FP32 lens copies for every map, one region per map
+    // FP32 lens copies for every map, one region per map; inverse masses for
+    // the maps that have masses
     if (precision == RL_FP32_COMP) {
         const size_t bytes = (size_t)std::max<int64_t>(total_lens, 1) * (sizeof(float4) + sizeof(float));
         e = ctx->lens.acquire(bytes, stream);
@@ -703,11 +707,11 @@ rl_status rl_shoot_batch(rl_context* ctx, const rl_map_desc* h_maps, int32_t n_m
         int64_t off = 0;
         for (int32_t i = 0; i < n_maps; ++i) {
             const rl_lenses& L = h_maps[i].lenses;
-            e = rl::launch_prep_lenses(L.x1, L.x2, L.m, L.n, xy + off, masses ? mf + off : nullptr, true,
-                                       stream);
+            const bool mi = L.m != nullptr;
+            e = rl::launch_prep_lenses(L.x1, L.x2, L.m, L.n, xy + off, mi ? mf + off : nullptr, true, stream);
             if (e != hipSuccess) return hip_fail(e, "prep_lenses launch");
             params[i].lens32 = xy + off;
-            params[i].imass32 = masses ? mf + off : nullptr;
+            params[i].imass32 = mi ? mf + off : nullptr;
             off += L.n;
         }
     } else {
@@ -718,7 +722,7 @@ rl_status rl_shoot_batch(rl_context* ctx, const rl_map_desc* h_maps, int32_t n_m
         }
     }
 
-    // records: [MapParams x n][WorkItem x n_items][counter]
+    // records: [MapParams x n][WorkItem x n_items][one counter per class]
     const size_t pbytes = sizeof(rl::MapParams) * (size_t)n_maps;
     const size_t ioff = (pbytes + 255) & ~(size_t)255;
     const size_t ibytes = sizeof(rl::WorkItem) * sorted.size();
@@ -734,10 +738,17 @@ rl_status rl_shoot_batch(rl_context* ctx, const rl_map_desc* h_maps, int32_t n_m
     char* ds = static_cast<char*>(ctx->batch.ptr);
     RL_TRY(stage_send(ctx, ds, total, stream));
 
-    e = rl::launch_shoot_batch(reinterpret_cast<const rl::MapParams*>(ds),
-                               reinterpret_cast<const rl::WorkItem*>(ds + ioff),
-                               (int64_t)sorted.size(), reinterpret_cast<unsigned int*>(ds + coff),
-                               (rl::Precision)precision, masses, ks, ctx->num_cus, stream);
+    const rl::MapParams* dmaps = reinterpret_cast<const rl::MapParams*>(ds);
+    const rl::WorkItem* ditems = reinterpret_cast<const rl::WorkItem*>(ds + ioff);
+    unsigned int* dcount = reinterpret_cast<unsigned int*>(ds + coff);
+    e = hipSuccess;
+    for (int c = 0; c < rl::kTuningClasses && e == hipSuccess; ++c) {
+        const int64_t n_items = seg_begin[c + 1] - seg_begin[c];
+        if (n_items == 0) continue;
+        e = rl::launch_shoot_batch(dmaps, ditems + seg_begin[c], n_items, dcount + c,
+                                   (rl::Precision)precision, c >= 3, ctx->tuning[precision][c],
+                                   ctx->num_cus, stream);
+    }
     hipError_t e2 = ctx->batch.release(stream);
     hipError_t e3 = precision == RL_FP32_COMP ? ctx->lens.release(stream) : hipSuccess;
     if (e == hipSuccess) e = e2;

@@ -497,6 +497,367 @@ __global__ void product_kernel(cplx* __restrict__ t, int n1, int n2) {
 }
 
 // ----------------------------------------------------------------------------
+// power-of-two sides (256 .. 8192): three passes, register-resident FFTs
+// ----------------------------------------------------------------------------
+//
+// Both M and K are real, so each is taken through real transforms whose
+// half spectra (u1 in [0, H), H = p1 / 2 + 1) are all that the product needs:
+//   A. rows: one complex FFT of two rows of M (M_j + i M_j+1) and one of two
+//      rows of K, unpacked into the half spectra of the four rows and stored
+//      in 64-byte chunks per row pair and frequency,
+//      a[x2 / 2][u1] = {M^(x2, u1), K^(x2, u1), M^(x2 + 1, u1), K^(x2 + 1, u1)},
+//      consecutive u1 at consecutive chunks (a workgroup's stores are
+//      contiguous);
+//   B. one column u1 per workgroup: forward FFTs of both columns along x2,
+//      their product, the inverse FFT along x2, stored as g[u1][x2];
+//   C. four rows per workgroup: the inverse FFTs of rows x2 (two rows per
+//      complex FFT, g(x2) + i g(x2 + 1), extended to u1 >= H by Hermitian
+//      symmetry), whose real and imaginary parts are rows x2 and x2 + 1 of
+//      C, times 1 / (p1 p2 n_avg).
+// Each pass reads and writes HBM once: pass B reads the columns of pass A's
+// output 32 bytes per row from 64-byte chunks (a column's neighbour in the
+// same cache line is read by the next workgroup, on the same XCD), pass C
+// reads the columns of pass B's output in 64-byte pieces; all stores are
+// contiguous. About 68 bytes per pixel in all, against 20 of input and
+// output. Rows of the same magnitude share a transform, so no balancing
+// factor is needed.
+//
+// The FFTs are Stockham transforms with T threads of E = N / T points each:
+// thread t holds the elements t + T m (m < E) between stages, reads them
+// straight from global memory for the first stage and keeps the last stage's
+// outputs, which are again t + T m; the stages in between exchange through an
+// LDS row padded by one slot in 16. Stage s (radix R, NS = product of the
+// earlier radices) turns butterfly j = t + T b (b < E / R) of inputs
+// x[j + q N / R] into y[(j / NS) NS R + j % NS + q NS], after the twiddles
+// w^q, w = exp(-+2 pi i (j % NS) / (NS R)) read from a table of one entry per
+// j % NS and stage (p2_twiddle_kernel), its powers formed in registers.
+
+// E = 8 points per thread (4 for N = 256): radix-8 stages, the last one of
+// radix 2 or 4 where N is not a power of 8.
+template <int N> constexpr int p2_threads() { return N == 256 ? 64 : N / 8; }
+template <int N> constexpr int p2_stages() {
+    return N == 512 ? 3 : (N == 8192 ? 5 : 4);
+}
+template <int N, int S> constexpr int p2_radix() {
+    return N == 256 ? 4
+         : N == 1024 ? (S < 3 ? 8 : 2)
+         : N == 2048 ? (S < 3 ? 8 : 4)
+         : N == 8192 ? (S < 4 ? 8 : 2)
+         : 8;    // 512, 4096
+}
+template <int N> constexpr int p2_lds() { return N + N / 16; }
+// NS of stage S (the product of the radices before it) and the offset of its
+// entries in the base-twiddle table: stage S holds exp(-2 pi i k / (NS R))
+// for k < NS at p2_tw_offset<N, S>() + k.
+template <int N, int S> constexpr int p2_ns() { return S == 0 ? 1 : p2_ns<N, (S > 0 ? S - 1 : 0)>() * p2_radix<N, (S > 0 ? S - 1 : 0)>(); }
+template <int N, int S> constexpr int p2_tw_offset() {
+    return S == 0 ? 0 : p2_tw_offset<N, (S > 0 ? S - 1 : 0)>() + p2_ns<N, (S > 0 ? S - 1 : 0)>();
+}
+
+// w^1 .. w^(R-1) from w by products (at most three roundings deep, so within a
+// few units of FP64 rounding of the exact roots).
+template <int R>
+__device__ __forceinline__ void twiddle_powers(cplx w, cplx (&p)[R]) {
+    p[1] = w;
+    if constexpr (R > 2) p[2] = cmul(w, w);
+    if constexpr (R > 3) p[3] = cmul(p[2], w);
+    if constexpr (R > 4) { p[4] = cmul(p[2], p[2]); p[5] = cmul(p[4], w); p[6] = cmul(p[3], p[3]);
+                           p[7] = cmul(p[6], w); }
+}
+
+// Base twiddles of a power-of-two plan: entry e of stage s (offset off_s,
+// off_0 = 0, off_s+1 = off_s + L[s]) is exp(-2 pi i k / L[s+1]), k = e - off_s.
+__global__ void p2_twiddle_kernel(cplx* __restrict__ tw, FftPlan P) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    int off = 0, s = 0;
+    while (s < P.ns && e >= off + P.L[s]) { off += P.L[s]; ++s; }
+    if (s >= P.ns) return;
+    double sn, cs;
+    sincospi(2.0 * (double)(e - off) / (double)P.L[s + 1], &sn, &cs);
+    tw[e] = cplx{cs, -sn};
+}
+
+__device__ __forceinline__ int pad16(int e) { return e + (e >> 4); }
+
+template <int N, int S, int NS, int V>
+__device__ __forceinline__ void p2_fft(cplx (&a)[V][N / p2_threads<N>()], cplx* __restrict__ lds,
+                                       const cplx* __restrict__ tw, bool inverse) {
+    constexpr int T = p2_threads<N>(), E = N / T, R = p2_radix<N, S>(), B = E / R;
+    constexpr bool kLast = NS * R == N;
+    const double sg = inverse ? 1.0 : -1.0;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int j = t + T * b;
+            const int k = j & (NS - 1);
+            cplx x[R];
+#pragma unroll
+            for (int q = 0; q < R; ++q) x[q] = a[v][b + q * B];
+            if constexpr (NS > 1) {
+                cplx w = tw[p2_tw_offset<N, S>() + k];
+                if (inverse) w.y = -w.y;
+                cplx wp[R];
+                twiddle_powers<R>(w, wp);
+#pragma unroll
+                for (int q = 1; q < R; ++q) x[q] = cmul(x[q], wp[q]);
+            }
+            small_dft<R>(x, sg);
+            if constexpr (kLast) {
+#pragma unroll
+                for (int q = 0; q < R; ++q) a[v][b + q * B] = x[q];
+            } else {
+                const int base = (j / NS) * NS * R + k;
+#pragma unroll
+                for (int q = 0; q < R; ++q) lds[pad16(base + q * NS)] = x[q];
+            }
+        }
+        if constexpr (!kLast) {
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < E; ++m) a[v][m] = lds[pad16(t + T * m)];
+            __syncthreads();
+        }
+    }
+    if constexpr (!kLast) p2_fft<N, S + 1, NS * R, V>(a, lds, tw, inverse);
+}
+
+// Bijective remap of a block id: blocks dispatched to the same XCD (block b
+// runs on XCD b % 8) take consecutive rows, so pieces of one cache line meet
+// in one L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int x = b % 8, idx = b / 8, per = nb / 8, rem = nb % 8;
+    return x < rem ? x * (per + 1) + idx : rem * (per + 1) + (x - rem) * per + idx;
+}
+
+// Pass A. Block = rows j0, j0 + 1 of the p2 x N maps M and K.
+template <int N>
+__global__ void __launch_bounds__(p2_threads<N>())
+p2_rows_fwd_kernel(const int32_t* __restrict__ M, const double* __restrict__ K, int p2,
+                   cplx* __restrict__ A, const cplx* __restrict__ tw) {
+    constexpr int T = p2_threads<N>(), E = N / T;
+    __shared__ cplx lds[p2_lds<N>()];
+    const int t = threadIdx.x;
+    const int j0 = 2 * xcd_block(blockIdx.x, gridDim.x);
+    const int32_t* __restrict__ m0 = M + (int64_t)j0 * N;
+    const double* __restrict__ k0 = K + (int64_t)j0 * N;
+    cplx a[2][E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int i = t + T * m;
+        a[0][m] = cplx{(double)m0[i], (double)m0[N + i]};
+        a[1][m] = cplx{k0[i], k0[N + i]};
+    }
+    p2_fft<N, 0, 1, 2>(a, lds, tw, false);
+    // unpack: X^(u) = (Z(u) + conj Z(-u)) / 2, Y^(u) = (Z(u) - conj Z(-u)) / 2i,
+    // stored at once: the four 16-byte pieces of a row pair's 64 bytes (M^ and
+    // K^ of rows j0 and j0 + 1) are written by this thread and meet in L2
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) lds[pad16(t + T * m)] = a[v][m];
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m <= E / 2; ++m) {
+            if (m == E / 2 && t != 0) continue;     // u = N / 2 belongs to thread 0
+            const int u = t + T * m;
+            const cplx zu = a[v][m];
+            const cplx zm = lds[pad16((N - u) & (N - 1))];
+            cplx* __restrict__ o = A + ((int64_t)(j0 / 2) * (N / 2 + 1) + u) * 4 + v;
+            o[0] = cplx{0.5 * (zu.x + zm.x), 0.5 * (zu.y - zm.y)};
+            o[2] = cplx{0.5 * (zu.y + zm.y), 0.5 * (zm.x - zu.x)};
+        }
+        __syncthreads();
+    }
+}
+
+// Pass B. Block = column u1 of the half spectra (p2 = N points along x2);
+// the two forward transforms run one after the other (fewer live registers:
+// two workgroups fit a CU).
+template <int N>
+__global__ void __launch_bounds__(p2_threads<N>())
+__attribute__((amdgpu_waves_per_eu(N >= 2048 && N <= 4096 ? 4 : 1)))
+p2_cols_kernel(const cplx* __restrict__ A, int H, cplx* __restrict__ G, const cplx* __restrict__ tw) {
+    constexpr int T = p2_threads<N>(), E = N / T;
+    __shared__ cplx lds[p2_lds<N>()];
+    const int t = threadIdx.x;
+    const int u1 = xcd_block(blockIdx.x, gridDim.x);
+    // chunk (x2 / 2, u1), piece 2 (x2 % 2) + {0: M^, 1: K^}
+    const cplx* __restrict__ col = A + (int64_t)u1 * 4;
+    cplx a[1][E], b[1][E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int i = t + T * m;
+        a[0][m] = col[(int64_t)(i >> 1) * H * 4 + (i & 1) * 2];
+    }
+    p2_fft<N, 0, 1, 1>(a, lds, tw, false);
+    // keep K^'s loads after M^'s transform: hoisted, they would hold registers
+    // through it
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int i = t + T * m;
+        b[0][m] = col[(int64_t)(i >> 1) * H * 4 + (i & 1) * 2 + 1];
+    }
+    p2_fft<N, 0, 1, 1>(b, lds, tw, false);
+#pragma unroll
+    for (int m = 0; m < E; ++m) a[0][m] = cmul(a[0][m], b[0][m]);
+    p2_fft<N, 0, 1, 1>(a, lds, tw, true);
+    cplx* __restrict__ g = G + (int64_t)u1 * N;
+#pragma unroll
+    for (int m = 0; m < E; ++m) g[t + T * m] = a[0][m];
+}
+
+// Pass C. Block = rows j0 .. j0 + 3 of the output (p1 = N points along x1).
+template <int N>
+__global__ void __launch_bounds__(p2_threads<N>())
+p2_rows_inv_kernel(const cplx* __restrict__ G, int p2, double scale, double* __restrict__ out,
+                   const cplx* __restrict__ tw) {
+    constexpr int T = p2_threads<N>(), E = N / T, H = N / 2 + 1;
+    __shared__ cplx lds[p2_lds<N>()];
+    const int t = threadIdx.x;
+    const int j0 = 4 * xcd_block(blockIdx.x, gridDim.x);
+    cplx a[2][E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int u = t + T * m;
+        const bool mirror = u >= H;
+        const int src = mirror ? N - u : u;
+        const cplx* __restrict__ c = G + (int64_t)src * p2 + j0;
+        const cplx c0 = c[0], c1 = c[1], c2 = c[2], c3 = c[3];
+        // g(x2) + i g(x2 + 1), or its value at -u: conj g(x2) + i conj g(x2 + 1)
+        if (!mirror) {
+            a[0][m] = cplx{c0.x - c1.y, c0.y + c1.x};
+            a[1][m] = cplx{c2.x - c3.y, c2.y + c3.x};
+        } else {
+            a[0][m] = cplx{c0.x + c1.y, c1.x - c0.y};
+            a[1][m] = cplx{c2.x + c3.y, c3.x - c2.y};
+        }
+    }
+    p2_fft<N, 0, 1, 2>(a, lds, tw, true);
+    double* __restrict__ o = out + (int64_t)j0 * N;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int i = t + T * m;
+        o[i] = a[0][m].x * scale;
+        o[N + i] = a[0][m].y * scale;
+        o[2 * N + i] = a[1][m].x * scale;
+        o[3 * N + i] = a[1][m].y * scale;
+    }
+}
+
+bool pow2_side(int n) { return n == 256 || n == 512 || n == 1024 || n == 2048 || n == 4096 || n == 8192; }
+
+// The stage radices of a power-of-two side as an FftPlan (for the base
+// twiddle table: L[s] = NS of stage s).
+template <int N>
+FftPlan p2_plan() {
+    FftPlan P{};
+    P.n = N;
+    P.ns = p2_stages<N>();
+    const int r[5] = {p2_radix<N, 0>(), p2_radix<N, 1>(), p2_radix<N, 2>(), p2_radix<N, 3>(),
+                      p2_radix<N, 4>()};
+    P.L[0] = 1;
+    for (int s = 0; s < P.ns; ++s) {
+        P.r[s] = r[s];
+        P.L[s + 1] = P.L[s] * r[s];
+        P.div[s] = 0;
+    }
+    return P;
+}
+
+FftPlan p2_plan_of(int n) {
+    switch (n) {
+        case 256: return p2_plan<256>();
+        case 512: return p2_plan<512>();
+        case 1024: return p2_plan<1024>();
+        case 2048: return p2_plan<2048>();
+        case 4096: return p2_plan<4096>();
+        default: return p2_plan<8192>();
+    }
+}
+
+template <int N>
+hipError_t p2_rows_fwd(const int32_t* M, const double* K, int p2, cplx* A, const cplx* tw, hipStream_t s) {
+    hipLaunchKernelGGL(p2_rows_fwd_kernel<N>, dim3(p2 / 2), dim3(p2_threads<N>()), 0, s, M, K, p2, A, tw);
+    return hipGetLastError();
+}
+template <int N>
+hipError_t p2_cols(const cplx* A, cplx* G, int H, const cplx* tw, hipStream_t s) {
+    hipLaunchKernelGGL(p2_cols_kernel<N>, dim3(H), dim3(p2_threads<N>()), 0, s, A, H, G, tw);
+    return hipGetLastError();
+}
+template <int N>
+hipError_t p2_rows_inv(const cplx* G, int p2, double scale, double* out, const cplx* tw, hipStream_t s) {
+    hipLaunchKernelGGL(p2_rows_inv_kernel<N>, dim3(p2 / 4), dim3(p2_threads<N>()), 0, s, G, p2, scale,
+                       out, tw);
+    return hipGetLastError();
+}
+
+hipError_t p2_rows_fwd_any(int n, const int32_t* M, const double* K, int p2, cplx* A, const cplx* tw,
+                           hipStream_t s) {
+#define RL_CALL(N) p2_rows_fwd<N>(M, K, p2, A, tw, s)
+    switch (n) {
+        case 256: return RL_CALL(256);
+        case 512: return RL_CALL(512);
+        case 1024: return RL_CALL(1024);
+        case 2048: return RL_CALL(2048);
+        case 4096: return RL_CALL(4096);
+        default: return RL_CALL(8192);
+    }
+#undef RL_CALL
+}
+hipError_t p2_cols_any(int n, const cplx* A, cplx* G, int H, const cplx* tw, hipStream_t s) {
+#define RL_CALL(N) p2_cols<N>(A, G, H, tw, s)
+    switch (n) {
+        case 256: return RL_CALL(256);
+        case 512: return RL_CALL(512);
+        case 1024: return RL_CALL(1024);
+        case 2048: return RL_CALL(2048);
+        case 4096: return RL_CALL(4096);
+        default: return RL_CALL(8192);
+    }
+#undef RL_CALL
+}
+hipError_t p2_rows_inv_any(int n, const cplx* G, int p2, double scale, double* out, const cplx* tw,
+                           hipStream_t s) {
+#define RL_CALL(N) p2_rows_inv<N>(G, p2, scale, out, tw, s)
+    switch (n) {
+        case 256: return RL_CALL(256);
+        case 512: return RL_CALL(512);
+        case 1024: return RL_CALL(1024);
+        case 2048: return RL_CALL(2048);
+        case 4096: return RL_CALL(4096);
+        default: return RL_CALL(8192);
+    }
+#undef RL_CALL
+}
+
+size_t p2_scratch_bytes(int p1, int p2) {
+    const size_t h = (size_t)(p1 / 2 + 1) * p2;
+    return h * 3 * sizeof(cplx) + (size_t)(p1 + p2) * sizeof(cplx) + 256;
+}
+
+hipError_t p2_convolve(const int32_t* counts, const double* kernel, int p1, int p2, double n_avg,
+                       double* out, void* scratch, hipStream_t s) {
+    const int H = p1 / 2 + 1;
+    cplx* A = static_cast<cplx*>(scratch);                 // p2 / 2 x H x {M^, K^ of two rows}
+    cplx* G = A + (size_t)H * p2 * 2;                      // H x p2
+    cplx* tw1 = G + (size_t)H * p2;                        // stage twiddles along x1
+    cplx* tw2 = tw1 + p1;                                  // ... along x2
+    const FftPlan P1 = p2_plan_of(p1), P2 = p2_plan_of(p2);
+    hipLaunchKernelGGL(p2_twiddle_kernel, dim3((p1 + 255) / 256), dim3(256), 0, s, tw1, P1);
+    hipLaunchKernelGGL(p2_twiddle_kernel, dim3((p2 + 255) / 256), dim3(256), 0, s, tw2, P2);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = p2_rows_fwd_any(p1, counts, kernel, p2, A, tw1, s);
+    if (e == hipSuccess) e = p2_cols_any(p2, A, G, H, tw2, s);
+    if (e == hipSuccess)
+        e = p2_rows_inv_any(p1, G, p2, 1.0 / ((double)p1 * (double)p2 * n_avg), out, tw1, s);
+    return e;
+}
+
+// ----------------------------------------------------------------------------
 // source kernels
 // ----------------------------------------------------------------------------
 
@@ -626,12 +987,14 @@ bool fft_side_supported(int n) {
 }
 
 size_t convolve_scratch_bytes(int p1, int p2) {
+    if (pow2_side(p1) && pow2_side(p2)) return p2_scratch_bytes(p1, p2);
     const size_t plane = (size_t)p1 * p2 * sizeof(cplx);
     return 2 * plane + (size_t)(p1 + 2 * p2) * sizeof(cplx) + (2 * kNormBlocks + 2) * sizeof(double) + 256;
 }
 
 hipError_t launch_convolve(const int32_t* counts, const double* kernel, int p1, int p2, double n_avg,
                            double* out, void* scratch, hipStream_t s) {
+    if (pow2_side(p1) && pow2_side(p2)) return p2_convolve(counts, kernel, p1, p2, n_avg, out, scratch, s);
     // plans for the x1 rows, the x2 row pairs and (long columns) the x2 rows
     FftPlan P1, P2, P2r;
     if (p1 > kMaxFftSide || p2 > kMaxFftSide || !make_plan(p1, &P1, max_radix(p1, 1, row_threads(p1))) ||
