@@ -509,18 +509,19 @@ __global__ void product_kernel(cplx* __restrict__ t, int n1, int n2) {
 //      consecutive u1 at consecutive chunks (a workgroup's stores are
 //      contiguous);
 //   B. one column u1 per workgroup: forward FFTs of both columns along x2,
-//      their product, the inverse FFT along x2, stored as g[u1][x2];
+//      their product, the inverse FFT along x2, stored in 64-byte chunks of
+//      four rows, g[x2 / 4][u1] = {g(x2 .. x2 + 3, u1)};
 //   C. four rows per workgroup: the inverse FFTs of rows x2 (two rows per
 //      complex FFT, g(x2) + i g(x2 + 1), extended to u1 >= H by Hermitian
 //      symmetry), whose real and imaginary parts are rows x2 and x2 + 1 of
 //      C, times 1 / (p1 p2 n_avg).
-// Each pass reads and writes HBM once: pass B reads the columns of pass A's
-// output 32 bytes per row from 64-byte chunks (a column's neighbour in the
-// same cache line is read by the next workgroup, on the same XCD), pass C
-// reads the columns of pass B's output in 64-byte pieces; all stores are
-// contiguous. About 68 bytes per pixel in all, against 20 of input and
-// output. Rows of the same magnitude share a transform, so no balancing
-// factor is needed.
+// Each pass reads and writes HBM once. The axis changes go through the chunk
+// layouts: pass B reads 32 bytes per row of pass A's chunks and writes its
+// column four lanes to a chunk (a chunk's neighbour in the same cache line
+// belongs to the next column, the next workgroup on the same XCD); passes A
+// and C store and load whole chunks at consecutive addresses. About 68 bytes
+// per pixel in all, against 20 of input and output. Rows of the same
+// magnitude share a transform, so no balancing factor is needed.
 //
 // The FFTs are Stockham transforms with T threads of E = N / T points each:
 // thread t holds the elements t + T m (m < E) between stages, reads them
@@ -631,44 +632,46 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     return x < rem ? x * (per + 1) + idx : rem * (per + 1) + (x - rem) * per + idx;
 }
 
-// Pass A. Block = rows j0, j0 + 1 of the p2 x N maps M and K.
+// Pass A. Block = rows j0, j0 + 1 of the p2 x N maps M and K; the M pair and
+// the K pair are transformed one after the other (fewer live registers: two
+// workgroups fit a CU).
 template <int N>
 __global__ void __launch_bounds__(p2_threads<N>())
+__attribute__((amdgpu_waves_per_eu(N >= 2048 && N <= 4096 ? 4 : 1)))
 p2_rows_fwd_kernel(const int32_t* __restrict__ M, const double* __restrict__ K, int p2,
                    cplx* __restrict__ A, const cplx* __restrict__ tw) {
     constexpr int T = p2_threads<N>(), E = N / T;
     __shared__ cplx lds[p2_lds<N>()];
     const int t = threadIdx.x;
     const int j0 = 2 * xcd_block(blockIdx.x, gridDim.x);
-    const int32_t* __restrict__ m0 = M + (int64_t)j0 * N;
-    const double* __restrict__ k0 = K + (int64_t)j0 * N;
-    cplx a[2][E];
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-        const int i = t + T * m;
-        a[0][m] = cplx{(double)m0[i], (double)m0[N + i]};
-        a[1][m] = cplx{k0[i], k0[N + i]};
-    }
-    p2_fft<N, 0, 1, 2>(a, lds, tw, false);
-    // unpack: X^(u) = (Z(u) + conj Z(-u)) / 2, Y^(u) = (Z(u) - conj Z(-u)) / 2i,
-    // stored at once: the four 16-byte pieces of a row pair's 64 bytes (M^ and
-    // K^ of rows j0 and j0 + 1) are written by this thread and meet in L2
 #pragma unroll
     for (int v = 0; v < 2; ++v) {
+        cplx a[1][E];
 #pragma unroll
-        for (int m = 0; m < E; ++m) lds[pad16(t + T * m)] = a[v][m];
+        for (int m = 0; m < E; ++m) {
+            const int i = t + T * m;
+            if (v == 0) a[0][m] = cplx{(double)M[(int64_t)j0 * N + i], (double)M[(int64_t)(j0 + 1) * N + i]};
+            else a[0][m] = cplx{K[(int64_t)j0 * N + i], K[(int64_t)(j0 + 1) * N + i]};
+        }
+        p2_fft<N, 0, 1, 1>(a, lds, tw, false);
+        // unpack: X^(u) = (Z(u) + conj Z(-u)) / 2, Y^(u) = (Z(u) - conj Z(-u)) / 2i,
+        // stored at once (the M^ and K^ pieces of a chunk meet in L2)
+#pragma unroll
+        for (int m = 0; m < E; ++m) lds[pad16(t + T * m)] = a[0][m];
         __syncthreads();
 #pragma unroll
         for (int m = 0; m <= E / 2; ++m) {
             if (m == E / 2 && t != 0) continue;     // u = N / 2 belongs to thread 0
             const int u = t + T * m;
-            const cplx zu = a[v][m];
+            const cplx zu = a[0][m];
             const cplx zm = lds[pad16((N - u) & (N - 1))];
             cplx* __restrict__ o = A + ((int64_t)(j0 / 2) * (N / 2 + 1) + u) * 4 + v;
             o[0] = cplx{0.5 * (zu.x + zm.x), 0.5 * (zu.y - zm.y)};
             o[2] = cplx{0.5 * (zu.y + zm.y), 0.5 * (zm.x - zu.x)};
         }
         __syncthreads();
+        // keep the K rows' loads after the M pair's stores
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -704,14 +707,18 @@ p2_cols_kernel(const cplx* __restrict__ A, int H, cplx* __restrict__ G, const cp
 #pragma unroll
     for (int m = 0; m < E; ++m) a[0][m] = cmul(a[0][m], b[0][m]);
     p2_fft<N, 0, 1, 1>(a, lds, tw, true);
-    cplx* __restrict__ g = G + (int64_t)u1 * N;
+    // chunk (x2 / 4, u1) holds rows x2 .. x2 + 3 (four consecutive lanes)
 #pragma unroll
-    for (int m = 0; m < E; ++m) g[t + T * m] = a[0][m];
+    for (int m = 0; m < E; ++m) {
+        const int i = t + T * m;
+        G[((int64_t)(i >> 2) * H + u1) * 4 + (i & 3)] = a[0][m];
+    }
 }
 
 // Pass C. Block = rows j0 .. j0 + 3 of the output (p1 = N points along x1).
 template <int N>
 __global__ void __launch_bounds__(p2_threads<N>())
+__attribute__((amdgpu_waves_per_eu(N >= 2048 && N <= 4096 ? 4 : 1)))
 p2_rows_inv_kernel(const cplx* __restrict__ G, int p2, double scale, double* __restrict__ out,
                    const cplx* __restrict__ tw) {
     constexpr int T = p2_threads<N>(), E = N / T, H = N / 2 + 1;
@@ -724,7 +731,7 @@ p2_rows_inv_kernel(const cplx* __restrict__ G, int p2, double scale, double* __r
         const int u = t + T * m;
         const bool mirror = u >= H;
         const int src = mirror ? N - u : u;
-        const cplx* __restrict__ c = G + (int64_t)src * p2 + j0;
+        const cplx* __restrict__ c = G + ((int64_t)(j0 / 4) * H + src) * 4;
         const cplx c0 = c[0], c1 = c[1], c2 = c[2], c3 = c[3];
         // g(x2) + i g(x2 + 1), or its value at -u: conj g(x2) + i conj g(x2 + 1)
         if (!mirror) {
@@ -843,7 +850,7 @@ hipError_t p2_convolve(const int32_t* counts, const double* kernel, int p1, int 
                        double* out, void* scratch, hipStream_t s) {
     const int H = p1 / 2 + 1;
     cplx* A = static_cast<cplx*>(scratch);                 // p2 / 2 x H x {M^, K^ of two rows}
-    cplx* G = A + (size_t)H * p2 * 2;                      // H x p2
+    cplx* G = A + (size_t)H * p2 * 2;                      // p2 / 4 x H x {4 rows}
     cplx* tw1 = G + (size_t)H * p2;                        // stage twiddles along x1
     cplx* tw2 = tw1 + p1;                                  // ... along x2
     const FftPlan P1 = p2_plan_of(p1), P2 = p2_plan_of(p2);

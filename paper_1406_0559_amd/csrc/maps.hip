@@ -108,8 +108,13 @@ __global__ void __launch_bounds__(256) count_stats_kernel(const int32_t* __restr
 // magnification probability distributions (Section 3.2.1 and Section 4)
 // ----------------------------------------------------------------------------
 
-constexpr int kHistLds = 8192;   // LDS words for the per-workgroup histogram copies
+constexpr int kHistLds = 16384;  // LDS words for the per-workgroup histogram copies
 constexpr int kMaxReps = 32;     // copies of a histogram in LDS
+// Histogram workgroups: 1024 threads (16 waves, 64 loads of 16 bytes in flight
+// per SIMD) with 64 KiB of LDS copies, one or two per CU: few workgroups keep
+// the flush (one device atomic per entry per workgroup) small.
+constexpr int kHistThreads = 1024;
+constexpr int kHistBlocks = 256;
 
 // Copies of an LDS histogram of `slots` entries that fit in kHistLds words
 // (a power of two, at most kMaxReps). Lane l adds into copy l % reps, stored
@@ -125,7 +130,7 @@ int hist_reps(int64_t slots, int64_t words = kHistLds) {
 // Frequency of each count value; values >= n_values - 1 share the last entry.
 // Values below kHistLds / reps (where almost every pixel lies) go to LDS
 // copies first, the rest straight to global atomics.
-__global__ void __launch_bounds__(256) count_hist_kernel(const int32_t* __restrict__ counts,
+__global__ void __launch_bounds__(kHistThreads) count_hist_kernel(const int32_t* __restrict__ counts,
                                                          int64_t n, int64_t n_values, int reps,
                                                          unsigned long long* __restrict__ hist) {
     extern __shared__ __align__(16) unsigned int sh[];
@@ -171,7 +176,7 @@ __global__ void mpd_lut_kernel(const double* __restrict__ thr, int nthr, uint16_
 // Binned MPD. Thresholds, the value table and `reps` interleaved copies of the
 // bins (as in count_hist_kernel) live in LDS; counts outside [0, kMpdLut) are
 // searched directly.
-__global__ void __launch_bounds__(256) mpd_kernel(const int32_t* __restrict__ counts, int64_t n,
+__global__ void __launch_bounds__(kHistThreads) mpd_kernel(const int32_t* __restrict__ counts, int64_t n,
                                                   const double* __restrict__ thr, int nthr, int reps,
                                                   const uint16_t* __restrict__ lut,
                                                   unsigned long long* __restrict__ bins) {
@@ -398,7 +403,7 @@ hipError_t launch_count_hist(const int32_t* counts, int64_t n, int64_t n_values,
     if (n <= 0) return hipSuccess;
     // fewer, longer blocks: each one zeroes and flushes its LDS histogram once
     const int reps = hist_reps(n_values < kHistLds ? n_values : kHistLds);
-    hipLaunchKernelGGL(count_hist_kernel, dim3(grid_for(n, 256 * 64, 512)), dim3(256),
+    hipLaunchKernelGGL(count_hist_kernel, dim3(grid_for(n, kHistThreads * 16, kHistBlocks)), dim3(kHistThreads),
                        (size_t)kHistLds * sizeof(unsigned int), s, counts, n, n_values, reps, hist);
     return hipGetLastError();
 }
@@ -413,8 +418,8 @@ hipError_t launch_mpd(const int32_t* counts, int64_t n, const double* thr, int n
     const int reps = hist_reps(nthr + 1, spare < kHistLds ? spare : kHistLds);
     const size_t lds = (size_t)nthr * sizeof(double) + (size_t)(nthr + 1) * reps * sizeof(unsigned int) +
                        (size_t)kMpdLut * sizeof(uint16_t);
-    hipLaunchKernelGGL(mpd_kernel, dim3(grid_for(n, 256 * 64, 512)), dim3(256), lds, s, counts, n,
-                       thr, nthr, reps, lut, bins);
+    hipLaunchKernelGGL(mpd_kernel, dim3(grid_for(n, kHistThreads * 16, kHistBlocks)), dim3(kHistThreads), lds, s,
+                       counts, n, thr, nthr, reps, lut, bins);
     return hipGetLastError();
 }
 
