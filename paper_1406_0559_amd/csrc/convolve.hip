@@ -504,10 +504,10 @@ __global__ void product_kernel(cplx* __restrict__ t, int n1, int n2) {
 // half spectra (u1 in [0, H), H = p1 / 2 + 1) are all that the product needs:
 //   A. rows: one complex FFT of two rows of M (M_j + i M_j+1) and one of two
 //      rows of K, unpacked into the half spectra of the four rows and stored
-//      in 64-byte chunks per row pair and frequency,
-//      a[x2 / 2][u1] = {M^(x2, u1), K^(x2, u1), M^(x2 + 1, u1), K^(x2 + 1, u1)},
-//      consecutive u1 at consecutive chunks (a workgroup's stores are
-//      contiguous);
+//      in 128-byte chunks of eight rows per frequency (one cache line), one
+//      plane for M^ and one for K^, a[x2 / 8][u1] = {M^(x2 .. x2 + 7, u1)};
+//      a workgroup writes 32 bytes of each chunk, and the four row pairs of a
+//      chunk are consecutive workgroups on one XCD, so lines fill in its L2;
 //   B. one column u1 per workgroup: forward FFTs of both columns along x2,
 //      their product, the inverse FFT along x2, stored in 64-byte chunks of
 //      four rows, g[x2 / 4][u1] = {g(x2 .. x2 + 3, u1)};
@@ -516,10 +516,10 @@ __global__ void product_kernel(cplx* __restrict__ t, int n1, int n2) {
 //      symmetry), whose real and imaginary parts are rows x2 and x2 + 1 of
 //      C, times 1 / (p1 p2 n_avg).
 // Each pass reads and writes HBM once. The axis changes go through the chunk
-// layouts: pass B reads 32 bytes per row of pass A's chunks and writes its
-// column four lanes to a chunk (a chunk's neighbour in the same cache line
-// belongs to the next column, the next workgroup on the same XCD); passes A
-// and C store and load whole chunks at consecutive addresses. About 68 bytes
+// layouts: pass B reads pass A's chunks eight lanes to a cache line and
+// writes its column four lanes to a chunk (a chunk's neighbour in the same
+// cache line belongs to the next column, the next workgroup on the same XCD);
+// pass C loads whole chunks at consecutive addresses. About 68 bytes
 // per pixel in all, against 20 of input and output. Rows of the same
 // magnitude share a transform, so no balancing factor is needed.
 //
@@ -665,9 +665,10 @@ p2_rows_fwd_kernel(const int32_t* __restrict__ M, const double* __restrict__ K, 
             const int u = t + T * m;
             const cplx zu = a[0][m];
             const cplx zm = lds[pad16((N - u) & (N - 1))];
-            cplx* __restrict__ o = A + ((int64_t)(j0 / 2) * (N / 2 + 1) + u) * 4 + v;
+            cplx* __restrict__ o = A + (int64_t)v * p2 * (N / 2 + 1) +
+                                   ((int64_t)(j0 / 8) * (N / 2 + 1) + u) * 8 + (j0 & 7);
             o[0] = cplx{0.5 * (zu.x + zm.x), 0.5 * (zu.y - zm.y)};
-            o[2] = cplx{0.5 * (zu.y + zm.y), 0.5 * (zm.x - zu.x)};
+            o[1] = cplx{0.5 * (zu.y + zm.y), 0.5 * (zm.x - zu.x)};
         }
         __syncthreads();
         // keep the K rows' loads after the M pair's stores
@@ -686,13 +687,14 @@ p2_cols_kernel(const cplx* __restrict__ A, int H, cplx* __restrict__ G, const cp
     __shared__ cplx lds[p2_lds<N>()];
     const int t = threadIdx.x;
     const int u1 = xcd_block(blockIdx.x, gridDim.x);
-    // chunk (x2 / 2, u1), piece 2 (x2 % 2) + {0: M^, 1: K^}
-    const cplx* __restrict__ col = A + (int64_t)u1 * 4;
+    // chunk (x2 / 8, u1) of the M^ plane, then of the K^ plane, row x2 % 8
+    const cplx* __restrict__ colm = A + (int64_t)u1 * 8;
+    const cplx* __restrict__ colk = colm + (int64_t)N * H;
     cplx a[1][E], b[1][E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const int i = t + T * m;
-        a[0][m] = col[(int64_t)(i >> 1) * H * 4 + (i & 1) * 2];
+        a[0][m] = colm[(int64_t)(i >> 3) * H * 8 + (i & 7)];
     }
     p2_fft<N, 0, 1, 1>(a, lds, tw, false);
     // keep K^'s loads after M^'s transform: hoisted, they would hold registers
@@ -701,7 +703,7 @@ p2_cols_kernel(const cplx* __restrict__ A, int H, cplx* __restrict__ G, const cp
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const int i = t + T * m;
-        b[0][m] = col[(int64_t)(i >> 1) * H * 4 + (i & 1) * 2 + 1];
+        b[0][m] = colk[(int64_t)(i >> 3) * H * 8 + (i & 7)];
     }
     p2_fft<N, 0, 1, 1>(b, lds, tw, false);
 #pragma unroll
@@ -849,7 +851,7 @@ size_t p2_scratch_bytes(int p1, int p2) {
 hipError_t p2_convolve(const int32_t* counts, const double* kernel, int p1, int p2, double n_avg,
                        double* out, void* scratch, hipStream_t s) {
     const int H = p1 / 2 + 1;
-    cplx* A = static_cast<cplx*>(scratch);                 // p2 / 2 x H x {M^, K^ of two rows}
+    cplx* A = static_cast<cplx*>(scratch);                 // {M^, K^} x p2 / 8 x H x {eight rows}
     cplx* G = A + (size_t)H * p2 * 2;                      // p2 / 4 x H x {4 rows}
     cplx* tw1 = G + (size_t)H * p2;                        // stage twiddles along x1
     cplx* tw2 = tw1 + p1;                                  // ... along x2
