@@ -388,7 +388,7 @@ def test_stats_match_the_oracle(ctx):
 
 
 # ---------------------------------------------------------------------------
-# full-size workloads in the benchmark's launch configuration, sampled rows
+# grids beyond one launch (whole full-size maps: test_gpu_full_maps.py)
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("prec", ["fp32c", "fp64"])
@@ -423,47 +423,3 @@ def test_map_wider_than_one_launch(ctx, prec):
     assert want.sum() > 0 and want.max() < 2 ** 31
     assert np.array_equal(got, want)
     assert int(esc.item()) == spec.rays - int(want.sum())
-
-
-@pytest.fixture(scope="module")
-def bench_ctx():
-    """A context in bench.py's launch configuration: the tuned shapes of the
-    cached table, applied the way bench.py applies them."""
-    from paper_1406_0559_amd import autotune
-    c = rl.Context(0)
-    try:
-        c.autotune(autotune.DEFAULT_CACHE, 0)
-    except rl.RaylensError:
-        pass                      # no table for this library version: defaults, as in bench.py
-    yield c
-    c.close()
-
-
-@pytest.mark.parametrize("make", [inputs.config_gerlumph, inputs.config_mixed],
-                         ids=["gerlumph", "mixed"])
-def test_full_size_maps_sampled_against_the_oracle(bench_ctx, make):
-    ctx = bench_ctx
-    spec = make()
-    f = spec.lenses()
-    L = dev_lenses(f)
-    rows = [int(r) for r in np.linspace(0, spec.n2 - 1, 6)]
-    for r in rows:
-        # FP64 per-ray positions on sampled rows: bit-identical
-        y1, y2 = ctx.ray_positions(L, spec, "fp64", r, r + 1)
-        o1, o2, _, _ = o_positions(spec, f, r, r + 1)
-        assert same_bits(y1.cpu().numpy(), o1) and same_bits(y2.cpu().numpy(), o2)
-        # single-row maps: FP64 exact, FP32 within the per-ray bar
-        c64, e64 = ctx.shoot(L, spec, "fp64", row_begin=r, row_end=r + 1)
-        oc, oe = o_shoot(spec, f, r, r + 1)
-        assert (c64.cpu().numpy() == oc).all() and int(e64.item()) == oe
-        check_fp32_positions(ctx, spec, f, r, r + 1)
-    # whole maps: exact ray conservation, FP32 mean magnification vs FP64
-    c32, e32 = ctx.shoot(L, spec, "fp32c")
-    c64, e64 = ctx.shoot(L, spec, "fp64")
-    s32 = int(c32.sum(dtype=torch.int64).item())
-    s64 = int(c64.sum(dtype=torch.int64).item())
-    assert s32 + int(e32.item()) == spec.n1 * spec.n2
-    assert s64 + int(e64.item()) == spec.n1 * spec.n2
-    assert abs(s32 - s64) / s64 <= TOL_MEAN_MU
-    diff = (c32.to(torch.int64) - c64.to(torch.int64)).abs().sum().item()
-    assert diff / s64 < 5e-3
