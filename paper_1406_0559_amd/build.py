@@ -56,6 +56,24 @@ def _compile(src, device, verbose):
     return obj
 
 
+PROBE = os.path.join(HERE, "issue_probe")
+
+
+def build_probe(verbose=False):
+    """The FP32 issue-rate microbenchmark (csrc/issue_probe.hip), a standalone
+    program that measures the VALU ceiling the shoot kernel is compared with."""
+    tmp = PROBE + ".tmp"
+    cmd = [HIPCC, "-O3", "-std=c++17", *DEVICE[2:], f"--offload-arch={ARCH}",
+           os.path.join(CSRC, "issue_probe.hip"), "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compiling issue_probe.hip failed:\n{r.stderr}")
+    os.replace(tmp, PROBE)
+    return PROBE
+
+
 def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
@@ -66,6 +84,7 @@ def build(verbose=False):
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    build_probe(verbose)
     return LIB
 
 
