@@ -233,12 +233,13 @@ typedef struct {
 } rl_map_desc;
 
 /* Shoots every map of h_maps[0 .. n_maps-1] (host array of descriptors) in
- * one persistent launch per tuning class present (see rl_get_tuning), the
- * single-GPU form of the batches of map jobs that GERLUMPH submits to its job
- * queue (Section 3.2.5, the `job' table): workgroups pull (map, ray-cell
- * range) items from a shared counter until the list is empty, so maps of
- * uneven lens counts and sizes share the GPU, each with its class's shape.
- * Results equal per-map rl_shoot calls bit for bit. n_maps >= 0; each
+ * one launch per tuning class present (see rl_get_tuning; more if a class
+ * needs over 2^23 workgroups), the single-GPU form of the batches of map jobs
+ * that GERLUMPH submits to its job queue (Section 3.2.5, the `job' table):
+ * the launch's grid is the concatenation of the maps' workgroups, heaviest
+ * lens fields first, so maps of uneven lens counts and sizes share the GPU,
+ * each with its class's shape, and the end of the launch is made of its
+ * cheapest workgroups. Results equal per-map rl_shoot calls bit for bit. n_maps >= 0; each
  * descriptor is validated as rl_shoot validates its arguments (the message
  * names the map). Asynchronous; the descriptors are copied before return. */
 rl_status rl_shoot_batch(rl_context* ctx, const rl_map_desc* h_maps, int32_t n_maps,
@@ -254,18 +255,13 @@ rl_status rl_shoot_batch(rl_context* ctx, const rl_map_desc* h_maps, int32_t n_m
  *                    LDS-privatised sub-map over the bounding box of the
  *                    workgroup's binned rays; 2 = an LDS-privatised 64 x 64 sub-map
  *                    around their mean pixel. In modes 1 and 2 each touched pixel
- *                    gets one global atomic; rays outside the sub-map go global.
- *   item_cells     : work-item size in rl_shoot_batch (>= 1): a map with N
- *                    lenses is cut into items of about item_cells * 2048 /
- *                    (N + 8) ray cells (whole workgroup passes, at most
- *                    4096), so items carry similar work */
+ *                    gets one global atomic; rays outside the sub-map go global. */
 typedef struct {
     int32_t rays_x;
     int32_t rays_y;
     int32_t lens_tile;
     int32_t waves;
     int32_t submap;
-    int32_t item_cells;
 } rl_tuning;
 
 /* Reads / sets the kernel shape used for `precision` and tuning class

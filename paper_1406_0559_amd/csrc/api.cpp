@@ -355,12 +355,10 @@ rl_status rl_create(int32_t hip_device, rl_context** out) {
     rl_context* c = new (std::nothrow) rl_context();
     if (!c) return fail(RL_E_NOMEM, "context allocation failed");
     c->device = hip_device;
-    // defaults measured on gfx950 (the autotuner refines them): unit masses
-    // 8 x 2 rays per lane, mass-weighted lenses 4 x 4; FP64 4 x 4
+    // defaults measured on gfx950 (the autotuner refines them): 4 x 4 rays
+    // per lane, 256-lens tiles, 4 waves, bounding-box sub-map
     for (int p = 0; p < 2; ++p)
-        for (int k = 0; k < rl::kTuningClasses; ++k)
-            c->tuning[p][k] = (p == RL_FP32_COMP && k < 3) ? rl::KernelShape{8, 2, 256, 4, 1, 64}
-                                                           : rl::KernelShape{4, 4, 256, 4, 1, 64};
+        for (int k = 0; k < rl::kTuningClasses; ++k) c->tuning[p][k] = rl::KernelShape{4, 4, 256, 4, 1};
     *out = c;
     return RL_OK;
 }
@@ -403,7 +401,7 @@ rl_status rl_get_tuning(rl_context* ctx, int32_t precision, int32_t n_cls, rl_tu
         return fail(RL_E_INVALID, "tuning class must be in [0, %d)", rl::kTuningClasses);
     if (!h_out) return fail(RL_E_INVALID, "h_out is NULL");
     const rl::KernelShape& k = ctx->tuning[precision][n_cls];
-    *h_out = rl_tuning{k.rays_x, k.rays_y, k.lens_tile, k.waves, k.submap, k.item_cells};
+    *h_out = rl_tuning{k.rays_x, k.rays_y, k.lens_tile, k.waves, k.submap};
     return RL_OK;
 }
 
@@ -414,10 +412,10 @@ rl_status rl_set_tuning(rl_context* ctx, int32_t precision, int32_t n_cls, const
     if (n_cls < 0 || n_cls >= rl::kTuningClasses)
         return fail(RL_E_INVALID, "tuning class must be in [0, %d)", rl::kTuningClasses);
     if (!t) return fail(RL_E_INVALID, "tuning is NULL");
-    rl::KernelShape k{t->rays_x, t->rays_y, t->lens_tile, t->waves, t->submap, t->item_cells};
+    rl::KernelShape k{t->rays_x, t->rays_y, t->lens_tile, t->waves, t->submap};
     if (!rl::shape_supported((rl::Precision)precision, k))
-        return fail(RL_E_INVALID, "unsupported kernel shape (%d x %d rays, tile %d, %d waves, submap %d, item %d)",
-                    k.rays_x, k.rays_y, k.lens_tile, k.waves, k.submap, k.item_cells);
+        return fail(RL_E_INVALID, "unsupported kernel shape (%d x %d rays, tile %d, %d waves, submap %d)",
+                    k.rays_x, k.rays_y, k.lens_tile, k.waves, k.submap);
     ctx->tuning[precision][n_cls] = k;
     return RL_OK;
 }
@@ -642,54 +640,64 @@ rl_status rl_shoot_batch(rl_context* ctx, const rl_map_desc* h_maps, int32_t n_m
     }
     if (n_maps == 0) return RL_OK;
 
-    // one persistent launch per tuning class present, each with its class's
-    // kernel shape (kernel shapes change no result bit, so every map still
-    // equals the map shot alone)
+    // per tuning class present: every map (or range of its cell rows) is a
+    // segment of that class's launches, with the class's kernel shape (kernel
+    // shapes change no result bit, so every map still equals the map shot
+    // alone); segments in descending cost per workgroup, so the last
+    // workgroups of a launch are the cheapest
     int64_t total_lens = 0;
     std::vector<int> cls((size_t)n_maps);
     for (int32_t i = 0; i < n_maps; ++i) {
         cls[i] = rl::tuning_class(h_maps[i].lenses.n, h_maps[i].lenses.m != nullptr);
         total_lens += h_maps[i].lenses.n;
     }
-
     std::vector<rl::MapParams> params((size_t)n_maps);
-    std::vector<rl::WorkItem> sorted;
-    int64_t seg_begin[rl::kTuningClasses + 1] = {0};
+    for (int32_t i = 0; i < n_maps; ++i) {
+        const rl_map_desc& d = h_maps[i];
+        build_params(&d.macro, &d.grid, &d.win, d.row_begin, d.row_end, &params[i]);
+        params[i].counts = d.d_counts;
+        params[i].escaped = reinterpret_cast<unsigned long long*>(d.d_escaped);
+        params[i].n_lens = d.lenses.n;
+    }
+    struct Launch {
+        int cls;
+        size_t seg0, nseg;
+        int64_t blocks;
+    };
+    std::vector<int32_t> seg_map;     // map of each segment
+    std::vector<int64_t> seg_row0, seg_cells, seg_first;
+    std::vector<Launch> launches;
     for (int c = 0; c < rl::kTuningClasses; ++c) {
-        seg_begin[c] = (int64_t)sorted.size();
-        const rl::KernelShape& ks = ctx->tuning[precision][c];
-        std::vector<rl::WorkItem> items;
-        for (int32_t i = 0; i < n_maps; ++i) {
-            if (cls[i] != c) continue;
-            const rl_map_desc& d = h_maps[i];
-            build_params(&d.macro, &d.grid, &d.win, d.row_begin, d.row_end, &params[i]);
-            params[i].counts = d.d_counts;
-            params[i].escaped = reinterpret_cast<unsigned long long*>(d.d_escaped);
-            params[i].n_lens = d.lenses.n;
-            // cells per item: item_cells cells' worth of work at 2048 lenses, so
-            // items carry about the same work whatever the lens count (short
-            // items for large fields keep the tail of the launch short, long
-            // items for small fields amortise the fetch of the next item), in
-            // whole workgroup passes
-            const int64_t pass = (int64_t)ks.waves * ((ks.rays_x * ks.rays_y) / rl::kRaysPerLane);
-            int64_t per = (int64_t)std::llround((double)ks.item_cells * 2048.0 / (double)(d.lenses.n + 8));
-            per = std::min<int64_t>(std::max<int64_t>(per, pass), 4096);
-            per = (per + pass - 1) / pass * pass;
-            for (int64_t cc = 0; cc < params[i].n_cells; cc += per) {
-                const int64_t nc = std::min<int64_t>(per, params[i].n_cells - cc);
-                items.push_back(rl::WorkItem{i, 0, cc, nc});
+        std::vector<int32_t> order;
+        for (int32_t i = 0; i < n_maps; ++i)
+            if (cls[i] == c && params[i].n_cells > 0) order.push_back(i);
+        if (order.empty()) continue;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t a, int32_t b) { return h_maps[a].lenses.n > h_maps[b].lenses.n; });
+        const int64_t per = rl::batch_cells_per_block(ctx->tuning[precision][c]);
+        Launch cur{c, seg_map.size(), 0, 0};
+        for (int32_t i : order) {
+            const rl::MapParams& P = params[i];
+            const int64_t rows = P.n_cells / P.cells_x;
+            const int64_t rows_per_seg = std::max<int64_t>(1, rl::kMaxLaunchBlocks * per / P.cells_x);
+            for (int64_t r0 = 0; r0 < rows; r0 += rows_per_seg) {
+                const int64_t nr = std::min(rows_per_seg, rows - r0);
+                const int64_t span = ((nr * P.cells_x + per - 1) / per + 7) / 8 * 8;
+                if (cur.blocks + span > rl::kMaxLaunchBlocks) {
+                    launches.push_back(cur);
+                    cur = Launch{c, seg_map.size(), 0, 0};
+                }
+                seg_map.push_back(i);
+                seg_row0.push_back(P.cell_row0 + r0);
+                seg_cells.push_back(nr * P.cells_x);
+                seg_first.push_back(cur.blocks);
+                cur.blocks += span;
+                cur.nseg += 1;
             }
         }
-        // most expensive items first so the tail of the launch is made of cheap ones
-        std::stable_sort(items.begin(), items.end(), [&](const rl::WorkItem& a, const rl::WorkItem& b) {
-            const double ca = (double)(params[a.map].n_lens + 8) * a.ncells;
-            const double cb = (double)(params[b.map].n_lens + 8) * b.ncells;
-            return ca > cb;
-        });
-        sorted.insert(sorted.end(), items.begin(), items.end());
+        launches.push_back(cur);
     }
-    seg_begin[rl::kTuningClasses] = (int64_t)sorted.size();
-    if (sorted.empty()) return RL_OK;
+    if (launches.empty()) return RL_OK;
 
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return hip_fail(dg.err, "hipSetDevice");
@@ -722,32 +730,35 @@ rl_status rl_shoot_batch(rl_context* ctx, const rl_map_desc* h_maps, int32_t n_m
         }
     }
 
-    // records: [MapParams x n][WorkItem x n_items][one counter per class]
-    const size_t pbytes = sizeof(rl::MapParams) * (size_t)n_maps;
-    const size_t ioff = (pbytes + 255) & ~(size_t)255;
-    const size_t ibytes = sizeof(rl::WorkItem) * sorted.size();
-    const size_t coff = (ioff + ibytes + 255) & ~(size_t)255;
-    const size_t total = coff + 256;
+    // records: [MapParams x n_segs][first block x n_segs], segments of one
+    // launch contiguous
+    const size_t nseg = seg_map.size();
+    std::vector<rl::MapParams> segs(nseg);
+    for (size_t k = 0; k < nseg; ++k) {
+        segs[k] = params[(size_t)seg_map[k]];
+        segs[k].cell_row0 = seg_row0[k];
+        segs[k].n_cells = seg_cells[k];
+    }
+    const size_t pbytes = sizeof(rl::MapParams) * nseg;
+    const size_t foff = (pbytes + 255) & ~(size_t)255;
+    const size_t total = foff + sizeof(int64_t) * nseg;
     char* hs = nullptr;
     RL_TRY(stage_reserve(ctx, total, &hs));
-    std::memset(hs, 0, total);
-    std::memcpy(hs, params.data(), pbytes);
-    std::memcpy(hs + ioff, sorted.data(), ibytes);
+    std::memcpy(hs, segs.data(), pbytes);
+    std::memcpy(hs + foff, seg_first.data(), sizeof(int64_t) * nseg);
     e = ctx->batch.acquire(total, stream);
     if (e != hipSuccess) return hip_fail(e, "batch scratch");
     char* ds = static_cast<char*>(ctx->batch.ptr);
     RL_TRY(stage_send(ctx, ds, total, stream));
 
-    const rl::MapParams* dmaps = reinterpret_cast<const rl::MapParams*>(ds);
-    const rl::WorkItem* ditems = reinterpret_cast<const rl::WorkItem*>(ds + ioff);
-    unsigned int* dcount = reinterpret_cast<unsigned int*>(ds + coff);
+    const rl::MapParams* dsegs = reinterpret_cast<const rl::MapParams*>(ds);
+    const int64_t* dfirst = reinterpret_cast<const int64_t*>(ds + foff);
     e = hipSuccess;
-    for (int c = 0; c < rl::kTuningClasses && e == hipSuccess; ++c) {
-        const int64_t n_items = seg_begin[c + 1] - seg_begin[c];
-        if (n_items == 0) continue;
-        e = rl::launch_shoot_batch(dmaps, ditems + seg_begin[c], n_items, dcount + c,
-                                   (rl::Precision)precision, c >= 3, ctx->tuning[precision][c],
-                                   ctx->num_cus, stream);
+    for (size_t l = 0; l < launches.size() && e == hipSuccess; ++l) {
+        const Launch& L = launches[l];
+        e = rl::launch_shoot_batch(dsegs + L.seg0, dfirst + L.seg0, (int)L.nseg, L.blocks,
+                                   (rl::Precision)precision, L.cls >= 3, ctx->tuning[precision][L.cls],
+                                   stream);
     }
     hipError_t e2 = ctx->batch.release(stream);
     hipError_t e3 = precision == RL_FP32_COMP ? ctx->lens.release(stream) : hipSuccess;

@@ -77,19 +77,17 @@ struct MapParams {
     double* out_y2;
 };
 
-struct WorkItem {
-    int32_t map;
-    int32_t pad;
-    int64_t cell0;
-    int64_t ncells;
-};
+// Workgroups per launch of the shoot kernels: at most 2^23 (2^31 work-items
+// with 4 waves, inside the 32-bit size of one dispatch). The host refuses
+// grids wider than 2^26 rays, so one cell row (at most 2^23 cells of >= 8
+// rays across) always fits one launch.
+constexpr int64_t kMaxLaunchBlocks = (int64_t)1 << 23;
 
 struct KernelShape {
     int32_t rays_x, rays_y;    // rays per lane along x1 / x2 (product 16; 32 = two cells per wave)
     int32_t lens_tile;         // lenses per LDS pass (multiple of kBlock)
     int32_t waves;             // waves per workgroup
     int32_t submap;            // 0 global atomics, 1 bounding-box LDS sub-map, 2 64x64 LDS window
-    int32_t item_cells;        // batch work-item size: cells at 2048 lenses
 };
 
 // Launchers of shoot.hip. Each returns the hipError_t of the launch. The
@@ -99,9 +97,14 @@ hipError_t launch_prep_lenses(const double* x1, const double* x2, const double* 
                               hipStream_t stream);
 hipError_t launch_shoot(const MapParams& P, Precision prec, const KernelShape& ks, bool out_y,
                         int num_cus, hipStream_t stream);
-hipError_t launch_shoot_batch(const MapParams* d_maps, const WorkItem* d_items, int64_t n_items,
-                              unsigned int* d_counter, Precision prec, bool masses,
-                              const KernelShape& ks, int num_cus, hipStream_t stream);
+// Batched launch over n_segs segments (device arrays): segment i is a map, or
+// a range of whole cell rows of one, with its workgroups at blocks
+// [first[i], first[i] + span_i) of the grid, span_i = the segment's blocks
+// (batch_cells_per_block cells each) rounded up to a multiple of 8, first[0]
+// = 0, and `blocks` = the sum of the spans, at most kMaxLaunchBlocks.
+int64_t batch_cells_per_block(const KernelShape& ks);
+hipError_t launch_shoot_batch(const MapParams* d_segs, const int64_t* d_first, int n_segs, int64_t blocks,
+                              Precision prec, bool masses, const KernelShape& ks, hipStream_t stream);
 hipError_t launch_bin_positions(const double* y1, const double* y2, int64_t n, int32_t p1,
                                 int32_t p2, double lo1, double lo2, double inv1, double inv2,
                                 int32_t* counts, unsigned long long* escaped, hipStream_t stream);

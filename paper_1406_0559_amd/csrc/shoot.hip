@@ -73,10 +73,12 @@ __device__ __forceinline__ int wave_max(int v) {
 }
 
 // Workgroup header in LDS: [0..2] sums of ix, iy and the binned count,
-// [3] the batch work item, [4..7] bounding box (min x, min y, max x, max y).
+// [3] the batch work item, [4..7] bounding box (min x, min y, max x, max y),
+// [8] escaped rays.
 __device__ __forceinline__ void reset_header(int* hdr) {
     hdr[0] = 0; hdr[1] = 0; hdr[2] = 0;
     hdr[4] = INT_MAX; hdr[5] = INT_MAX; hdr[6] = -1; hdr[7] = -1;
+    hdr[8] = 0;
 }
 
 // Bijective remap of a linear block id so that blocks dispatched to the same
@@ -185,6 +187,10 @@ __device__ __forceinline__ void lens_step_f32_single(const float* __restrict__ w
     }
 }
 
+// Lens loads each lane keeps in flight while staging a tile (two: deeper
+// staging raised the register count of the 16-ray shapes and ran slower).
+constexpr int kStageDepth = 2;
+
 // FP32-compensated deflection of the cell's rays; alpha returned in FP64 as
 // sum + compensation. With CPW cells per wave, each cell is handled by
 // kLanes / CPW lanes (cl = lane within the cell) and has its own rebased copy
@@ -217,19 +223,37 @@ __device__ __forceinline__ void deflect_f32(const MapParams& P, int64_t i0, int6
     const int64_t n = P.n_lens;
     for (int64_t t0 = 0; t0 < n; t0 += L) {
         const int cnt = (int)((n - t0) < (int64_t)L ? (n - t0) : (int64_t)L);
-        for (int q = cl; q < cnt; q += LPC) {
-            const float4 h = P.lens32[t0 + q];
-            const float r1 = rebase(h.x, h.y, C1h, C1l);
-            const float r2 = rebase(h.z, h.w, C2h, C2l);
-            if constexpr (MASS) {
-                // a massless lens (inverse 0) is staged 2^62 away in both
-                // coordinates: r'^2 products overflow, the shared reciprocal
-                // is 0 and its terms are exactly zero
-                const float im = P.imass32[t0 + q];
-                reinterpret_cast<float4*>(wh)[q] = im != 0.0f ? make_float4(r1 * im, r2 * im, im, 0.0f)
-                                                              : make_float4(-0x1p62f, -0x1p62f, 0.0f, 0.0f);
-            } else {
-                reinterpret_cast<float2*>(wh)[q] = make_float2(r1, r2);
+        // kStageDepth lens loads in flight per lane before the first is
+        // used: one load at a time left every wave of the workgroup waiting
+        // a full L2 round trip per LPC lenses of the tile
+        for (int q0 = cl; q0 < cnt; q0 += LPC * kStageDepth) {
+            float4 h[kStageDepth];
+            float im[kStageDepth];
+#pragma unroll
+            for (int u = 0; u < kStageDepth; ++u) {
+                const int q = q0 + u * LPC;
+                if (q < cnt) {
+                    h[u] = P.lens32[t0 + q];
+                    if constexpr (MASS) im[u] = P.imass32[t0 + q];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kStageDepth; ++u) {
+                const int q = q0 + u * LPC;
+                if (q < cnt) {
+                    const float r1 = rebase(h[u].x, h[u].y, C1h, C1l);
+                    const float r2 = rebase(h[u].z, h[u].w, C2h, C2l);
+                    if constexpr (MASS) {
+                        // a massless lens (inverse 0) is staged 2^62 away in
+                        // both coordinates: r'^2 products overflow, the shared
+                        // reciprocal is 0 and its terms are exactly zero
+                        reinterpret_cast<float4*>(wh)[q] =
+                            im[u] != 0.0f ? make_float4(r1 * im[u], r2 * im[u], im[u], 0.0f)
+                                          : make_float4(-0x1p62f, -0x1p62f, 0.0f, 0.0f);
+                    } else {
+                        reinterpret_cast<float2*>(wh)[q] = make_float2(r1, r2);
+                    }
+                }
             }
         }
         __syncthreads();
@@ -411,8 +435,14 @@ __device__ __forceinline__ void process_cell(const MapParams& P, int64_t cell, b
     }
     if constexpr (OUT_Y) return;
 
+    // Escaped rays: one device atomic per wave on a single address
+    // serialised short launches, so the sub-map modes sum them per workgroup
+    // in the header first and add them once, after the flush.
     esc = wave_sum(esc);
-    if (lane == 0 && esc) atomicAdd(P.escaped, (unsigned long long)esc);
+    if (lane == 0 && esc) {
+        if constexpr (SUBMAP) atomicAdd(&hdr[8], esc);
+        else atomicAdd(P.escaped, (unsigned long long)esc);
+    }
 
     if constexpr (!SUBMAP) {
 #pragma unroll
@@ -482,7 +512,11 @@ __device__ __forceinline__ void process_cell(const MapParams& P, int64_t cell, b
             }
         }
         __syncthreads();
-        if (threadIdx.x == 0) reset_header(hdr);
+        if (threadIdx.x == 0) {
+            const int e = hdr[8];
+            if (e) atomicAdd(P.escaped, (unsigned long long)e);
+            reset_header(hdr);
+        }
         __syncthreads();
     }
 }
@@ -490,17 +524,12 @@ __device__ __forceinline__ void process_cell(const MapParams& P, int64_t cell, b
 constexpr int kHdrBytes = 64;
 
 // Occupancy floor in waves per SIMD: 2 holds the 32-ray shapes to 256
-// registers; the 16-ray FP32 shapes with masses are held at 3, where they fit
-// without spilling (the unit-mass ones reach 3 by themselves; measured on
-// gfx950, 4 with a few spilled registers ran ~1 % slower).
+// registers; the 16-ray FP32 shapes are held at 3, where they fit without
+// spilling (left to itself the compiler gives the unit-mass ones 2 once the
+// tile staging keeps two loads in flight; measured on gfx950, 4 with a few
+// spilled registers ran ~1 % slower with masses).
 template <bool MASS, int CPW, int PREC>
-constexpr int min_waves() { return (MASS && CPW == 1 && PREC == kFP32Comp) ? 3 : 2; }
-// The persistent batch kernel holds its work-item state as well; left to
-// itself the compiler gives the 16-ray FP32 shapes 2 waves per SIMD there, so
-// they are held at 3 like the single-map kernel.
-template <bool MASS, int CPW, int PREC>
-constexpr int min_waves_batch() { return (CPW == 1 && PREC == kFP32Comp) ? 3 : 2; }
-
+constexpr int min_waves() { return (CPW == 1 && PREC == kFP32Comp) ? 3 : 2; }
 template <int KX, int KY, bool MASS, int SUBMAP, bool OUT_Y, int PREC, int CPW>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(min_waves<MASS, CPW, PREC>())))
 shoot_kernel(MapParams P, int L) {
@@ -519,39 +548,45 @@ shoot_kernel(MapParams P, int L) {
                                                          lens_base, sub, hdr);
 }
 
-// Persistent batch kernel: workgroups pull (map, cell range) items from a
-// global counter until the list is exhausted; every workgroup reaches the
-// exit because the counter only grows.
+// Batched launch: the grid is the concatenation of the workgroups of several
+// maps (or row segments of maps), segment i owning blocks
+// [first[i], first[i] + span_i) with first[i] a multiple of 8, so that block
+// b runs on XCD b % 8 exactly as in a single-map launch and the same
+// XCD-aware remap applies within the segment. A workgroup finds its segment
+// with one wave-wide comparison per 64 segments, then runs the single-map
+// body: nothing is carried across cells, so the lens loop compiles as in
+// shoot_kernel. Blocks of the padding to the next multiple of 8 exit at once.
 template <int KX, int KY, bool MASS, int SUBMAP, int PREC, int CPW>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(min_waves_batch<MASS, CPW, PREC>())))
-shoot_batch_kernel(const MapParams* __restrict__ maps,
-                                                          const WorkItem* __restrict__ items,
-                                                          int64_t n_items, unsigned int* counter,
-                                                          int L) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(min_waves<MASS, CPW, PREC>())))
+shoot_batch_kernel(const MapParams* __restrict__ segs, const int64_t* __restrict__ first, int n_segs,
+                   int L) {
     extern __shared__ __align__(16) char smem[];
     int* hdr = reinterpret_cast<int*>(smem);
     char* lens_base = smem + kHdrBytes;
     int* sub = reinterpret_cast<int*>(smem + kHdrBytes);
-    if (threadIdx.x == 0) { reset_header(hdr); hdr[3] = 0; }
+    if (threadIdx.x == 0) reset_header(hdr);
     __syncthreads();
     const int wave = threadIdx.x / kLanes, lane = threadIdx.x % kLanes;
     const int W = blockDim.x / kLanes;
-    for (;;) {
-        if (threadIdx.x == 0) hdr[3] = (int)atomicAdd(counter, 1u);
-        __syncthreads();
-        const int64_t it = (int64_t)(unsigned)__builtin_amdgcn_readfirstlane(hdr[3]);
-        __syncthreads();
-        if (it >= n_items) break;
-        const WorkItem w = items[it];
-        const MapParams& P = maps[w.map];
-        const int64_t end = w.cell0 + w.ncells;
-        for (int64_t c0 = w.cell0; c0 < end; c0 += (int64_t)W * CPW) {
-            const int64_t cell = c0 + wave * CPW + lane / (kLanes / CPW);
-            const bool valid = cell < end;
-            process_cell<KX, KY, MASS, SUBMAP, false, PREC, CPW>(P, valid ? cell : w.cell0, valid, wave,
-                                                                 lane, L, lens_base, sub, hdr);
-        }
+    const int64_t b = blockIdx.x;
+    // segment: the number of segments starting at or before b, minus one
+    // (first[] ascends and first[0] = 0)
+    int m = -1;
+    for (int k0 = 0; k0 < n_segs; k0 += kLanes) {
+        const int k = k0 + lane;
+        const unsigned long long bal = __ballot(k < n_segs && first[k] <= b);
+        m += __popcll(bal);
+        if (!((bal >> (kLanes - 1)) & 1ull)) break;
     }
+    const MapParams& P = segs[m];
+    const int64_t per = (int64_t)W * CPW;
+    const int64_t nb = (P.n_cells + per - 1) / per;
+    const int64_t r = xcd_remap(b - first[m], (nb + 7) / 8 * 8);
+    if (r >= nb) return;
+    const int64_t cell = (r * W + wave) * CPW + lane / (kLanes / CPW);
+    const bool valid = cell < P.n_cells;
+    process_cell<KX, KY, MASS, SUBMAP, false, PREC, CPW>(P, valid ? cell : 0, valid, wave, lane, L,
+                                                         lens_base, sub, hdr);
 }
 
 // ----------------------------------------------------------------------------
@@ -616,13 +651,10 @@ int grid_for(int64_t n, int threads, int cap) {
 template <int KX, int KY>
 constexpr int cells_per_wave() { return KX * KY / kRaysPerLane; }
 
-// Workgroups per launch of the single-map kernel: at most 2^23 (2^31
-// work-items with 4 waves, inside the 32-bit size of one dispatch). A longer
-// row range goes out as several launches over whole cell rows; a cell's rays
-// and lenses do not depend on the launch it is in, so no result changes. The
-// host refuses grids wider than 2^26 rays, so one cell row (at most 2^23
-// cells of >= 8 rays across) always fits one launch.
-constexpr int64_t kMaxBlocks = (int64_t)1 << 23;
+// Workgroups per launch: at most kMaxLaunchBlocks. A longer row range goes
+// out as several launches over whole cell rows; a cell's rays and lenses do
+// not depend on the launch it is in, so no result changes.
+constexpr int64_t kMaxBlocks = kMaxLaunchBlocks;
 
 template <int KX, int KY, bool MASS, int SUBMAP, bool OUT_Y, int PREC>
 hipError_t launch_one(const MapParams& P, const KernelShape& ks, size_t lds, hipStream_t s) {
@@ -646,17 +678,13 @@ hipError_t launch_one(const MapParams& P, const KernelShape& ks, size_t lds, hip
 }
 
 template <int KX, int KY, bool MASS, int SUBMAP, int PREC>
-hipError_t launch_batch_one(const MapParams* maps, const WorkItem* items, int64_t n_items,
-                            unsigned int* counter, const KernelShape& ks, size_t lds,
-                            int num_cus, hipStream_t s) {
-    const int W = ks.waves;
-    // enough resident workgroups to fill every CU several times over
-    int64_t blocks = (int64_t)num_cus * (16 / W);
-    if (blocks > n_items) blocks = n_items;
-    if (blocks <= 0) return hipSuccess;
+hipError_t launch_batch_one(const MapParams* segs, const int64_t* first, int n_segs, int64_t blocks,
+                            const KernelShape& ks, size_t lds, hipStream_t s) {
+    if (blocks <= 0 || n_segs <= 0) return hipSuccess;
+    if (blocks > kMaxBlocks) return hipErrorInvalidValue;
     hipLaunchKernelGGL((shoot_batch_kernel<KX, KY, MASS, SUBMAP, PREC, cells_per_wave<KX, KY>()>),
-                       dim3((unsigned)blocks),
-                       dim3(W * kLanes), lds, s, maps, items, n_items, counter, ks.lens_tile);
+                       dim3((unsigned)blocks), dim3(ks.waves * kLanes), lds, s, segs, first, n_segs,
+                       ks.lens_tile);
     return hipGetLastError();
 }
 
@@ -681,22 +709,20 @@ hipError_t dispatch_shape(const MapParams& P, const KernelShape& ks, bool masses
 }
 
 template <int KX, int KY, bool MASS, int PREC>
-hipError_t dispatch_batch_submap(const MapParams* maps, const WorkItem* items, int64_t n_items,
-                                 unsigned int* counter, const KernelShape& ks, size_t lds,
-                                 int num_cus, hipStream_t s) {
+hipError_t dispatch_batch_submap(const MapParams* segs, const int64_t* first, int n_segs, int64_t blocks,
+                                 const KernelShape& ks, size_t lds, hipStream_t s) {
     switch (ks.submap) {
-        case 1: return launch_batch_one<KX, KY, MASS, 1, PREC>(maps, items, n_items, counter, ks, lds, num_cus, s);
-        case 2: return launch_batch_one<KX, KY, MASS, 2, PREC>(maps, items, n_items, counter, ks, lds, num_cus, s);
-        default: return launch_batch_one<KX, KY, MASS, 0, PREC>(maps, items, n_items, counter, ks, lds, num_cus, s);
+        case 1: return launch_batch_one<KX, KY, MASS, 1, PREC>(segs, first, n_segs, blocks, ks, lds, s);
+        case 2: return launch_batch_one<KX, KY, MASS, 2, PREC>(segs, first, n_segs, blocks, ks, lds, s);
+        default: return launch_batch_one<KX, KY, MASS, 0, PREC>(segs, first, n_segs, blocks, ks, lds, s);
     }
 }
 
 template <int KX, int KY, int PREC>
-hipError_t dispatch_batch_shape(const MapParams* maps, const WorkItem* items, int64_t n_items,
-                                unsigned int* counter, bool masses, const KernelShape& ks,
-                                size_t lds, int num_cus, hipStream_t s) {
-    return masses ? dispatch_batch_submap<KX, KY, true, PREC>(maps, items, n_items, counter, ks, lds, num_cus, s)
-                  : dispatch_batch_submap<KX, KY, false, PREC>(maps, items, n_items, counter, ks, lds, num_cus, s);
+hipError_t dispatch_batch_shape(const MapParams* segs, const int64_t* first, int n_segs, int64_t blocks,
+                                bool masses, const KernelShape& ks, size_t lds, hipStream_t s) {
+    return masses ? dispatch_batch_submap<KX, KY, true, PREC>(segs, first, n_segs, blocks, ks, lds, s)
+                  : dispatch_batch_submap<KX, KY, false, PREC>(segs, first, n_segs, blocks, ks, lds, s);
 }
 
 }  // namespace
@@ -712,7 +738,6 @@ bool shape_supported(Precision prec, const KernelShape& ks) {
     if (ks.lens_tile < kBlock || ks.lens_tile > 2048 || ks.lens_tile % kBlock) return false;
     if (!(ks.waves == 1 || ks.waves == 2 || ks.waves == 4)) return false;
     if (ks.submap < 0 || ks.submap > 2) return false;
-    if (ks.item_cells < 1) return false;
     return true;
 }
 
@@ -757,22 +782,25 @@ hipError_t launch_shoot(const MapParams& P, Precision prec, const KernelShape& k
     return dispatch_shape<8, 2, kFP32Comp>(P, k, masses, out_y, lds, s);
 }
 
-hipError_t launch_shoot_batch(const MapParams* d_maps, const WorkItem* d_items, int64_t n_items,
-                              unsigned int* d_counter, Precision prec, bool masses,
-                              const KernelShape& ks_in, int num_cus, hipStream_t s) {
+int64_t batch_cells_per_block(const KernelShape& ks) {
+    return (int64_t)ks.waves * (ks.rays_x * ks.rays_y / kRaysPerLane);
+}
+
+hipError_t launch_shoot_batch(const MapParams* d_segs, const int64_t* d_first, int n_segs, int64_t blocks,
+                              Precision prec, bool masses, const KernelShape& ks_in, hipStream_t s) {
     const KernelShape ks = fit_lds(prec, masses, ks_in);
     const size_t lds = shoot_lds_bytes(prec, masses, ks);
     if (prec == kFP64Plain)
-        return dispatch_batch_shape<4, 4, kFP64Plain>(d_maps, d_items, n_items, d_counter, masses, ks, lds, num_cus, s);
+        return dispatch_batch_shape<4, 4, kFP64Plain>(d_segs, d_first, n_segs, blocks, masses, ks, lds, s);
     if (ks.rays_x == 4 && ks.rays_y == 4)
-        return dispatch_batch_shape<4, 4, kFP32Comp>(d_maps, d_items, n_items, d_counter, masses, ks, lds, num_cus, s);
+        return dispatch_batch_shape<4, 4, kFP32Comp>(d_segs, d_first, n_segs, blocks, masses, ks, lds, s);
     if (ks.rays_x == 2)
-        return dispatch_batch_shape<2, 8, kFP32Comp>(d_maps, d_items, n_items, d_counter, masses, ks, lds, num_cus, s);
+        return dispatch_batch_shape<2, 8, kFP32Comp>(d_segs, d_first, n_segs, blocks, masses, ks, lds, s);
     if (ks.rays_x == 4)
-        return dispatch_batch_shape<4, 8, kFP32Comp>(d_maps, d_items, n_items, d_counter, masses, ks, lds, num_cus, s);
+        return dispatch_batch_shape<4, 8, kFP32Comp>(d_segs, d_first, n_segs, blocks, masses, ks, lds, s);
     if (ks.rays_y == 4)
-        return dispatch_batch_shape<8, 4, kFP32Comp>(d_maps, d_items, n_items, d_counter, masses, ks, lds, num_cus, s);
-    return dispatch_batch_shape<8, 2, kFP32Comp>(d_maps, d_items, n_items, d_counter, masses, ks, lds, num_cus, s);
+        return dispatch_batch_shape<8, 4, kFP32Comp>(d_segs, d_first, n_segs, blocks, masses, ks, lds, s);
+    return dispatch_batch_shape<8, 2, kFP32Comp>(d_segs, d_first, n_segs, blocks, masses, ks, lds, s);
 }
 
 hipError_t launch_prep_lenses(const double* x1, const double* x2, const double* m, int64_t n,

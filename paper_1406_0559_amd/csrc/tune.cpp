@@ -178,9 +178,9 @@ const char* prec_name(int p) { return p == RL_FP32_COMP ? "fp32c" : "fp64"; }
 constexpr int kClassLenses[3] = {400, 2624, 16000};
 
 std::vector<rl_tuning> ray_shapes(int prec) {
-    if (prec == RL_FP64_PLAIN) return {rl_tuning{4, 4, 256, 4, 1, 16}};
-    return {rl_tuning{4, 4, 256, 4, 1, 16}, rl_tuning{2, 8, 256, 4, 1, 16}, rl_tuning{8, 2, 256, 4, 1, 16},
-            rl_tuning{4, 8, 256, 4, 1, 16}, rl_tuning{8, 4, 256, 4, 1, 16}};
+    if (prec == RL_FP64_PLAIN) return {rl_tuning{4, 4, 256, 4, 1}};
+    return {rl_tuning{4, 4, 256, 4, 1}, rl_tuning{2, 8, 256, 4, 1}, rl_tuning{8, 2, 256, 4, 1},
+            rl_tuning{4, 8, 256, 4, 1}, rl_tuning{8, 4, 256, 4, 1}};
 }
 
 // ---------------------------------------------------------------------------
@@ -268,9 +268,9 @@ struct Result {
 std::string shape_json(const rl_tuning& t) {
     char buf[200];
     std::snprintf(buf, sizeof buf,
-                  "{\"item_cells\": %d, \"lens_tile\": %d, \"rays_x\": %d, \"rays_y\": %d, "
+                  "{\"lens_tile\": %d, \"rays_x\": %d, \"rays_y\": %d, "
                   "\"submap\": %d, \"waves\": %d}",
-                  t.item_cells, t.lens_tile, t.rays_x, t.rays_y, t.submap, t.waves);
+                  t.lens_tile, t.rays_x, t.rays_y, t.submap, t.waves);
     return buf;
 }
 
@@ -377,60 +377,16 @@ struct Tuner {
         std::sort(results.begin(), results.end(), [](const Result& a, const Result& b) { return a.ms < b.ms; });
         rl_tuning best = results.front().t;
 
-        // work-item size of the batched launch with the best shape: three maps
-        // of a quarter of the rays with N / 4, N and 3 N lenses
-        int item_best = 64;
-        double item_ms = -1.0;
-        if (time_left()) {
-            Probe bp[3];
-            const int64_t nl[3] = {std::max<int64_t>(200, n_lens / 4), n_lens, std::min<int64_t>(20000, n_lens * 3)};
-            for (int i = 0; i < 3; ++i) {
-                e = bp[i].make(nl[i], masses, std::max<int64_t>(min_rays / 4, rays / 4), 0xBA7C0000ull + i);
-                if (e != hipSuccess) return rl::set_error(RL_E_NOMEM, "probe allocation failed");
-            }
-            for (int item : {16, 64, 256}) {
-                rl_tuning t = best;
-                t.item_cells = item;
-                RL_TRY(rl_set_tuning(ctx, prec, cls, &t));
-                rl_map_desc d[3];
-                for (int i = 0; i < 3; ++i)
-                    d[i] = rl_map_desc{bp[i].lenses, bp[i].macro, bp[i].grid, bp[i].win, 0, bp[i].grid.n2,
-                                       static_cast<int32_t*>(bp[i].counts.p),
-                                       static_cast<int64_t*>(bp[i].escaped.p)};
-                double ms = 1e300;
-                for (int r = 0; r <= reps; ++r) {
-                    for (int i = 0; i < 3; ++i) {
-                        e = hipMemsetAsync(bp[i].counts.p, 0, bp[i].map_bytes(), nullptr);
-                        if (e == hipSuccess) e = hipMemsetAsync(bp[i].escaped.p, 0, sizeof(int64_t), nullptr);
-                        if (e != hipSuccess) return rl::set_error(RL_E_DEVICE, hipGetErrorString(e));
-                    }
-                    if ((e = hipEventRecord(tm.a, nullptr)) != hipSuccess)
-                        return rl::set_error(RL_E_DEVICE, hipGetErrorString(e));
-                    RL_TRY(rl_shoot_batch(ctx, d, 3, prec, nullptr));
-                    e = hipEventRecord(tm.b, nullptr);
-                    if (e == hipSuccess) e = hipEventSynchronize(tm.b);
-                    float t2 = 0.0f;
-                    if (e == hipSuccess) e = hipEventElapsedTime(&t2, tm.a, tm.b);
-                    if (e != hipSuccess) return rl::set_error(RL_E_DEVICE, hipGetErrorString(e));
-                    if (r > 0) ms = std::min(ms, (double)t2);
-                }
-                if (item_ms < 0.0 || ms < item_ms) {
-                    item_best = item;
-                    item_ms = ms;
-                }
-            }
-        }
-        best.item_cells = item_best;
         RL_TRY(rl_set_tuning(ctx, prec, cls, &best));
 
         char head[512];
         std::snprintf(head, sizeof head,
                       "  \"%s/%d\": {\"shape\": %s, \"probe_lenses\": %lld, \"probe_masses\": %s, "
                       "\"probe_evals\": %lld, \"best_ms\": %.6g, \"worst_ms\": %.6g, "
-                      "\"probe_evals_per_s\": %.6g, \"candidates\": %zu, \"batch_item_ms\": %.6g, \"top5\": [",
+                      "\"probe_evals_per_s\": %.6g, \"candidates\": %zu, \"top5\": [",
                       prec_name(prec), cls, shape_json(best).c_str(), (long long)n_lens,
                       masses ? "true" : "false", (long long)pr.evals, results.front().ms, results.back().ms,
-                      (double)pr.evals / (results.front().ms * 1e-3), results.size(), item_ms);
+                      (double)pr.evals / (results.front().ms * 1e-3), results.size());
         *json += head;
         for (size_t i = 0; i < std::min<size_t>(5, results.size()); ++i) {
             std::string s = shape_json(results[i].t);
@@ -475,14 +431,14 @@ bool apply_cache(rl_context* ctx, const char* path, const std::string& arch) {
         const int cls = std::atoi(key.c_str() + slash + 1);
         const JValue* sh = kv.second.get("shape");
         if (prec < 0 || !sh) return false;
-        int v[6];
-        const char* names[6] = {"rays_x", "rays_y", "lens_tile", "waves", "submap", "item_cells"};
-        for (int i = 0; i < 6; ++i) {
+        int v[5];
+        const char* names[5] = {"rays_x", "rays_y", "lens_tile", "waves", "submap"};
+        for (int i = 0; i < 5; ++i) {
             const JValue* x = sh->get(names[i]);
             if (!x || x->kind != JValue::Num) return false;
             v[i] = (int)x->num;
         }
-        todo.push_back({{prec, cls}, rl_tuning{v[0], v[1], v[2], v[3], v[4], v[5]}});
+        todo.push_back({{prec, cls}, rl_tuning{v[0], v[1], v[2], v[3], v[4]}});
     }
     std::vector<rl_tuning> saved;
     for (const auto& t : todo) {
@@ -542,9 +498,9 @@ extern "C" rl_status rl_autotune(rl_context* ctx, const char* cache_path, int32_
             if (log) {
                 rl_tuning t;
                 (void)rl_get_tuning(ctx, prec, cls, &t);
-                std::fprintf(stderr, "rl_autotune: %s class %d -> %dx%d tile %d waves %d submap %d item %d (%.1f s)\n",
+                std::fprintf(stderr, "rl_autotune: %s class %d -> %dx%d tile %d waves %d submap %d (%.1f s)\n",
                              prec_name(prec), cls, t.rays_x, t.rays_y, t.lens_tile, t.waves, t.submap,
-                             t.item_cells, std::chrono::duration<double>(Clock::now() - t0).count());
+                             std::chrono::duration<double>(Clock::now() - t0).count());
                 std::fflush(stderr);
             }
             body += (first ? "" : ",\n") + one;

@@ -67,7 +67,7 @@ PROFILES = {"uniform": 0, "gaussian": 1, "power": 2}
 
 class rl_tuning(C.Structure):
     _fields_ = [("rays_x", C.c_int32), ("rays_y", C.c_int32), ("lens_tile", C.c_int32),
-                ("waves", C.c_int32), ("submap", C.c_int32), ("item_cells", C.c_int32)]
+                ("waves", C.c_int32), ("submap", C.c_int32)]
 
 
 _lib = None

@@ -129,23 +129,23 @@ def test_tuning_table_validation():
         t = rl.rl_get_tuning(ctx, rl.RL_FP32_COMP, 1)
         assert t.rays_x * t.rays_y in (16, 32)
         for bad in [dict(rays_x=3), dict(lens_tile=100), dict(lens_tile=4096), dict(waves=3),
-                    dict(submap=3), dict(item_cells=0)]:
+                    dict(submap=3)]:
             cur = {f: getattr(t, f) for f, _ in rl.rl_tuning._fields_}
             cur.update(bad)
             with pytest.raises(rl.RaylensError):
                 rl.rl_set_tuning(ctx, rl.RL_FP32_COMP, 1, rl.rl_tuning(**cur))
-        ok = rl.rl_tuning(2, 8, 512, 2, 0, 8)
+        ok = rl.rl_tuning(2, 8, 512, 2, 0)
         rl.rl_set_tuning(ctx, rl.RL_FP32_COMP, 2, ok)
         back = rl.rl_get_tuning(ctx, rl.RL_FP32_COMP, 2)
-        assert (back.rays_x, back.rays_y, back.lens_tile, back.waves, back.submap,
-                back.item_cells) == (2, 8, 512, 2, 0, 8)
+        assert (back.rays_x, back.rays_y, back.lens_tile, back.waves,
+                back.submap) == (2, 8, 512, 2, 0)
         with pytest.raises(rl.RaylensError):   # FP64 path keeps 4 x 4 rays per lane
             rl.rl_set_tuning(ctx, rl.RL_FP64_PLAIN, 0, ok)
         for cls in (-1, rl.TUNING_CLASSES):
             with pytest.raises(rl.RaylensError):
                 rl.rl_get_tuning(ctx, rl.RL_FP32_COMP, cls)
         # classes 3-5 (fields with masses) are separate entries
-        rl.rl_set_tuning(ctx, rl.RL_FP32_COMP, 5, rl.rl_tuning(4, 8, 256, 4, 1, 16))
+        rl.rl_set_tuning(ctx, rl.RL_FP32_COMP, 5, rl.rl_tuning(4, 8, 256, 4, 1))
         assert rl.rl_get_tuning(ctx, rl.RL_FP32_COMP, 2).rays_y == 8
         assert (rl.rl_get_tuning(ctx, rl.RL_FP32_COMP, 5).rays_x, rl.rl_get_tuning(ctx, rl.RL_FP32_COMP, 5).rays_y) == (4, 8)
         assert rl.tuning_class(999, False) == 0 and rl.tuning_class(10000, True) == 5

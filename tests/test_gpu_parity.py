@@ -322,17 +322,17 @@ def test_batch_equals_alone(ctx, prec):
 
 
 def test_batch_with_two_cells_per_wave_equals_alone(ctx):
-    """The persistent batch launch with the 32-ray shapes (two cells per wave,
-    odd cell counts leave half-waves idle) against single-map launches with
-    the default shapes."""
+    """The batched launch with the 32-ray shapes (two cells per wave, odd cell
+    counts leave half-waves idle) against single-map launches with the
+    default shapes."""
     specs = [SMALL, MIXED_SMALL] + ODD_SHAPES
     fields = [s.lenses() for s in specs]
     Ls = [dev_lenses(f) for f in fields]
     alone = [ctx.shoot(L, s, "fp32c") for L, s in zip(Ls, specs)]
     saved = {c: ctx.get_tuning("fp32c", c) for c in range(rl.TUNING_CLASSES)}
     try:
-        for sh in (dict(rays_x=4, rays_y=8, lens_tile=256, waves=4, submap=1, item_cells=3),
-                   dict(rays_x=8, rays_y=4, lens_tile=256, waves=1, submap=2, item_cells=1)):
+        for sh in (dict(rays_x=4, rays_y=8, lens_tile=256, waves=4, submap=1),
+                   dict(rays_x=8, rays_y=4, lens_tile=256, waves=1, submap=2)):
             for c in range(rl.TUNING_CLASSES):
                 ctx.set_tuning("fp32c", c, **sh)
             outs = [ctx.new_map(s) for s in specs]
@@ -346,10 +346,9 @@ def test_batch_with_two_cells_per_wave_equals_alone(ctx):
 
 
 def test_batch_of_uneven_lens_counts_equals_alone(ctx):
-    """Work items are sized by work (about item_cells cells at 2048 lenses):
-    a batch mixing 0, 1, 300 and 20000 lenses, with and without masses, cut
-    into items of a few cells for the large field and whole maps for the
-    small ones, gives the same bits as each map shot alone."""
+    """A batch mixing 0, 1, 300 and 20000 lenses, with and without masses,
+    over every workgroup size (the segments' 8-block padding and XCD remap
+    differ with it) gives the same bits as each map shot alone."""
     specs = [spec_custom(f"uneven-{n}", 0.45, 0.3, 0.2, 700, 520, 6.0, 3.0, 96, 64, 5.0, 4.0, n,
                          max(1.0, (n / 0.36) ** 0.5), m, 40 + n % 97)
              for n, m in ((20000, "unit"), (0, "unit"), (1, "unit"), (300, "salpeter"), (20000, "salpeter"))]
@@ -358,17 +357,67 @@ def test_batch_of_uneven_lens_counts_equals_alone(ctx):
     saved = {c: ctx.get_tuning("fp32c", c) for c in range(rl.TUNING_CLASSES)}
     try:
         alone = [ctx.shoot(L, s, "fp32c") for L, s in zip(Ls, specs)]
-        for item in (1, 64, 100000):
+        for waves in (1, 2, 4):
             for c in range(rl.TUNING_CLASSES):
-                ctx.set_tuning("fp32c", c, item_cells=item)
+                ctx.set_tuning("fp32c", c, waves=waves)
             outs = [ctx.new_map(s) for s in specs]
             ctx.shoot_batch([(L, s, c, e) for L, s, (c, e) in zip(Ls, specs, outs)], "fp32c")
             for (c, e), (ca, ea), s in zip(outs, alone, specs):
-                assert torch.equal(c, ca), (s.name, item)
-                assert int(e.item()) == int(ea.item()), (s.name, item)
+                assert torch.equal(c, ca), (s.name, waves)
+                assert int(e.item()) == int(ea.item()), (s.name, waves)
     finally:
         for c in range(rl.TUNING_CLASSES):
             ctx.set_tuning("fp32c", c, **saved[c])
+
+
+def test_batch_of_many_maps_equals_alone(ctx):
+    """70 small maps of one tuning class: one launch whose workgroups find
+    their map among 70 segments (two 64-wide comparison rounds); every map
+    equals the map shot alone, row ranges included."""
+    specs = [spec_custom(f"many-{i}", 0.3 + 0.005 * i, 0.2, 0.0, 120 + 7 * (i % 5), 90 + 11 * (i % 3),
+                         4.0, 3.0, 32, 24, 4.0, 3.0, 20 + i, 3.0, "unit", 300 + i)
+             for i in range(70)]
+    fields = [s.lenses() for s in specs]
+    Ls = [dev_lenses(f) for f in fields]
+    rows = [(0, s.n2) if i % 4 else (5 + i % 7, 60 + i % 13) for i, s in enumerate(specs)]
+    alone = []
+    for L, s, (r0, r1) in zip(Ls, specs, rows):
+        c, e = ctx.new_map(s)
+        ctx.shoot(L, s, "fp32c", c, e, row_begin=r0, row_end=r1)
+        alone.append((c, e))
+    outs = [ctx.new_map(s) for s in specs]
+    ctx.shoot_batch([(L, s, c, e, r0, r1) for L, s, (c, e), (r0, r1) in zip(Ls, specs, outs, rows)],
+                    "fp32c")
+    torch.cuda.synchronize()
+    for (c, e), (ca, ea), s in zip(outs, alone, specs):
+        assert torch.equal(c, ca), s.name
+        assert int(e.item()) == int(ea.item()), s.name
+
+
+def test_batch_splits_a_map_over_launches(ctx):
+    """A map needing more than 2^23 workgroups (8.7e9 rays at one cell per
+    workgroup) is cut into row segments over two launches of the batch, as the
+    single-map path cuts it; a small map shares the batch. Both equal their
+    maps shot alone."""
+    big = spec_custom("split-big", 0.4, 0.3, 0.0, 93312, 93312, 30.0, 30.0, 128, 128, 20.0, 20.0,
+                      1, 1.0, "unit", 77)
+    small = spec_custom("split-small", 0.4, 0.3, 0.0, 300, 200, 5.0, 3.0, 64, 64, 4.0, 4.0,
+                        1, 1.0, "unit", 78)
+    specs = [big, small]
+    Ls = [dev_lenses(s.lenses()) for s in specs]
+    saved = ctx.get_tuning("fp32c", 0)
+    try:
+        ctx.set_tuning("fp32c", 0, rays_x=4, rays_y=4, waves=1, submap=1)
+        alone = [ctx.shoot(L, s, "fp32c") for L, s in zip(Ls, specs)]
+        outs = [ctx.new_map(s) for s in specs]
+        ctx.shoot_batch([(L, s, c, e) for L, s, (c, e) in zip(Ls, specs, outs)], "fp32c")
+        torch.cuda.synchronize()
+        for (c, e), (ca, ea), s in zip(outs, alone, specs):
+            assert torch.equal(c, ca), s.name
+            assert int(e.item()) == int(ea.item()), s.name
+        assert int(outs[0][0].sum().item()) + int(outs[0][1].item()) == big.rays
+    finally:
+        ctx.set_tuning("fp32c", 0, **saved)
 
 
 def test_stats_match_the_oracle(ctx):
