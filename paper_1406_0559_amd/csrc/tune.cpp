@@ -175,7 +175,10 @@ bool read_file(const char* path, std::string* out) {
 
 const char* prec_name(int p) { return p == RL_FP32_COMP ? "fp32c" : "fp64"; }
 
-constexpr int kClassLenses[3] = {400, 2624, 16000};
+// Probe lens counts per class: near the geometric middle of 100..1000 for
+// the small fields, the bench map's count for the middle class, 16000 for
+// large fields.
+constexpr int kClassLenses[3] = {300, 2624, 16000};
 
 std::vector<rl_tuning> ray_shapes(int prec) {
     if (prec == RL_FP64_PLAIN) return {rl_tuning{4, 4, 256, 4, 1}};
@@ -355,14 +358,14 @@ struct Tuner {
             return RL_OK;
         };
         // stage 1: rays per lane at a middle tile; stage 2: every tile, wave
-        // count and binning mode for the two best ray shapes
+        // count and binning mode for the three best ray shapes
         for (const rl_tuning& t : ray_shapes(prec)) {
             if (!time_left() && !results.empty()) break;
             RL_TRY(run(t));
         }
         std::vector<Result> stage1 = results;
         std::sort(stage1.begin(), stage1.end(), [](const Result& a, const Result& b) { return a.ms < b.ms; });
-        const size_t top = std::min<size_t>(2, stage1.size());
+        const size_t top = std::min<size_t>(3, stage1.size());
         for (size_t i = 0; i < top && time_left(); ++i)
             for (int tile : {256, 512, 1024, 2048})
                 for (int waves : {1, 2, 4})
