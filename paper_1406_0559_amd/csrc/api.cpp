@@ -244,6 +244,9 @@ struct Scratch {
 
 }  // namespace
 
+// Pinned read-back buffer: the reduction slots plus the escaped count.
+constexpr size_t kReadBytes = rl::kRedBytes + 256;
+
 struct rl_context {
     int device = 0;
     bool ready = false;
@@ -255,6 +258,7 @@ struct rl_context {
     Scratch fft;         // convolution planes
     void* host_stage = nullptr;  // pinned staging for batch records
     size_t host_cap = 0;
+    void* host_read = nullptr;   // pinned landing buffer for small results read back (kReadBytes)
     hipEvent_t stage_done = nullptr;
     bool stage_used = false;
     rl::KernelShape tuning[2][rl::kTuningClasses];
@@ -276,8 +280,21 @@ rl_status ensure_ready(rl_context* ctx) {
     ctx->num_cus = cus > 0 ? cus : 256;
     e = hipEventCreateWithFlags(&ctx->stage_done, hipEventDisableTiming);
     if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    e = hipHostMalloc(&ctx->host_read, kReadBytes, hipHostMallocDefault);
+    if (e != hipSuccess) { ctx->host_read = nullptr; return hip_fail(e, "pinned read-back buffer"); }
     ctx->ready = true;
     return RL_OK;
+}
+
+// Copies `bytes` of device results to host memory in stream order and waits
+// for them: through the context's pinned buffer when they fit (a pageable
+// destination costs an extra staged copy in the runtime), directly otherwise.
+hipError_t read_back(rl_context* ctx, void* dst, const void* src, size_t bytes, hipStream_t s) {
+    const bool pinned = ctx->host_read && bytes <= kReadBytes;
+    hipError_t e = hipMemcpyAsync(pinned ? ctx->host_read : dst, src, bytes, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && pinned) std::memcpy(dst, ctx->host_read, bytes);
+    return e;
 }
 
 // Prepares FP32 hi/lo lens copies in the context's lens scratch.
@@ -375,6 +392,7 @@ rl_status rl_destroy(rl_context* ctx) {
         ctx->aux.destroy();
         ctx->fft.destroy();
         if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
+        if (ctx->host_read) (void)hipHostFree(ctx->host_read);
         if (ctx->stage_done) (void)hipEventDestroy(ctx->stage_done);
     }
     delete ctx;
@@ -593,10 +611,7 @@ rl_status rl_stats_get(rl_context* ctx, const int32_t* d_counts, const int64_t* 
     if (e == hipSuccess)
         e = hipMemcpyAsync(acc + words, d_escaped, sizeof(int64_t), hipMemcpyDeviceToDevice, stream);
     std::vector<unsigned long long> slots(words + 1, 0);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(slots.data(), acc, slots.size() * sizeof(unsigned long long),
-                           hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e == hipSuccess) e = read_back(ctx, slots.data(), acc, slots.size() * sizeof(unsigned long long), stream);
     hipError_t e2 = ctx->stats.release(stream);
     if (e == hipSuccess) e = e2;
     if (e != hipSuccess) return hip_fail(e, "stats");
@@ -849,8 +864,7 @@ rl_status rl_probability_sums(rl_context* ctx, const int32_t* d_counts, const rl
     }
     e = rl::launch_prob_sum(d_counts, n, lo, acc, stream);
     std::vector<unsigned long long> slots(rl::kRedBytes / sizeof(unsigned long long), 0);
-    if (e == hipSuccess) e = hipMemcpyAsync(slots.data(), acc, rl::kRedBytes, hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e == hipSuccess) e = read_back(ctx, slots.data(), acc, rl::kRedBytes, stream);
     hipError_t e2 = ctx->stats.release(stream);
     if (e == hipSuccess) e = e2;
     if (e != hipSuccess) return hip_fail(e, "probability sums");
@@ -898,8 +912,7 @@ rl_status rl_codec_encode(rl_context* ctx, const int32_t* d_counts, const rl_win
     unsigned long long* acc = static_cast<unsigned long long*>(ctx->stats.ptr);
     e = rl::launch_count_stats(d_counts, n_pix, acc, stream);
     std::vector<unsigned long long> slots(rl::kRedBytes / sizeof(unsigned long long), 0);
-    if (e == hipSuccess) e = hipMemcpyAsync(slots.data(), acc, rl::kRedBytes, hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e == hipSuccess) e = read_back(ctx, slots.data(), acc, rl::kRedBytes, stream);
     hipError_t e2 = ctx->stats.release(stream);
     if (e == hipSuccess) e = e2;
     if (e != hipSuccess) return hip_fail(e, "codec statistics");
@@ -927,8 +940,7 @@ rl_status rl_codec_encode(rl_context* ctx, const int32_t* d_counts, const rl_win
     if (e == hipSuccess) e = rl::launch_count_hist(d_counts, n_pix, n_values, hist, stream);
     if (e == hipSuccess) e = rl::launch_distinct_ranks(hist, n_values, flag, rank, sums, total, stream);
     int64_t nd = 0;
-    if (e == hipSuccess) e = hipMemcpyAsync(&nd, total, sizeof(nd), hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e == hipSuccess) e = read_back(ctx, &nd, total, sizeof(nd), stream);
     if (e != hipSuccess) { (void)ctx->aux.release(stream); return hip_fail(e, "codec ranks"); }
     int32_t bits = 1;
     while (bits < 32 && ((int64_t)1 << bits) < nd) ++bits;

@@ -329,13 +329,15 @@ __global__ void scatter_values_kernel(const int32_t* __restrict__ flag,
         if (flag[v]) values[rank[v]] = (int32_t)v;
 }
 
-// One output word per thread: gathers the indices of the pixels whose bits
-// fall into word w (bits [32w, 32w + 32), pixel p at bits [p b, p b + b),
-// least significant bit first). Stores are coalesced and need no atomics.
+// One output word per thread for words [w_begin, n_words): gathers the
+// indices of the pixels whose bits fall into word w (bits [32w, 32w + 32),
+// pixel p at bits [p b, p b + b), least significant bit first). Stores are
+// coalesced and need no atomics. The general path, and the tail of the
+// chunked one.
 __global__ void pack_kernel(const int32_t* __restrict__ counts, int64_t n_pix,
                             const int32_t* __restrict__ rank, int64_t n_values, int bits,
-                            int64_t n_words, uint32_t* __restrict__ packed) {
-    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < n_words;
+                            int64_t w_begin, int64_t n_words, uint32_t* __restrict__ packed) {
+    for (int64_t w = w_begin + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < n_words;
          w += (int64_t)gridDim.x * blockDim.x) {
         const int64_t lo_bit = w * 32;
         const int64_t p0 = lo_bit / bits;
@@ -354,13 +356,64 @@ __global__ void pack_kernel(const int32_t* __restrict__ counts, int64_t n_pix,
     }
 }
 
-// Inverse of pack_kernel; an index past the table (a stream not produced by
-// the encoder) decodes to -1 instead of reading out of bounds.
-__global__ void unpack_kernel(const uint32_t* __restrict__ packed, int64_t n_pix, int bits,
+constexpr int kPackChunk = 4096;      // pixels per chunk: kPackChunk * bits is a whole number of words
+constexpr int kPackRankLds = 8192;    // rank-table entries staged in LDS
+
+// Chunked pack: a workgroup takes 4096 pixels at a time with coalesced
+// 16-byte loads, ORs each pixel's index into an LDS word array at bit p * b
+// (a multiply, no division), and stores the chunk's 128 b words coalesced.
+// The rank table sits in LDS when it has at most kPackRankLds entries.
+// counts 16-byte aligned; full chunks only.
+template <bool LDS>
+__global__ void __launch_bounds__(256) pack_chunks_kernel(const int32_t* __restrict__ counts, int64_t chunks,
+                                                          const int32_t* __restrict__ rank, int64_t n_values,
+                                                          int bits, uint32_t* __restrict__ packed) {
+    __shared__ int32_t sr[LDS ? kPackRankLds : 1];
+    __shared__ uint32_t sw[kPackChunk + 1];
+    if constexpr (LDS) {
+        for (int i = threadIdx.x; i < n_values; i += blockDim.x) sr[i] = rank[i];
+    }
+    const int nw = bits * (kPackChunk / 32);
+    for (int i = threadIdx.x; i <= nw; i += blockDim.x) sw[i] = 0u;
+    __syncthreads();
+    for (int64_t ch = blockIdx.x; ch < chunks; ch += gridDim.x) {
+        const int4* __restrict__ src = reinterpret_cast<const int4*>(counts + ch * kPackChunk);
+        int4 v[kPackChunk / 1024];
+#pragma unroll
+        for (int u = 0; u < kPackChunk / 1024; ++u) v[u] = src[threadIdx.x + 256 * u];
+#pragma unroll
+        for (int u = 0; u < kPackChunk / 1024; ++u) {
+            const int base = 4 * (threadIdx.x + 256 * u);
+            const int c[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                uint32_t idx = 0u;
+                if (c[e] >= 0 && c[e] < n_values) idx = (uint32_t)(LDS ? sr[c[e]] : rank[c[e]]);
+                const int sbit = (base + e) * bits;
+                const uint64_t sh = (uint64_t)idx << (sbit & 31);
+                if ((uint32_t)sh) atomicOr(&sw[sbit >> 5], (uint32_t)sh);
+                if ((uint32_t)(sh >> 32)) atomicOr(&sw[(sbit >> 5) + 1], (uint32_t)(sh >> 32));
+            }
+        }
+        __syncthreads();
+        uint32_t* __restrict__ dst = packed + ch * nw;
+        for (int w = threadIdx.x; w < nw; w += blockDim.x) {
+            dst[w] = sw[w];
+            sw[w] = 0u;
+        }
+        if (threadIdx.x == 0) sw[nw] = 0u;
+        __syncthreads();
+    }
+}
+
+// Inverse of pack_kernel for pixels [p_begin, n_pix); an index past the
+// table (a stream not produced by the encoder) decodes to -1 instead of
+// reading out of bounds. The general path, and the tail of the 4-pixel one.
+__global__ void unpack_kernel(const uint32_t* __restrict__ packed, int64_t p_begin, int64_t n_pix, int bits,
                               const int32_t* __restrict__ values, int64_t n_values,
                               int32_t* __restrict__ counts) {
     const unsigned long long mask = bits >= 32 ? 0xFFFFFFFFull : ((1ull << bits) - 1ull);
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n_pix;
+    for (int64_t p = p_begin + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n_pix;
          p += (int64_t)gridDim.x * blockDim.x) {
         const int64_t start = p * bits;
         const int64_t w = start >> 5;
@@ -369,6 +422,44 @@ __global__ void unpack_kernel(const uint32_t* __restrict__ packed, int64_t n_pix
         if (off + bits > 32) v |= (unsigned long long)packed[w + 1] << (32 - off);
         const unsigned long long idx = v & mask;
         counts[p] = idx < (unsigned long long)n_values ? values[idx] : -1;
+    }
+}
+
+constexpr int kUnpackValuesLds = 4096;   // value-table entries staged in LDS
+
+// 4-pixel unpack for codes of at most 16 bits: a thread decodes pixels
+// 4q .. 4q + 3, whose 4 b bits lie in the three words from bit 4 q b on (read
+// together before any is used; words past the stream's n_words read as 0),
+// and stores them as one 16-byte write; the value table sits in LDS when it
+// has at most kUnpackValuesLds entries. counts 16-byte aligned; pixels
+// [0, 4 nq).
+template <bool LDS>
+__global__ void __launch_bounds__(256) unpack4_kernel(const uint32_t* __restrict__ packed, int64_t n_words,
+                                                      int64_t nq, int bits, const int32_t* __restrict__ values,
+                                                      int64_t n_values, int32_t* __restrict__ counts) {
+    __shared__ int32_t sv[LDS ? kUnpackValuesLds : 1];
+    if constexpr (LDS) {
+        for (int i = threadIdx.x; i < n_values; i += blockDim.x) sv[i] = values[i];
+        __syncthreads();
+    }
+    const uint32_t mask = (1u << bits) - 1u;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t start = q * 4 * bits;
+        const int64_t w = start >> 5;
+        const int off = (int)(start & 31);
+        const uint32_t w0 = packed[w];
+        const uint32_t w1 = w + 1 < n_words ? packed[w + 1] : 0u;
+        const uint32_t w2 = w + 2 < n_words ? packed[w + 2] : 0u;
+        const unsigned __int128 all = (unsigned __int128)w0 | ((unsigned __int128)w1 << 32) |
+                                      ((unsigned __int128)w2 << 64);
+        int r[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t idx = (uint32_t)(all >> (off + u * bits)) & mask;
+            if constexpr (LDS) r[u] = idx < (uint32_t)n_values ? sv[idx] : -1;
+            else r[u] = idx < (uint32_t)n_values ? values[idx] : -1;
+        }
+        reinterpret_cast<int4*>(counts)[q] = make_int4(r[0], r[1], r[2], r[3]);
     }
 }
 
@@ -463,16 +554,44 @@ hipError_t launch_codec_pack(const int32_t* counts, int64_t n_pix, const int32_t
     const int64_t n_words = (n_pix * bits + 31) / 32;
     hipLaunchKernelGGL(scatter_values_kernel, dim3(grid_for(n_values, 256, 8192)), dim3(256), 0, s, flag,
                        rank, n_values, values);
-    hipLaunchKernelGGL(pack_kernel, dim3(grid_for(n_words, 256, 16384)), dim3(256), 0, s, counts, n_pix,
-                       rank, n_values, bits, n_words, packed);
+    // whole 4096-pixel chunks through the chunked kernel when the counts are
+    // 16-byte aligned, the remaining words word by word
+    const int64_t chunks = (reinterpret_cast<uintptr_t>(counts) % 16 == 0) ? n_pix / kPackChunk : 0;
+    if (chunks > 0) {
+        const int g = grid_for(chunks, 1, 2048);
+        if (n_values <= kPackRankLds)
+            hipLaunchKernelGGL(pack_chunks_kernel<true>, dim3(g), dim3(256), 0, s, counts, chunks, rank,
+                               n_values, bits, packed);
+        else
+            hipLaunchKernelGGL(pack_chunks_kernel<false>, dim3(g), dim3(256), 0, s, counts, chunks, rank,
+                               n_values, bits, packed);
+    }
+    const int64_t w_begin = chunks * (kPackChunk / 32) * bits;
+    if (w_begin < n_words)
+        hipLaunchKernelGGL(pack_kernel, dim3(grid_for(n_words - w_begin, 256, 16384)), dim3(256), 0, s,
+                           counts, n_pix, rank, n_values, bits, w_begin, n_words, packed);
     return hipGetLastError();
 }
 
 hipError_t launch_codec_unpack(const uint32_t* packed, int64_t n_pix, int bits, const int32_t* values,
                                int64_t n_values, int32_t* counts, hipStream_t s) {
     if (n_pix <= 0) return hipSuccess;
-    hipLaunchKernelGGL(unpack_kernel, dim3(grid_for(n_pix, 256, 16384)), dim3(256), 0, s, packed, n_pix,
-                       bits, values, n_values, counts);
+    // 4 pixels per thread for codes of <= 16 bits into 16-byte aligned maps;
+    // the last n_pix % 4 pixels (or all, otherwise) one per thread
+    const int64_t nq = (bits <= 16 && reinterpret_cast<uintptr_t>(counts) % 16 == 0) ? n_pix / 4 : 0;
+    if (nq > 0) {
+        const int g = grid_for(nq, 256, 2048);
+        const int64_t n_words = (n_pix * bits + 31) / 32;
+        if (n_values <= kUnpackValuesLds)
+            hipLaunchKernelGGL(unpack4_kernel<true>, dim3(g), dim3(256), 0, s, packed, n_words, nq, bits,
+                               values, n_values, counts);
+        else
+            hipLaunchKernelGGL(unpack4_kernel<false>, dim3(g), dim3(256), 0, s, packed, n_words, nq, bits,
+                               values, n_values, counts);
+    }
+    if (4 * nq < n_pix)
+        hipLaunchKernelGGL(unpack_kernel, dim3(grid_for(n_pix - 4 * nq, 256, 16384)), dim3(256), 0, s,
+                           packed, 4 * nq, n_pix, bits, values, n_values, counts);
     return hipGetLastError();
 }
 

@@ -36,13 +36,36 @@ def roundtrip(ctx, c, spec):
 
 
 @pytest.mark.parametrize("hi,shape", [(0, (16, 16)), (1, (33, 17)), (255, (257, 131)),
-                                      (70000, (301, 203)), (2 ** 31 - 1, (64, 64))])
+                                      (70000, (301, 203)), (2 ** 31 - 1, (64, 64)),
+                                      (1_000_000, (512, 512)), (5000, (4096, 3))])
 def test_random_maps(ctx, hi, shape):
     rng = np.random.default_rng(hi % 1000 + 1)
     c = rng.integers(0, hi, size=shape, endpoint=True).astype(np.int32)
     if hi == 2 ** 31 - 1:
         c = np.minimum(c, 3_000_000)        # keep the value histogram to a few MB
     roundtrip(ctx, c, spec_of(shape[1], shape[0]))
+
+
+def test_unaligned_maps_take_the_general_kernels(ctx):
+    """Counts at a 4-byte offset (not 16-byte aligned) encode and decode with
+    the word-by-word and pixel-by-pixel kernels: same stream, same map."""
+    p1, p2 = 129, 67            # 8643 pixels: two whole 4096-pixel chunks and a tail when aligned
+    rng = np.random.default_rng(9)
+    c = rng.integers(0, 900, size=(p2, p1)).astype(np.int32)
+    spec = spec_of(p1, p2)
+    ov, ob, op = oracle.codec_encode(c)
+    big = torch.zeros(p1 * p2 + 1, dtype=torch.int32, device="cuda")
+    view = big[1:].view(p2, p1)
+    view.copy_(torch.from_numpy(c).cuda())
+    assert view.data_ptr() % 16 != 0
+    values, bits, packed = ctx.encode(view, spec)
+    assert bits == ob and (values.cpu().numpy() == ov).all()
+    assert (packed.cpu().numpy().view(np.uint32) == op).all()
+    out = torch.full((p1 * p2 + 1,), -7, dtype=torch.int32, device="cuda")
+    oview = out[1:].view(p2, p1)
+    ctx.decode(packed, bits, values, spec, counts=oview)
+    assert torch.equal(oview, view)
+    assert int(out[0].item()) == -7
 
 
 def test_shot_maps(ctx):
