@@ -535,17 +535,16 @@ __global__ void product_kernel(cplx* __restrict__ t, int n1, int n2) {
 
 // E = 8 points per thread (4 for N = 256): radix-8 stages, the last one of
 // radix 2 or 4 where N is not a power of 8.
-template <int N> constexpr int p2_threads() { return N == 256 ? 64 : (N == 4096 ? 1024 : N / 8); }
+template <int N> constexpr int p2_threads() { return N == 256 ? 64 : N / 8; }
 template <int N> constexpr int p2_stages() {
-    return N == 512 ? 3 : (N == 8192 ? 5 : (N == 4096 ? 6 : 4));
+    return N == 512 ? 3 : (N == 8192 ? 5 : 4);
 }
 template <int N, int S> constexpr int p2_radix() {
     return N == 256 ? 4
          : N == 1024 ? (S < 3 ? 8 : 2)
          : N == 2048 ? (S < 3 ? 8 : 4)
          : N == 8192 ? (S < 4 ? 8 : 2)
-         : N == 4096 ? 4
-         : 8;    // 512
+         : 8;    // 512, 4096
 }
 template <int N> constexpr int p2_lds() { return N + N / 16; }
 // NS of stage S (the product of the radices before it) and the offset of its
@@ -638,7 +637,7 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 // workgroups fit a CU).
 template <int N>
 __global__ void __launch_bounds__(p2_threads<N>())
-__attribute__((amdgpu_waves_per_eu(N == 4096 ? 8 : (N == 2048 ? 4 : 1))))
+__attribute__((amdgpu_waves_per_eu(N >= 2048 && N <= 4096 ? 4 : 1)))
 p2_rows_fwd_kernel(const int32_t* __restrict__ M, const double* __restrict__ K, int p2,
                    cplx* __restrict__ A, const cplx* __restrict__ tw) {
     constexpr int T = p2_threads<N>(), E = N / T;
@@ -682,7 +681,7 @@ p2_rows_fwd_kernel(const int32_t* __restrict__ M, const double* __restrict__ K, 
 // two workgroups fit a CU).
 template <int N>
 __global__ void __launch_bounds__(p2_threads<N>())
-__attribute__((amdgpu_waves_per_eu(N == 4096 ? 8 : (N == 2048 ? 4 : 1))))
+__attribute__((amdgpu_waves_per_eu(N >= 2048 && N <= 4096 ? 4 : 1)))
 p2_cols_kernel(const cplx* __restrict__ A, int H, cplx* __restrict__ G, const cplx* __restrict__ tw) {
     constexpr int T = p2_threads<N>(), E = N / T;
     __shared__ cplx lds[p2_lds<N>()];
@@ -721,7 +720,7 @@ p2_cols_kernel(const cplx* __restrict__ A, int H, cplx* __restrict__ G, const cp
 // Pass C. Block = rows j0 .. j0 + 3 of the output (p1 = N points along x1).
 template <int N>
 __global__ void __launch_bounds__(p2_threads<N>())
-__attribute__((amdgpu_waves_per_eu(N == 4096 ? 8 : (N == 2048 ? 4 : 1))))
+__attribute__((amdgpu_waves_per_eu(N >= 2048 && N <= 4096 ? 4 : 1)))
 p2_rows_inv_kernel(const cplx* __restrict__ G, int p2, double scale, double* __restrict__ out,
                    const cplx* __restrict__ tw) {
     constexpr int T = p2_threads<N>(), E = N / T, H = N / 2 + 1;
@@ -766,8 +765,8 @@ FftPlan p2_plan() {
     FftPlan P{};
     P.n = N;
     P.ns = p2_stages<N>();
-    const int r[6] = {p2_radix<N, 0>(), p2_radix<N, 1>(), p2_radix<N, 2>(), p2_radix<N, 3>(),
-                      p2_radix<N, 4>(), p2_radix<N, 5>()};
+    const int r[5] = {p2_radix<N, 0>(), p2_radix<N, 1>(), p2_radix<N, 2>(), p2_radix<N, 3>(),
+                      p2_radix<N, 4>()};
     P.L[0] = 1;
     for (int s = 0; s < P.ns; ++s) {
         P.r[s] = r[s];
