@@ -202,6 +202,7 @@ struct Scratch {
     size_t cap = 0;
     hipEvent_t last = nullptr;
     bool used = false;
+    uint64_t gen = 0;    // bumped on every (re)allocation: contents from before are gone
 
     hipError_t acquire(size_t bytes, hipStream_t s) {
         hipError_t e;
@@ -225,6 +226,7 @@ struct Scratch {
             size_t want = std::max<size_t>(bytes, 1 << 16);
             want = (want + 4095) & ~(size_t)4095;
             e = hipMalloc(&ptr, want);
+            ++gen;
             if (e != hipSuccess) { ptr = nullptr; return e; }
             cap = want;
         }
@@ -256,6 +258,10 @@ struct rl_context {
     Scratch stats;       // reduction outputs
     Scratch aux;         // MPD thresholds, codec tables, source samples
     Scratch fft;         // convolution planes
+    // sides and scratch generation of the stage-twiddle tables the last
+    // convolution left in the fft scratch (recomputed when either changes)
+    int fft_tw_p1 = 0, fft_tw_p2 = 0;
+    uint64_t fft_tw_gen = 0;
     void* host_stage = nullptr;  // pinned staging for batch records
     size_t host_cap = 0;
     void* host_read = nullptr;   // pinned landing buffer for small results read back (kReadBytes)
@@ -1025,10 +1031,19 @@ rl_status rl_convolve(rl_context* ctx, const int32_t* d_counts, const double* d_
     RL_TRY(ensure_ready(ctx));
     hipError_t e = ctx->fft.acquire(rl::convolve_scratch_bytes(win->p1, win->p2), stream);
     if (e != hipSuccess) return hip_fail(e, "convolution scratch");
-    e = rl::launch_convolve(d_counts, d_kernel, win->p1, win->p2, n_avg, d_out, ctx->fft.ptr, stream);
+    const bool tw_ready = ctx->fft_tw_gen == ctx->fft.gen && ctx->fft_tw_p1 == win->p1 &&
+                          ctx->fft_tw_p2 == win->p2;
+    e = rl::launch_convolve(d_counts, d_kernel, win->p1, win->p2, n_avg, d_out, ctx->fft.ptr, tw_ready,
+                            stream);
     hipError_t e2 = ctx->fft.release(stream);
     if (e == hipSuccess) e = e2;
-    if (e != hipSuccess) return hip_fail(e, "convolution launch");
+    if (e != hipSuccess) {
+        ctx->fft_tw_p1 = 0;
+        return hip_fail(e, "convolution launch");
+    }
+    ctx->fft_tw_gen = ctx->fft.gen;
+    ctx->fft_tw_p1 = win->p1;
+    ctx->fft_tw_p2 = win->p2;
     return RL_OK;
 }
 

@@ -650,8 +650,14 @@ p2_rows_fwd_kernel(const int32_t* __restrict__ M, const double* __restrict__ K, 
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             const int i = t + T * m;
-            if (v == 0) a[0][m] = cplx{(double)M[(int64_t)j0 * N + i], (double)M[(int64_t)(j0 + 1) * N + i]};
-            else a[0][m] = cplx{K[(int64_t)j0 * N + i], K[(int64_t)(j0 + 1) * N + i]};
+            // streamed once: non-temporal, so they do not push the half
+            // spectra's partly written lines out of L2
+            if (v == 0)
+                a[0][m] = cplx{(double)__builtin_nontemporal_load(&M[(int64_t)j0 * N + i]),
+                               (double)__builtin_nontemporal_load(&M[(int64_t)(j0 + 1) * N + i])};
+            else
+                a[0][m] = cplx{__builtin_nontemporal_load(&K[(int64_t)j0 * N + i]),
+                               __builtin_nontemporal_load(&K[(int64_t)(j0 + 1) * N + i])};
         }
         p2_fft<N, 0, 1, 1>(a, lds, tw, false);
         // unpack: X^(u) = (Z(u) + conj Z(-u)) / 2, Y^(u) = (Z(u) - conj Z(-u)) / 2i,
@@ -676,6 +682,13 @@ p2_rows_fwd_kernel(const int32_t* __restrict__ M, const double* __restrict__ K, 
     }
 }
 
+// A complex value read once by this workgroup (its whole cache line is read
+// by the same wave): non-temporal, so it does not hold L2 lines that
+// partly written outputs still need.
+__device__ __forceinline__ cplx nt_load(const cplx* p) {
+    return cplx{__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y)};
+}
+
 // Pass B. Block = column u1 of the half spectra (p2 = N points along x2);
 // the two forward transforms run one after the other (fewer live registers:
 // two workgroups fit a CU).
@@ -694,7 +707,7 @@ p2_cols_kernel(const cplx* __restrict__ A, int H, cplx* __restrict__ G, const cp
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const int i = t + T * m;
-        a[0][m] = colm[(int64_t)(i >> 3) * H * 8 + (i & 7)];
+        a[0][m] = nt_load(&colm[(int64_t)(i >> 3) * H * 8 + (i & 7)]);
     }
     p2_fft<N, 0, 1, 1>(a, lds, tw, false);
     // keep K^'s loads after M^'s transform: hoisted, they would hold registers
@@ -703,7 +716,7 @@ p2_cols_kernel(const cplx* __restrict__ A, int H, cplx* __restrict__ G, const cp
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const int i = t + T * m;
-        b[0][m] = colk[(int64_t)(i >> 3) * H * 8 + (i & 7)];
+        b[0][m] = nt_load(&colk[(int64_t)(i >> 3) * H * 8 + (i & 7)]);
     }
     p2_fft<N, 0, 1, 1>(b, lds, tw, false);
 #pragma unroll
@@ -749,10 +762,11 @@ p2_rows_inv_kernel(const cplx* __restrict__ G, int p2, double scale, double* __r
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const int i = t + T * m;
-        o[i] = a[0][m].x * scale;
-        o[N + i] = a[0][m].y * scale;
-        o[2 * N + i] = a[1][m].x * scale;
-        o[3 * N + i] = a[1][m].y * scale;
+        // written once and not read back here: non-temporal
+        __builtin_nontemporal_store(a[0][m].x * scale, &o[i]);
+        __builtin_nontemporal_store(a[0][m].y * scale, &o[N + i]);
+        __builtin_nontemporal_store(a[1][m].x * scale, &o[2 * N + i]);
+        __builtin_nontemporal_store(a[1][m].y * scale, &o[3 * N + i]);
     }
 }
 
@@ -849,15 +863,17 @@ size_t p2_scratch_bytes(int p1, int p2) {
 }
 
 hipError_t p2_convolve(const int32_t* counts, const double* kernel, int p1, int p2, double n_avg,
-                       double* out, void* scratch, hipStream_t s) {
+                       double* out, void* scratch, bool twiddles_ready, hipStream_t s) {
     const int H = p1 / 2 + 1;
     cplx* A = static_cast<cplx*>(scratch);                 // {M^, K^} x p2 / 8 x H x {eight rows}
     cplx* G = A + (size_t)H * p2 * 2;                      // p2 / 4 x H x {4 rows}
     cplx* tw1 = G + (size_t)H * p2;                        // stage twiddles along x1
     cplx* tw2 = tw1 + p1;                                  // ... along x2
-    const FftPlan P1 = p2_plan_of(p1), P2 = p2_plan_of(p2);
-    hipLaunchKernelGGL(p2_twiddle_kernel, dim3((p1 + 255) / 256), dim3(256), 0, s, tw1, P1);
-    hipLaunchKernelGGL(p2_twiddle_kernel, dim3((p2 + 255) / 256), dim3(256), 0, s, tw2, P2);
+    if (!twiddles_ready) {
+        const FftPlan P1 = p2_plan_of(p1), P2 = p2_plan_of(p2);
+        hipLaunchKernelGGL(p2_twiddle_kernel, dim3((p1 + 255) / 256), dim3(256), 0, s, tw1, P1);
+        hipLaunchKernelGGL(p2_twiddle_kernel, dim3((p2 + 255) / 256), dim3(256), 0, s, tw2, P2);
+    }
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = p2_rows_fwd_any(p1, counts, kernel, p2, A, tw1, s);
     if (e == hipSuccess) e = p2_cols_any(p2, A, G, H, tw2, s);
@@ -1002,8 +1018,9 @@ size_t convolve_scratch_bytes(int p1, int p2) {
 }
 
 hipError_t launch_convolve(const int32_t* counts, const double* kernel, int p1, int p2, double n_avg,
-                           double* out, void* scratch, hipStream_t s) {
-    if (pow2_side(p1) && pow2_side(p2)) return p2_convolve(counts, kernel, p1, p2, n_avg, out, scratch, s);
+                           double* out, void* scratch, bool twiddles_ready, hipStream_t s) {
+    if (pow2_side(p1) && pow2_side(p2))
+        return p2_convolve(counts, kernel, p1, p2, n_avg, out, scratch, twiddles_ready, s);
     // plans for the x1 rows, the x2 row pairs and (long columns) the x2 rows
     FftPlan P1, P2, P2r;
     if (p1 > kMaxFftSide || p2 > kMaxFftSide || !make_plan(p1, &P1, max_radix(p1, 1, row_threads(p1))) ||
@@ -1018,9 +1035,11 @@ hipError_t launch_convolve(const int32_t* counts, const double* kernel, int p1, 
     cplx* tw2r = tw2 + p2;                              // ... of P2r (rows)
     double* part = reinterpret_cast<double*>(tw2r + p2); // kNormBlocks x {|M|^2, |K|^2}
     double* bal = part + 2 * kNormBlocks;               // {2^e, 2^-e}
-    hipLaunchKernelGGL(stage_twiddle_kernel, dim3((p1 + 255) / 256), dim3(256), 0, s, tw1, P1);
-    hipLaunchKernelGGL(stage_twiddle_kernel, dim3((p2 + 255) / 256), dim3(256), 0, s, tw2, P2);
-    hipLaunchKernelGGL(stage_twiddle_kernel, dim3((p2 + 255) / 256), dim3(256), 0, s, tw2r, P2r);
+    if (!twiddles_ready) {
+        hipLaunchKernelGGL(stage_twiddle_kernel, dim3((p1 + 255) / 256), dim3(256), 0, s, tw1, P1);
+        hipLaunchKernelGGL(stage_twiddle_kernel, dim3((p2 + 255) / 256), dim3(256), 0, s, tw2, P2);
+        hipLaunchKernelGGL(stage_twiddle_kernel, dim3((p2 + 255) / 256), dim3(256), 0, s, tw2r, P2r);
+    }
     hipLaunchKernelGGL(norms_kernel, dim3(kNormBlocks), dim3(256), 0, s, counts, kernel, n, part);
     hipLaunchKernelGGL(balance_kernel, dim3(1), dim3(256), 0, s, part, bal);
     // forward along x1 (rows of the map), Z = M + i 2^e K packed on the way in

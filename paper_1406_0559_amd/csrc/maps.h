@@ -52,8 +52,11 @@ hipError_t launch_codec_unpack(const uint32_t* packed, int64_t n_pix, int bits, 
 // [2, kMaxFftSide].
 bool fft_side_supported(int n);
 size_t convolve_scratch_bytes(int p1, int p2);
+// The scratch holds the stage-twiddle tables of both axes at offsets fixed
+// by (p1, p2); twiddles_ready says that a previous call with the same sides
+// and the same scratch buffer left them there, so they are not recomputed.
 hipError_t launch_convolve(const int32_t* counts, const double* kernel, int p1, int p2, double n_avg,
-                           double* out, void* scratch, hipStream_t stream);
+                           double* out, void* scratch, bool twiddles_ready, hipStream_t stream);
 size_t source_scratch_bytes(int h1, int h2);
 hipError_t launch_source_kernel(int shape, double radius, double hole, double pix1, double pix2,
                                 int h1, int h2, int p1, int p2, double* kernel, double* scratch,

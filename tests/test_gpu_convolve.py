@@ -97,3 +97,31 @@ def test_convolution_of_a_10000sq_map_at_sampled_pixels(ctx):
     got = np.array([mu[j, i] for j, i in pts])
     assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
     assert abs(mu.sum() * 40.0 - M.sum(dtype=np.int64)) < 1e-9 * M.sum(dtype=np.int64)
+
+
+def test_cached_twiddles_across_calls():
+    """A fresh context convolves sides in the order A, A, B, A, C (C larger,
+    so the scratch is reallocated), A: the stage-twiddle tables are reused
+    only while the sides and the scratch buffer are the same, and every call
+    gives the same bits as the first call for its sides."""
+    c = rl.Context(0)
+    try:
+        rng = np.random.default_rng(17)
+        sides = {"A": (512, 256), "B": (300, 120), "C": (2048, 1024)}
+        data = {}
+        for name, (p1, p2) in sides.items():
+            M = rng.integers(0, 900, size=(p2, p1)).astype(np.int32)
+            K = rng.random((p2, p1))
+            K /= K.sum()
+            data[name] = (spec_of(p1, p2), torch.from_numpy(M).cuda(), torch.from_numpy(K).cuda(),
+                          ocv.convolve(M, K, 2.5))
+        first = {}
+        for name in ["A", "A", "B", "A", "C", "A"]:
+            spec, M, K, ref = data[name]
+            out = c.convolve(M, K, spec, n_avg=2.5).cpu().numpy()
+            assert np.abs(out - ref).max() <= 1e-12 * np.abs(ref).max(), name
+            if name in first:
+                assert np.array_equal(out, first[name]), name
+            first.setdefault(name, out)
+    finally:
+        c.close()
