@@ -897,60 +897,71 @@ __device__ double brightness(int shape, double r, double radius, double hole) {
     return pow((r > core ? r : core) / radius, -0.75);
 }
 
-// Pixel (i, j), |i| <= h1, |j| <= h2, gets the mean brightness over an s x s
+// Pixel (i, j), |i| <= h1, |j| <= h2, gets the mean brightness over an 8 x 8
 // grid of sub-samples, stored compactly at q = (j + h2) (2 h1 + 1) + (i + h1).
-__global__ void source_samples_kernel(int shape, double radius, double hole, double pix1, double pix2,
-                                      int h1, int h2, int s, double* __restrict__ compact) {
+// One wave per pixel, lane l on sub-sample (l mod 8, l / 8); the 64 values are
+// summed in a fixed butterfly order.
+constexpr int kSourceSub = 8;
+__global__ void __launch_bounds__(256) source_samples_kernel(int shape, double radius, double hole, double pix1,
+                                                             double pix2, int h1, int h2,
+                                                             double* __restrict__ compact) {
     const int w = 2 * h1 + 1;
     const int64_t total = (int64_t)w * (2 * h2 + 1);
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
-         q += (int64_t)gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x % 64;
+    const double ox = ((double)(lane % kSourceSub) + 0.5) / (double)kSourceSub - 0.5;
+    const double oy = ((double)(lane / kSourceSub) + 0.5) / (double)kSourceSub - 0.5;
+    const int wpb = blockDim.x / 64;
+    for (int64_t q = (int64_t)blockIdx.x * wpb + threadIdx.x / 64; q < total; q += (int64_t)gridDim.x * wpb) {
         const int i = (int)(q % w) - h1, j = (int)(q / w) - h2;
-        double acc = 0.0;
-        for (int b = 0; b < s; ++b) {
-            const double y = ((double)j + (((double)b + 0.5) / (double)s - 0.5)) * pix2;
-            for (int a = 0; a < s; ++a) {
-                const double x = ((double)i + (((double)a + 0.5) / (double)s - 0.5)) * pix1;
-                acc += brightness(shape, hypot(x, y), radius, hole);
-            }
-        }
-        compact[q] = acc / (double)(s * s);
+        const double x = ((double)i + ox) * pix1;
+        const double y = ((double)j + oy) * pix2;
+        double v = brightness(shape, hypot(x, y), radius, hole);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (lane == 0) compact[q] = v / (double)(kSourceSub * kSourceSub);
     }
 }
 
-// One workgroup, fixed summation order: the normalisation is reproducible.
-__global__ void __launch_bounds__(256) ordered_sum_kernel(const double* __restrict__ v, int64_t n,
-                                                          double* __restrict__ out) {
-    __shared__ double part[256];
+// One workgroup, fixed summation order (four loads in flight per thread, then
+// a fixed tree): the normalisation is reproducible.
+__global__ void __launch_bounds__(1024) ordered_sum_kernel(const double* __restrict__ v, int64_t n,
+                                                           double* __restrict__ out) {
+    __shared__ double part[1024];
+    const int t = threadIdx.x;
     double s = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += v[i];
-    part[threadIdx.x] = s;
+    int64_t i = t;
+    for (; i + 3 * 1024 < n; i += 4 * 1024) {
+        const double a = v[i], b = v[i + 1024], c = v[i + 2048], d = v[i + 3072];
+        s += a;
+        s += b;
+        s += c;
+        s += d;
+    }
+    for (; i < n; i += 1024) s += v[i];
+    part[t] = s;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int i = 0; i < (int)blockDim.x; ++i) t += part[i];
-        *out = t;
+    for (int h = 512; h > 0; h >>= 1) {
+        if (t < h) part[t] += part[t + h];
+        __syncthreads();
     }
+    if (t == 0) *out = part[0];
 }
 
-// kernel[(j mod p2), (i mod p1)] = compact[q] / total
-__global__ void scatter_kernel(const double* __restrict__ compact, int h1, int h2, int p1, int p2,
-                               const double* __restrict__ total, double* __restrict__ k) {
-    const int w = 2 * h1 + 1;
-    const int64_t m = (int64_t)w * (2 * h2 + 1);
-    const double t = *total;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < m;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        const int i = (int)(q % w) - h1, j = (int)(q / w) - h2;
-        const int ii = ((i % p1) + p1) % p1, jj = ((j % p2) + p2) % p2;
-        k[(int64_t)jj * p1 + ii] = compact[q] / t;
-    }
-}
-
-__global__ void zero_f64_kernel(double* __restrict__ v, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        v[i] = 0.0;
+// The whole p2 x p1 kernel in one pass, row jj = blockIdx.y: pixel (ii, jj)
+// holds compact[(j + h2) (2 h1 + 1) + (i + h1)] / total for the offsets
+// i = ii or ii - p1, j = jj or jj - p2 inside the source box, 0 elsewhere
+// (2 h + 1 <= p on both axes, so no two offsets meet).
+__global__ void __launch_bounds__(256) fill_source_kernel(const double* __restrict__ compact, int h1, int h2,
+                                                          int p1, int p2, const double* __restrict__ total,
+                                                          double* __restrict__ k) {
+    const int jj = blockIdx.y;
+    const int ii = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ii >= p1) return;
+    const int j = jj <= h2 ? jj : jj - p2;
+    const int i = ii <= h1 ? ii : ii - p1;
+    double v = 0.0;
+    if (j >= -h2 && j <= h2 && i >= -h1 && i <= h1) v = compact[(int64_t)(j + h2) * (2 * h1 + 1) + (i + h1)] / *total;
+    k[(int64_t)jj * p1 + ii] = v;
 }
 
 int grid_of(int64_t n, int cap) {
@@ -1069,16 +1080,14 @@ size_t source_scratch_bytes(int h1, int h2) {
 hipError_t launch_source_kernel(int shape, double radius, double hole, double pix1, double pix2,
                                 int h1, int h2, int p1, int p2, double* kernel, double* scratch,
                                 hipStream_t s) {
-    const int64_t n = (int64_t)p1 * p2;
     const int64_t m = (int64_t)(2 * h1 + 1) * (2 * h2 + 1);
     double* total = scratch;
     double* compact = scratch + 2;
-    hipLaunchKernelGGL(zero_f64_kernel, dim3(grid_of(n, 8192)), dim3(256), 0, s, kernel, n);
-    hipLaunchKernelGGL(source_samples_kernel, dim3(grid_of(m, 8192)), dim3(256), 0, s, shape, radius,
-                       hole, pix1, pix2, h1, h2, 8, compact);
-    hipLaunchKernelGGL(ordered_sum_kernel, dim3(1), dim3(256), 0, s, compact, m, total);
-    hipLaunchKernelGGL(scatter_kernel, dim3(grid_of(m, 8192)), dim3(256), 0, s, compact, h1, h2, p1, p2,
-                       total, kernel);
+    hipLaunchKernelGGL(source_samples_kernel, dim3((unsigned)std::min<int64_t>((m + 3) / 4, 65536)), dim3(256), 0,
+                       s, shape, radius, hole, pix1, pix2, h1, h2, compact);
+    hipLaunchKernelGGL(ordered_sum_kernel, dim3(1), dim3(1024), 0, s, compact, m, total);
+    hipLaunchKernelGGL(fill_source_kernel, dim3((p1 + 255) / 256, p2), dim3(256), 0, s, compact, h1, h2, p1,
+                       p2, total, kernel);
     return hipGetLastError();
 }
 
