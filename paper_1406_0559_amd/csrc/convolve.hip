@@ -42,13 +42,23 @@ __device__ __forceinline__ cplx conj(cplx a) { return cplx{a.x, -a.y}; }
 __device__ __forceinline__ cplx rot(cplx a, double sg) { return cplx{-sg * a.y, sg * a.x}; }
 
 
-// In-place DFTs of 2, 3, 4, 5, 8 and 16 points:
+// In-place DFTs of 2, 3, 4, 5, 8, 10 and 16 points:
 // y_k = sum_q a_q exp(sg 2 pi i k q / r), sg = -1 forward, +1 inverse.
 constexpr double kSin60 = 0.86602540378443864676;    // sqrt(3) / 2
 constexpr double kCos72 = 0.30901699437494742410;    // (sqrt(5) - 1) / 4
 constexpr double kCos144 = -0.80901699437494742410;  // -(sqrt(5) + 1) / 4
 constexpr double kSin72 = 0.95105651629515357212;
 constexpr double kSin144 = 0.58778525229247312917;
+
+// cos and sin of 2 pi m / 10, m = 0 .. 9
+constexpr double kC10[10] = {1.0, 0.80901699437494742410, 0.30901699437494742410,
+                             -0.30901699437494742410, -0.80901699437494742410, -1.0,
+                             -0.80901699437494742410, -0.30901699437494742410,
+                             0.30901699437494742410, 0.80901699437494742410};
+constexpr double kS10[10] = {0.0, 0.58778525229247312917, 0.95105651629515357212,
+                             0.95105651629515357212, 0.58778525229247312917, 0.0,
+                             -0.58778525229247312917, -0.95105651629515357212,
+                             -0.95105651629515357212, -0.58778525229247312917};
 
 // cos and sin of 2 pi m / 16, m = 0 .. 15
 constexpr double kC16[16] = {1.0, 0.92387953251128675613, 0.70710678118654752440,
@@ -82,8 +92,15 @@ __device__ __forceinline__ void composite_dft(cplx* a, double sg) {
 #pragma unroll
         for (int k1 = 1; k1 < A; ++k1) {
             if (q2 == 0) continue;
-            const int m = ((q2 * k1) % R) * (16 / R);   // index into the 16th roots
-            const cplx w = cplx{kC16[m], sg * kS16[m]};
+            cplx w;
+            if constexpr (16 % R == 0) {
+                const int m = ((q2 * k1) % R) * (16 / R);   // index into the 16th roots
+                w = cplx{kC16[m], sg * kS16[m]};
+            } else {
+                static_assert(R == 10, "composite DFTs of 16 / 8 or 10 points");
+                const int m = (q2 * k1) % 10;
+                w = cplx{kC10[m], sg * kS10[m]};
+            }
             t[q2][k1] = cmul(t[q2][k1], w);
         }
     }
@@ -102,6 +119,8 @@ template <int R>
 __device__ __forceinline__ void small_dft(cplx* a, double sg) {
     if constexpr (R == 16) {
         composite_dft<4, 4>(a, sg);
+    } else if constexpr (R == 10) {
+        composite_dft<5, 2>(a, sg);
     } else if constexpr (R == 8) {
         composite_dft<4, 2>(a, sg);
     } else if constexpr (R == 2) {
@@ -534,8 +553,9 @@ __global__ void product_kernel(cplx* __restrict__ t, int n1, int n2) {
 // j % NS and stage (p2_twiddle_kernel), its powers formed in registers.
 
 // E = 8 points per thread (4 for N = 256): radix-8 stages, the last one of
-// radix 2 or 4 where N is not a power of 8.
-template <int N> constexpr int p2_threads() { return N == 256 ? 64 : N / 8; }
+// radix 2 or 4 where N is not a power of 8. N = 10000 (the high-resolution
+// GERLUMPH maps): 1000 threads of 10 points, four radix-10 stages.
+template <int N> constexpr int p2_threads() { return N == 256 ? 64 : (N == 10000 ? 1000 : N / 8); }
 template <int N> constexpr int p2_stages() {
     return N == 512 ? 3 : (N == 8192 ? 5 : 4);
 }
@@ -544,9 +564,13 @@ template <int N, int S> constexpr int p2_radix() {
          : N == 1024 ? (S < 3 ? 8 : 2)
          : N == 2048 ? (S < 3 ? 8 : 4)
          : N == 8192 ? (S < 4 ? 8 : 2)
+         : N == 10000 ? 10
          : 8;    // 512, 4096
 }
-template <int N> constexpr int p2_lds() { return N + N / 16; }
+// LDS row padding: one slot in 16, one in 64 for N = 10000 (so that the row
+// stays within the 160 KiB a workgroup may use).
+template <int N> __device__ __forceinline__ int p2_pad(int e) { return N == 10000 ? e + (e >> 6) : e + (e >> 4); }
+template <int N> constexpr int p2_lds() { return N == 10000 ? N + N / 64 + 1 : N + N / 16; }
 // NS of stage S (the product of the radices before it) and the offset of its
 // entries in the base-twiddle table: stage S holds exp(-2 pi i k / (NS R))
 // for k < NS at p2_tw_offset<N, S>() + k.
@@ -564,6 +588,7 @@ __device__ __forceinline__ void twiddle_powers(cplx w, cplx (&p)[R]) {
     if constexpr (R > 3) p[3] = cmul(p[2], w);
     if constexpr (R > 4) { p[4] = cmul(p[2], p[2]); p[5] = cmul(p[4], w); p[6] = cmul(p[3], p[3]);
                            p[7] = cmul(p[6], w); }
+    if constexpr (R > 8) { p[8] = cmul(p[4], p[4]); p[9] = cmul(p[5], p[4]); }
 }
 
 // Base twiddles of a power-of-two plan: entry e of stage s (offset off_s,
@@ -578,12 +603,11 @@ __global__ void p2_twiddle_kernel(cplx* __restrict__ tw, FftPlan P) {
     tw[e] = cplx{cs, -sn};
 }
 
-__device__ __forceinline__ int pad16(int e) { return e + (e >> 4); }
 
-template <int N, int S, int NS, int V>
-__device__ __forceinline__ void p2_fft(cplx (&a)[V][N / p2_threads<N>()], cplx* __restrict__ lds,
+template <int N, int S, int NS, int V, int T = p2_threads<N>()>
+__device__ __forceinline__ void p2_fft(cplx (&a)[V][N / T], cplx* __restrict__ lds,
                                        const cplx* __restrict__ tw, bool inverse) {
-    constexpr int T = p2_threads<N>(), E = N / T, R = p2_radix<N, S>(), B = E / R;
+    constexpr int E = N / T, R = p2_radix<N, S>(), B = E / R;
     constexpr bool kLast = NS * R == N;
     const double sg = inverse ? 1.0 : -1.0;
     const int t = threadIdx.x;
@@ -592,7 +616,7 @@ __device__ __forceinline__ void p2_fft(cplx (&a)[V][N / p2_threads<N>()], cplx* 
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int j = t + T * b;
-            const int k = j & (NS - 1);
+            const int k = (int)((unsigned)j % (unsigned)NS);
             cplx x[R];
 #pragma unroll
             for (int q = 0; q < R; ++q) x[q] = a[v][b + q * B];
@@ -611,17 +635,17 @@ __device__ __forceinline__ void p2_fft(cplx (&a)[V][N / p2_threads<N>()], cplx* 
             } else {
                 const int base = (j / NS) * NS * R + k;
 #pragma unroll
-                for (int q = 0; q < R; ++q) lds[pad16(base + q * NS)] = x[q];
+                for (int q = 0; q < R; ++q) lds[p2_pad<N>(base + q * NS)] = x[q];
             }
         }
         if constexpr (!kLast) {
             __syncthreads();
 #pragma unroll
-            for (int m = 0; m < E; ++m) a[v][m] = lds[pad16(t + T * m)];
+            for (int m = 0; m < E; ++m) a[v][m] = lds[p2_pad<N>(t + T * m)];
             __syncthreads();
         }
     }
-    if constexpr (!kLast) p2_fft<N, S + 1, NS * R, V>(a, lds, tw, inverse);
+    if constexpr (!kLast) p2_fft<N, S + 1, NS * R, V, T>(a, lds, tw, inverse);
 }
 
 // Bijective remap of a block id: blocks dispatched to the same XCD (block b
@@ -663,14 +687,14 @@ p2_rows_fwd_kernel(const int32_t* __restrict__ M, const double* __restrict__ K, 
         // unpack: X^(u) = (Z(u) + conj Z(-u)) / 2, Y^(u) = (Z(u) - conj Z(-u)) / 2i,
         // stored at once (the M^ and K^ pieces of a chunk meet in L2)
 #pragma unroll
-        for (int m = 0; m < E; ++m) lds[pad16(t + T * m)] = a[0][m];
+        for (int m = 0; m < E; ++m) lds[p2_pad<N>(t + T * m)] = a[0][m];
         __syncthreads();
 #pragma unroll
         for (int m = 0; m <= E / 2; ++m) {
             if (m == E / 2 && t != 0) continue;     // u = N / 2 belongs to thread 0
             const int u = t + T * m;
             const cplx zu = a[0][m];
-            const cplx zm = lds[pad16((N - u) & (N - 1))];
+            const cplx zm = lds[p2_pad<N>(u == 0 ? 0 : N - u)];
             cplx* __restrict__ o = A + (int64_t)v * p2 * (N / 2 + 1) +
                                    ((int64_t)(j0 / 8) * (N / 2 + 1) + u) * 8 + (j0 & 7);
             o[0] = cplx{0.5 * (zu.x + zm.x), 0.5 * (zu.y - zm.y)};
@@ -709,7 +733,7 @@ p2_cols_kernel(const cplx* __restrict__ A, int H, cplx* __restrict__ G, const cp
         const int i = t + T * m;
         a[0][m] = nt_load(&colm[(int64_t)(i >> 3) * H * 8 + (i & 7)]);
     }
-    p2_fft<N, 0, 1, 1>(a, lds, tw, false);
+    p2_fft<N, 0, 1, 1, T>(a, lds, tw, false);
     // keep K^'s loads after M^'s transform: hoisted, they would hold registers
     // through it
     __builtin_amdgcn_sched_barrier(0);
@@ -718,10 +742,10 @@ p2_cols_kernel(const cplx* __restrict__ A, int H, cplx* __restrict__ G, const cp
         const int i = t + T * m;
         b[0][m] = nt_load(&colk[(int64_t)(i >> 3) * H * 8 + (i & 7)]);
     }
-    p2_fft<N, 0, 1, 1>(b, lds, tw, false);
+    p2_fft<N, 0, 1, 1, T>(b, lds, tw, false);
 #pragma unroll
     for (int m = 0; m < E; ++m) a[0][m] = cmul(a[0][m], b[0][m]);
-    p2_fft<N, 0, 1, 1>(a, lds, tw, true);
+    p2_fft<N, 0, 1, 1, T>(a, lds, tw, true);
     // chunk (x2 / 4, u1) holds rows x2 .. x2 + 3 (four consecutive lanes)
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -757,7 +781,7 @@ p2_rows_inv_kernel(const cplx* __restrict__ G, int p2, double scale, double* __r
             a[1][m] = cplx{c2.x + c3.y, c3.x - c2.y};
         }
     }
-    p2_fft<N, 0, 1, 2>(a, lds, tw, true);
+    p2_fft<N, 0, 1, 2, T>(a, lds, tw, true);
     double* __restrict__ o = out + (int64_t)j0 * N;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -770,7 +794,10 @@ p2_rows_inv_kernel(const cplx* __restrict__ G, int p2, double scale, double* __r
     }
 }
 
-bool pow2_side(int n) { return n == 256 || n == 512 || n == 1024 || n == 2048 || n == 4096 || n == 8192; }
+// Sides of the three-pass path: powers of two from 256 to 8192, and 10000.
+bool pow2_side(int n) {
+    return n == 256 || n == 512 || n == 1024 || n == 2048 || n == 4096 || n == 8192 || n == 10000;
+}
 
 // The stage radices of a power-of-two side as an FftPlan (for the base
 // twiddle table: L[s] = NS of stage s).
@@ -797,7 +824,8 @@ FftPlan p2_plan_of(int n) {
         case 1024: return p2_plan<1024>();
         case 2048: return p2_plan<2048>();
         case 4096: return p2_plan<4096>();
-        default: return p2_plan<8192>();
+        case 8192: return p2_plan<8192>();
+        default: return p2_plan<10000>();
     }
 }
 
@@ -827,7 +855,8 @@ hipError_t p2_rows_fwd_any(int n, const int32_t* M, const double* K, int p2, cpl
         case 1024: return RL_CALL(1024);
         case 2048: return RL_CALL(2048);
         case 4096: return RL_CALL(4096);
-        default: return RL_CALL(8192);
+        case 8192: return RL_CALL(8192);
+        default: return RL_CALL(10000);
     }
 #undef RL_CALL
 }
@@ -839,7 +868,8 @@ hipError_t p2_cols_any(int n, const cplx* A, cplx* G, int H, const cplx* tw, hip
         case 1024: return RL_CALL(1024);
         case 2048: return RL_CALL(2048);
         case 4096: return RL_CALL(4096);
-        default: return RL_CALL(8192);
+        case 8192: return RL_CALL(8192);
+        default: return RL_CALL(10000);
     }
 #undef RL_CALL
 }
@@ -852,7 +882,8 @@ hipError_t p2_rows_inv_any(int n, const cplx* G, int p2, double scale, double* o
         case 1024: return RL_CALL(1024);
         case 2048: return RL_CALL(2048);
         case 4096: return RL_CALL(4096);
-        default: return RL_CALL(8192);
+        case 8192: return RL_CALL(8192);
+        default: return RL_CALL(10000);
     }
 #undef RL_CALL
 }

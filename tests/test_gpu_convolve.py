@@ -37,11 +37,13 @@ def test_source_kernel_matches_the_oracle(ctx, shape, radius, hole):
 
 # Powers of two, mixed radices (2, 3, 4, 5), odd sides, rows longer than 4096
 # (the 160 KiB LDS class) and columns longer than 5120 (the split pass); then
-# every side of the three-pass power-of-two path (256 .. 8192) along each axis.
+# every side of the three-pass path (256 .. 8192 and 10000) along each axis,
+# and the full 10000^2 map of the high-resolution GERLUMPH datasets.
 @pytest.mark.parametrize("p1,p2", [(2, 2), (16, 8), (64, 256), (1024, 512), (3, 5), (30, 12),
                                    (100, 250), (375, 81), (1000, 600), (6000, 16), (64, 6000),
-                                   (2048, 10), (256, 8192), (8192, 256), (512, 2048),
-                                   (4096, 1024), (2048, 4096), (256, 256)])
+                                   (2048, 10), (10240, 8), (256, 8192), (8192, 256), (512, 2048),
+                                   (4096, 1024), (2048, 4096), (256, 256), (10000, 256),
+                                   (256, 10000), (10000, 10000)])
 def test_convolution_matches_the_oracle(ctx, p1, p2):
     rng = np.random.default_rng(p1 + p2)
     spec = spec_of(p1, p2)
