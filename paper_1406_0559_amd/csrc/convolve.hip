@@ -754,34 +754,44 @@ p2_cols_kernel(const cplx* __restrict__ A, int H, cplx* __restrict__ G, const cp
     }
 }
 
-// Pass C. Block = rows j0 .. j0 + 3 of the output (p1 = N points along x1).
+// Output rows per workgroup of pass C: four (two complex transforms), two for
+// N = 10000, whose transforms alone fill the 128 registers of a lane.
+template <int N> constexpr int p2_inv_rows() { return N == 10000 ? 2 : 4; }
+
+// Pass C. Block = rows j0 .. j0 + RW - 1 of the output (p1 = N points along x1).
 template <int N>
 __global__ void __launch_bounds__(p2_threads<N>())
 __attribute__((amdgpu_waves_per_eu(N >= 2048 && N <= 4096 ? 4 : 1)))
 p2_rows_inv_kernel(const cplx* __restrict__ G, int p2, double scale, double* __restrict__ out,
                    const cplx* __restrict__ tw) {
-    constexpr int T = p2_threads<N>(), E = N / T, H = N / 2 + 1;
+    constexpr int T = p2_threads<N>(), E = N / T, H = N / 2 + 1, RW = p2_inv_rows<N>(), V = RW / 2;
     __shared__ cplx lds[p2_lds<N>()];
     const int t = threadIdx.x;
-    const int j0 = 4 * xcd_block(blockIdx.x, gridDim.x);
-    cplx a[2][E];
+    const int j0 = RW * xcd_block(blockIdx.x, gridDim.x);
+    cplx a[V][E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const int u = t + T * m;
         const bool mirror = u >= H;
         const int src = mirror ? N - u : u;
-        const cplx* __restrict__ c = G + ((int64_t)(j0 / 4) * H + src) * 4;
-        const cplx c0 = c[0], c1 = c[1], c2 = c[2], c3 = c[3];
+        // chunk (j0 / 4, src) holds rows 4 (j0 / 4) .. + 3
+        const cplx* __restrict__ c = G + ((int64_t)(j0 / 4) * H + src) * 4 + (j0 & 3);
         // g(x2) + i g(x2 + 1), or its value at -u: conj g(x2) + i conj g(x2 + 1)
-        if (!mirror) {
-            a[0][m] = cplx{c0.x - c1.y, c0.y + c1.x};
-            a[1][m] = cplx{c2.x - c3.y, c2.y + c3.x};
+        if constexpr (V == 2) {
+            const cplx c0 = c[0], c1 = c[1], c2 = c[2], c3 = c[3];
+            if (!mirror) {
+                a[0][m] = cplx{c0.x - c1.y, c0.y + c1.x};
+                a[V - 1][m] = cplx{c2.x - c3.y, c2.y + c3.x};
+            } else {
+                a[0][m] = cplx{c0.x + c1.y, c1.x - c0.y};
+                a[V - 1][m] = cplx{c2.x + c3.y, c3.x - c2.y};
+            }
         } else {
-            a[0][m] = cplx{c0.x + c1.y, c1.x - c0.y};
-            a[1][m] = cplx{c2.x + c3.y, c3.x - c2.y};
+            const cplx c0 = c[0], c1 = c[1];
+            a[0][m] = mirror ? cplx{c0.x + c1.y, c1.x - c0.y} : cplx{c0.x - c1.y, c0.y + c1.x};
         }
     }
-    p2_fft<N, 0, 1, 2, T>(a, lds, tw, true);
+    p2_fft<N, 0, 1, V, T>(a, lds, tw, true);
     double* __restrict__ o = out + (int64_t)j0 * N;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -789,8 +799,10 @@ p2_rows_inv_kernel(const cplx* __restrict__ G, int p2, double scale, double* __r
         // written once and not read back here: non-temporal
         __builtin_nontemporal_store(a[0][m].x * scale, &o[i]);
         __builtin_nontemporal_store(a[0][m].y * scale, &o[N + i]);
-        __builtin_nontemporal_store(a[1][m].x * scale, &o[2 * N + i]);
-        __builtin_nontemporal_store(a[1][m].y * scale, &o[3 * N + i]);
+        if constexpr (V == 2) {
+            __builtin_nontemporal_store(a[V - 1][m].x * scale, &o[2 * N + i]);
+            __builtin_nontemporal_store(a[V - 1][m].y * scale, &o[3 * N + i]);
+        }
     }
 }
 
@@ -841,7 +853,7 @@ hipError_t p2_cols(const cplx* A, cplx* G, int H, const cplx* tw, hipStream_t s)
 }
 template <int N>
 hipError_t p2_rows_inv(const cplx* G, int p2, double scale, double* out, const cplx* tw, hipStream_t s) {
-    hipLaunchKernelGGL(p2_rows_inv_kernel<N>, dim3(p2 / 4), dim3(p2_threads<N>()), 0, s, G, p2, scale,
+    hipLaunchKernelGGL(p2_rows_inv_kernel<N>, dim3(p2 / p2_inv_rows<N>()), dim3(p2_threads<N>()), 0, s, G, p2, scale,
                        out, tw);
     return hipGetLastError();
 }
