@@ -350,8 +350,12 @@ def main():
             cs, es = ctx.new_map(sp)
             best = None
             for k in range(3):
-                cs.zero_()
-                es.zero_()
+                # device time: the zeroing and a GPU sleep are queued ahead of
+                # the events, so the call's host work overlaps them
+                with torch.cuda.stream(stream):
+                    cs.zero_()
+                    es.zero_()
+                    torch.cuda._sleep(1000000)
                 a = torch.cuda.Event(enable_timing=True)
                 b = torch.cuda.Event(enable_timing=True)
                 a.record(stream)

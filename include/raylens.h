@@ -24,7 +24,9 @@
  *   - "d_" pointers are device pointers (HIP device memory of the context's
  *     device); "h_" pointers are host pointers. The caller owns every buffer;
  *     the library never frees caller memory. Only the context owns memory of
- *     its own (prepared lens copies, work lists, statistics scratch).
+ *     its own (prepared lens copies, work lists, FFT planes, and a pinned,
+ *     device-mapped host buffer into which the reductions behind the calls
+ *     that return host values store their partial results).
  *   - Work is enqueued on the given stream (NULL = the default stream) and is
  *     asynchronous unless stated otherwise. Buffers passed in must stay alive
  *     until the stream reaches that work.

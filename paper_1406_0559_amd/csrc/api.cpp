@@ -50,13 +50,12 @@ rl_status hip_fail(hipError_t e, const char* what) {
 
 bool is_finite(double v) { return std::isfinite(v); }
 
-// Folds the reduction slots copied back from the device (launch_count_stats,
-// launch_prob_sum): out[0] and out[2] sum words 0 and 2, out[1] is the
-// largest word 1.
-void fold_slots(const std::vector<unsigned long long>& h, unsigned long long out[3]) {
+// Folds the per-workgroup records of launch_count_stats / launch_prob_sum:
+// out[0] and out[2] sum words 0 and 2, out[1] is the largest word 1.
+void fold_records(const unsigned long long* rec, int nb, unsigned long long out[3]) {
     out[0] = out[1] = out[2] = 0;
-    for (int i = 0; i < rl::kRedSlots; ++i) {
-        const unsigned long long* w = h.data() + (size_t)i * rl::kSlotWords;
+    for (int i = 0; i < nb; ++i) {
+        const unsigned long long* w = rec + (size_t)i * rl::kRecWords;
         out[0] += w[0];
         out[1] = w[1] > out[1] ? w[1] : out[1];
         out[2] += w[2];
@@ -255,7 +254,6 @@ struct rl_context {
     int num_cus = 256;
     Scratch lens;        // FP32 lens copies
     Scratch batch;       // map records + work items + counter
-    Scratch stats;       // reduction outputs
     Scratch aux;         // MPD thresholds, codec tables, source samples
     Scratch fft;         // convolution planes
     // sides and scratch generation of the stage-twiddle tables the last
@@ -264,7 +262,10 @@ struct rl_context {
     uint64_t fft_tw_gen = 0;
     void* host_stage = nullptr;  // pinned staging for batch records
     size_t host_cap = 0;
-    void* host_read = nullptr;   // pinned landing buffer for small results read back (kReadBytes)
+    // pinned, device-mapped buffer of kReadBytes: the reductions' records are
+    // stored straight into it, and small copies back land in it
+    void* host_read = nullptr;
+    unsigned long long* host_read_dev = nullptr;   // its device address
     hipEvent_t stage_done = nullptr;
     bool stage_used = false;
     rl::KernelShape tuning[2][rl::kTuningClasses];
@@ -286,10 +287,26 @@ rl_status ensure_ready(rl_context* ctx) {
     ctx->num_cus = cus > 0 ? cus : 256;
     e = hipEventCreateWithFlags(&ctx->stage_done, hipEventDisableTiming);
     if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
-    e = hipHostMalloc(&ctx->host_read, kReadBytes, hipHostMallocDefault);
+    e = hipHostMalloc(&ctx->host_read, kReadBytes, hipHostMallocMapped | hipHostMallocCoherent);
     if (e != hipSuccess) { ctx->host_read = nullptr; return hip_fail(e, "pinned read-back buffer"); }
+    void* dev = nullptr;
+    e = hipHostGetDevicePointer(&dev, ctx->host_read, 0);
+    if (e != hipSuccess) {
+        (void)hipHostFree(ctx->host_read);
+        ctx->host_read = nullptr;
+        return hip_fail(e, "device address of the read-back buffer");
+    }
+    ctx->host_read_dev = static_cast<unsigned long long*>(dev);
     ctx->ready = true;
     return RL_OK;
+}
+
+// Waits for a reduction launched into ctx->host_read_dev and folds its `nb`
+// records (also returns the records, for words past them).
+hipError_t fold_reduction(rl_context* ctx, int nb, hipStream_t s, unsigned long long out[3]) {
+    const hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess) fold_records(static_cast<const unsigned long long*>(ctx->host_read), nb, out);
+    return e;
 }
 
 // Copies `bytes` of device results to host memory in stream order and waits
@@ -394,7 +411,6 @@ rl_status rl_destroy(rl_context* ctx) {
         (void)hipDeviceSynchronize();
         ctx->lens.destroy();
         ctx->batch.destroy();
-        ctx->stats.destroy();
         ctx->aux.destroy();
         ctx->fft.destroy();
         if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
@@ -608,22 +624,15 @@ rl_status rl_stats_get(rl_context* ctx, const int32_t* d_counts, const int64_t* 
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return hip_fail(dg.err, "hipSetDevice");
     RL_TRY(ensure_ready(ctx));
-    // the reduction slots, then the escaped count in one more word
-    const size_t words = rl::kRedBytes / sizeof(unsigned long long);
-    hipError_t e = ctx->stats.acquire(rl::kRedBytes + sizeof(unsigned long long), stream);
-    if (e != hipSuccess) return hip_fail(e, "stats scratch");
-    unsigned long long* acc = static_cast<unsigned long long*>(ctx->stats.ptr);
-    e = rl::launch_count_stats(d_counts, (int64_t)win->p1 * win->p2, acc, stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(acc + words, d_escaped, sizeof(int64_t), hipMemcpyDeviceToDevice, stream);
-    std::vector<unsigned long long> slots(words + 1, 0);
-    if (e == hipSuccess) e = read_back(ctx, slots.data(), acc, slots.size() * sizeof(unsigned long long), stream);
-    hipError_t e2 = ctx->stats.release(stream);
-    if (e == hipSuccess) e = e2;
-    if (e != hipSuccess) return hip_fail(e, "stats");
+    // the workgroups' records, then the escaped count in one more word, stored
+    // in the pinned buffer
+    const int64_t n = (int64_t)win->p1 * win->p2;
+    hipError_t e = rl::launch_count_stats(d_counts, n, reinterpret_cast<const unsigned long long*>(d_escaped),
+                                          ctx->host_read_dev, stream);
     unsigned long long host[4];
-    fold_slots(slots, host);
-    host[3] = slots[words];
+    if (e == hipSuccess) e = fold_reduction(ctx, rl::reduce_blocks(n), stream, host);
+    if (e != hipSuccess) return hip_fail(e, "stats");
+    host[3] = static_cast<const unsigned long long*>(ctx->host_read)[(size_t)rl::kRedBlocks * rl::kRecWords];
     double n_avg = 0.0;
     RL_TRY(rl_n_avg(grid, win, &n_avg));
     rl_stats st;
@@ -820,21 +829,31 @@ rl_status rl_mpd(rl_context* ctx, const int32_t* d_counts, const rl_window* win,
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return hip_fail(dg.err, "hipSetDevice");
     RL_TRY(ensure_ready(ctx));
-    // count thresholds of the log10(mu / mu_ref) bin edges, in FP64 on the host
+    // count thresholds of the log10(mu / mu_ref) bin edges, in FP64 on the
+    // host; up to kMpdArgThr of them go with the launch, more through scratch
     const int nthr = nbins + 1;
+    const double step = (log_hi - log_lo) / (double)nbins;
+    const double scale = n_avg * mu_ref;
+    auto threshold = [&](int k) { return scale * std::pow(10.0, log_lo + (double)k * step); };
+    const int64_t n = (int64_t)win->p1 * win->p2;
+    rl::MpdThresholds args{};
+    hipError_t e;
+    if (nthr <= rl::kMpdArgThr) {
+        for (int k = 0; k < nthr; ++k) args.t[k] = threshold(k);
+        e = rl::launch_mpd(d_counts, n, args, nullptr, nthr, reinterpret_cast<unsigned long long*>(d_bins),
+                           stream);
+        if (e != hipSuccess) return hip_fail(e, "mpd launch");
+        return RL_OK;
+    }
     const size_t bytes = (size_t)nthr * sizeof(double);
     char* hs = nullptr;
     RL_TRY(stage_reserve(ctx, bytes, &hs));
     double* thr = reinterpret_cast<double*>(hs);
-    const double step = (log_hi - log_lo) / (double)nbins;
-    const double scale = n_avg * mu_ref;
-    for (int k = 0; k < nthr; ++k) thr[k] = scale * std::pow(10.0, log_lo + (double)k * step);
-    const size_t thr_bytes = (bytes + 255) & ~(size_t)255;
-    hipError_t e = ctx->aux.acquire(thr_bytes + (size_t)rl::kMpdLut * sizeof(uint16_t), stream);
+    for (int k = 0; k < nthr; ++k) thr[k] = threshold(k);
+    e = ctx->aux.acquire(bytes, stream);
     if (e != hipSuccess) return hip_fail(e, "threshold scratch");
     RL_TRY(stage_send(ctx, ctx->aux.ptr, bytes, stream));
-    e = rl::launch_mpd(d_counts, (int64_t)win->p1 * win->p2, static_cast<const double*>(ctx->aux.ptr),
-                       nthr, reinterpret_cast<uint16_t*>(static_cast<char*>(ctx->aux.ptr) + thr_bytes),
+    e = rl::launch_mpd(d_counts, n, args, static_cast<const double*>(ctx->aux.ptr), nthr,
                        reinterpret_cast<unsigned long long*>(d_bins), stream);
     hipError_t e2 = ctx->aux.release(stream);
     if (e == hipSuccess) e = e2;
@@ -854,9 +873,6 @@ rl_status rl_probability_sums(rl_context* ctx, const int32_t* d_counts, const rl
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return hip_fail(dg.err, "hipSetDevice");
     RL_TRY(ensure_ready(ctx));
-    hipError_t e = ctx->stats.acquire(rl::kRedBytes, stream);
-    if (e != hipSuccess) return hip_fail(e, "stats scratch");
-    unsigned long long* acc = static_cast<unsigned long long*>(ctx->stats.ptr);
     const int64_t n = (int64_t)win->p1 * win->p2;
     // N / N_avg in FP64 is non-decreasing in the integer N (IEEE division by a
     // positive number is monotone), so "N / N_avg < mu_lim" holds exactly for
@@ -868,14 +884,10 @@ rl_status rl_probability_sums(rl_context* ctx, const int32_t* d_counts, const rl
         if ((double)mid / n_avg < mu_lim) lo = mid + 1;
         else hi = mid;
     }
-    e = rl::launch_prob_sum(d_counts, n, lo, acc, stream);
-    std::vector<unsigned long long> slots(rl::kRedBytes / sizeof(unsigned long long), 0);
-    if (e == hipSuccess) e = read_back(ctx, slots.data(), acc, rl::kRedBytes, stream);
-    hipError_t e2 = ctx->stats.release(stream);
-    if (e == hipSuccess) e = e2;
-    if (e != hipSuccess) return hip_fail(e, "probability sums");
+    hipError_t e = rl::launch_prob_sum(d_counts, n, lo, ctx->host_read_dev, stream);
     unsigned long long folded[3];
-    fold_slots(slots, folded);
+    if (e == hipSuccess) e = fold_reduction(ctx, rl::reduce_blocks(n), stream, folded);
+    if (e != hipSuccess) return hip_fail(e, "probability sums");
     const unsigned long long below = folded[0];
     *h_below = (int64_t)below;
     *h_above = n - (int64_t)below;
@@ -913,17 +925,10 @@ rl_status rl_codec_encode(rl_context* ctx, const int32_t* d_counts, const rl_win
     RL_TRY(ensure_ready(ctx));
     const int64_t n_pix = (int64_t)win->p1 * win->p2;
     // 1. largest count and negatives
-    hipError_t e = ctx->stats.acquire(rl::kRedBytes, stream);
-    if (e != hipSuccess) return hip_fail(e, "stats scratch");
-    unsigned long long* acc = static_cast<unsigned long long*>(ctx->stats.ptr);
-    e = rl::launch_count_stats(d_counts, n_pix, acc, stream);
-    std::vector<unsigned long long> slots(rl::kRedBytes / sizeof(unsigned long long), 0);
-    if (e == hipSuccess) e = read_back(ctx, slots.data(), acc, rl::kRedBytes, stream);
-    hipError_t e2 = ctx->stats.release(stream);
-    if (e == hipSuccess) e = e2;
-    if (e != hipSuccess) return hip_fail(e, "codec statistics");
+    hipError_t e = rl::launch_count_stats(d_counts, n_pix, nullptr, ctx->host_read_dev, stream);
     unsigned long long host[3];
-    fold_slots(slots, host);
+    if (e == hipSuccess) e = fold_reduction(ctx, rl::reduce_blocks(n_pix), stream, host);
+    if (e != hipSuccess) return hip_fail(e, "codec statistics");
     if (host[2]) return fail(RL_E_INVALID, "counts must be >= 0 (%llu negative)", host[2]);
     const int64_t n_values = (int64_t)host[1] + 1;
     // 2. histogram of values, distinct flags and their ranks
@@ -964,7 +969,7 @@ rl_status rl_codec_encode(rl_context* ctx, const int32_t* d_counts, const rl_win
     }
     // 3. index table and packed map
     e = rl::launch_codec_pack(d_counts, n_pix, flag, rank, n_values, bits, d_values, d_packed, stream);
-    e2 = ctx->aux.release(stream);
+    const hipError_t e2 = ctx->aux.release(stream);
     if (e == hipSuccess) e = e2;
     if (e != hipSuccess) return hip_fail(e, "codec pack");
     return RL_OK;

@@ -10,26 +10,33 @@ namespace rl {
 // Launchers; each returns the hipError_t of the launch.
 hipError_t launch_normalise(const int32_t* counts, int64_t n, double n_avg, float* mu,
                             hipStream_t stream);
-// Scalar reductions over a map (count statistics, probability sums) end in
-// one device-scope atomic per workgroup per word. The workgroups spread them
-// over kRedSlots slots, 128 bytes apart, which the host folds after copying
-// them back (fold_slots).
-constexpr int kRedSlots = 64;
-constexpr int kSlotWords = 16;   // u64 words per slot
-constexpr size_t kRedBytes = (size_t)kRedSlots * kSlotWords * sizeof(unsigned long long);
-// slots (kRedBytes of device memory, zeroed by the launcher): word 0 of a slot
-// sums the non-negative counts, word 1 is the largest count, word 2 counts the
-// negative ones
-hipError_t launch_count_stats(const int32_t* counts, int64_t n, unsigned long long* slots,
-                              hipStream_t stream);
+// Scalar reductions over a map (count statistics, probability sums): each
+// workgroup stores one record of kRecWords u64 words at out[kRecWords * b]
+// (no atomics, so nothing has to be zeroed first), reduce_blocks(n) records
+// in all, and the host folds them. `out` may be device-mapped pinned host
+// memory, so that the records need no copy before the host reads them.
+constexpr int kRedBlocks = 2048;
+constexpr int kRecWords = 4;
+constexpr size_t kRedBytes = (size_t)kRedBlocks * kRecWords * sizeof(unsigned long long);
+int reduce_blocks(int64_t n);
+// record: word 0 sums the non-negative counts, word 1 is the largest count,
+// word 2 counts the negative ones; with `escaped` non-null, workgroup 0 also
+// copies *escaped to out[kRedBlocks * kRecWords]
+hipError_t launch_count_stats(const int32_t* counts, int64_t n, const unsigned long long* escaped,
+                              unsigned long long* out, hipStream_t stream);
 hipError_t launch_count_hist(const int32_t* counts, int64_t n, int64_t n_values,
                              unsigned long long* hist, hipStream_t stream);
-// lut: device scratch of kMpdLut uint16 (the bin of every count below kMpdLut)
-hipError_t launch_mpd(const int32_t* counts, int64_t n, const double* thr, int nthr, uint16_t* lut,
-                      unsigned long long* bins, hipStream_t stream);
-// slots as for launch_count_stats; word 0 counts the pixels below t_below
+// Thresholds of at most kMpdArgThr entries travel as a kernel argument (no
+// copy ahead of the launch); longer lists are read from thr in device memory.
+constexpr int kMpdArgThr = 256;
+struct MpdThresholds {
+    double t[kMpdArgThr];
+};
+hipError_t launch_mpd(const int32_t* counts, int64_t n, const MpdThresholds& args, const double* thr,
+                      int nthr, unsigned long long* bins, hipStream_t stream);
+// record word 0 counts the pixels below t_below
 hipError_t launch_prob_sum(const int32_t* counts, int64_t n, int64_t t_below,
-                           unsigned long long* slots, hipStream_t s);
+                           unsigned long long* out, hipStream_t s);
 hipError_t launch_mpd_moments(const unsigned long long* bins, int n_maps, int n_bins, double n_pix,
                               double* mean, double* stdev, hipStream_t stream);
 

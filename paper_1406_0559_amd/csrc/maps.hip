@@ -13,7 +13,6 @@ namespace rl {
 namespace {
 
 constexpr int kInFlight = 4;   // 16-byte loads in flight per thread
-constexpr int kReduceBlocks = 2048;   // workgroups of the scalar reductions
 
 // Calls f(v) for every count of c[0 .. n) once, over the whole grid: 16-byte
 // vector loads for the aligned body, kInFlight of them in flight per thread
@@ -67,6 +66,7 @@ __global__ void normalise_kernel(const int32_t* __restrict__ counts, int64_t n, 
 
 __global__ void __launch_bounds__(256) count_stats_kernel(const int32_t* __restrict__ counts,
                                                           int64_t n,
+                                                          const unsigned long long* __restrict__ escaped,
                                                           unsigned long long* __restrict__ out) {
     __shared__ unsigned long long ssum[4];
     __shared__ unsigned long long sneg[4];
@@ -96,10 +96,11 @@ __global__ void __launch_bounds__(256) count_stats_kernel(const int32_t* __restr
             bn += sneg[i];
             bm = smax[i] > bm ? smax[i] : bm;
         }
-        unsigned long long* o = out + (blockIdx.x % kRedSlots) * kSlotWords;
-        atomicAdd(&o[0], bs);
-        atomicMax(&o[1], (unsigned long long)bm);
-        if (bn) atomicAdd(&o[2], bn);
+        unsigned long long* o = out + (int64_t)blockIdx.x * kRecWords;
+        o[0] = bs;
+        o[1] = (unsigned long long)bm;
+        o[2] = bn;
+        if (escaped && blockIdx.x == 0) out[(int64_t)kRedBlocks * kRecWords] = *escaped;
     }
 }
 
@@ -166,27 +167,25 @@ __device__ __forceinline__ int mpd_bin(const double* __restrict__ st, int nthr, 
     return lo;
 }
 
-// lut[v] = bin of the count v for v < kMpdLut: counts are integers, so the
-// decision for each value is taken once per call instead of once per pixel.
-__global__ void mpd_lut_kernel(const double* __restrict__ thr, int nthr, uint16_t* __restrict__ lut) {
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v < kMpdLut) lut[v] = (uint16_t)mpd_bin(thr, nthr, (double)v);
-}
-
-// Binned MPD. Thresholds, the value table and `reps` interleaved copies of the
+// Binned MPD. Thresholds, the value table (the bin of every count below
+// kMpdLut: counts are integers, so each value's decision is taken once per
+// workgroup instead of once per pixel) and `reps` interleaved copies of the
 // bins (as in count_hist_kernel) live in LDS; counts outside [0, kMpdLut) are
-// searched directly.
+// searched directly. The thresholds come from the kernel argument when there
+// are at most kMpdArgThr of them, else from thr.
 __global__ void __launch_bounds__(kHistThreads) mpd_kernel(const int32_t* __restrict__ counts, int64_t n,
-                                                  const double* __restrict__ thr, int nthr, int reps,
-                                                  const uint16_t* __restrict__ lut,
+                                                  MpdThresholds targ, const double* __restrict__ thr,
+                                                  int nthr, int reps,
                                                   unsigned long long* __restrict__ bins) {
     extern __shared__ __align__(16) char smem[];
     double* st = reinterpret_cast<double*>(smem);
     unsigned int* sb = reinterpret_cast<unsigned int*>(st + nthr);
     uint16_t* sl = reinterpret_cast<uint16_t*>(sb + (nthr + 1) * reps);
-    for (int e = threadIdx.x; e < nthr; e += blockDim.x) st[e] = thr[e];
+    const bool in_arg = nthr <= kMpdArgThr;
+    for (int e = threadIdx.x; e < nthr; e += blockDim.x) st[e] = in_arg ? targ.t[e] : thr[e];
     for (int e = threadIdx.x; e < (nthr + 1) * reps; e += blockDim.x) sb[e] = 0;
-    for (int e = threadIdx.x; e < kMpdLut; e += blockDim.x) sl[e] = lut[e];
+    __syncthreads();
+    for (int e = threadIdx.x; e < kMpdLut; e += blockDim.x) sl[e] = (uint16_t)mpd_bin(st, nthr, (double)e);
     __syncthreads();
     const int r = threadIdx.x & (reps - 1);
     grid_counts(counts, n, [&](int cv) {
@@ -217,7 +216,7 @@ __global__ void __launch_bounds__(256) prob_sum_kernel(const int32_t* __restrict
     if (threadIdx.x == 0) {
         unsigned long long t = 0;
         for (int i = 0; i < (int)(blockDim.x / kLanes); ++i) t += part[i];
-        atomicAdd(out + (blockIdx.x % kRedSlots) * kSlotWords, t);
+        out[(int64_t)blockIdx.x * kRecWords] = t;
     }
 }
 
@@ -480,12 +479,12 @@ hipError_t launch_normalise(const int32_t* counts, int64_t n, double n_avg, floa
     return hipGetLastError();
 }
 
-hipError_t launch_count_stats(const int32_t* counts, int64_t n, unsigned long long* slots,
-                              hipStream_t s) {
-    hipError_t e = launch_fill_u32(reinterpret_cast<unsigned int*>(slots), (int64_t)(kRedBytes / 4), 0u, s);
-    if (e != hipSuccess || n <= 0) return e;
-    hipLaunchKernelGGL(count_stats_kernel, dim3(grid_for(n, 256 * 16, kReduceBlocks)), dim3(256), 0, s,
-                       counts, n, slots);
+int reduce_blocks(int64_t n) { return grid_for(n, 256 * 16, kRedBlocks); }
+
+hipError_t launch_count_stats(const int32_t* counts, int64_t n, const unsigned long long* escaped,
+                              unsigned long long* out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(count_stats_kernel, dim3(reduce_blocks(n)), dim3(256), 0, s, counts, n, escaped, out);
     return hipGetLastError();
 }
 
@@ -499,10 +498,9 @@ hipError_t launch_count_hist(const int32_t* counts, int64_t n, int64_t n_values,
     return hipGetLastError();
 }
 
-hipError_t launch_mpd(const int32_t* counts, int64_t n, const double* thr, int nthr, uint16_t* lut,
-                      unsigned long long* bins, hipStream_t s) {
+hipError_t launch_mpd(const int32_t* counts, int64_t n, const MpdThresholds& args, const double* thr,
+                      int nthr, unsigned long long* bins, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(mpd_lut_kernel, dim3((kMpdLut + 255) / 256), dim3(256), 0, s, thr, nthr, lut);
     // the copies get what the thresholds and the table leave of 64 KiB, at most kHistLds words
     const int64_t fixed = (int64_t)nthr * (int64_t)sizeof(double) + (int64_t)kMpdLut * (int64_t)sizeof(uint16_t);
     const int64_t spare = (65536 - fixed) / (int64_t)sizeof(unsigned int);
@@ -510,16 +508,14 @@ hipError_t launch_mpd(const int32_t* counts, int64_t n, const double* thr, int n
     const size_t lds = (size_t)nthr * sizeof(double) + (size_t)(nthr + 1) * reps * sizeof(unsigned int) +
                        (size_t)kMpdLut * sizeof(uint16_t);
     hipLaunchKernelGGL(mpd_kernel, dim3(grid_for(n, kHistThreads * 16, kHistBlocks)), dim3(kHistThreads), lds, s,
-                       counts, n, thr, nthr, reps, lut, bins);
+                       counts, n, args, thr, nthr, reps, bins);
     return hipGetLastError();
 }
 
 hipError_t launch_prob_sum(const int32_t* counts, int64_t n, int64_t t_below,
-                           unsigned long long* slots, hipStream_t s) {
-    hipError_t e = launch_fill_u32(reinterpret_cast<unsigned int*>(slots), (int64_t)(kRedBytes / 4), 0u, s);
-    if (e != hipSuccess || n <= 0) return e;
-    hipLaunchKernelGGL(prob_sum_kernel, dim3(grid_for(n, 256 * 16, kReduceBlocks)), dim3(256), 0, s,
-                       counts, n, t_below, slots);
+                           unsigned long long* out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(prob_sum_kernel, dim3(reduce_blocks(n)), dim3(256), 0, s, counts, n, t_below, out);
     return hipGetLastError();
 }
 

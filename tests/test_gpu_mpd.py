@@ -33,7 +33,10 @@ def check_all(ctx, counts_np, spec, n_avg, mu_ref):
     for n_values in (nv, max(2, nv // 3), 1):
         h = ctx.count_histogram(counts, spec, n_values).cpu().numpy()
         assert (h == oracle.count_histogram(counts_np, n_values)).all()
-    for lo, hi, nb in ((-1.0, 1.0, 100), (-1.5, 1.5, 400), (0.0, 1.0, 1), (-3.0, 2.0, 4096)):
+    # 255 bins (256 thresholds) is the longest list that travels with the
+    # launch, 256 bins the shortest one read from device memory
+    for lo, hi, nb in ((-1.0, 1.0, 100), (-1.5, 1.5, 400), (0.0, 1.0, 1), (-3.0, 2.0, 4096),
+                       (-1.0, 1.0, 255), (-1.0, 1.0, 256)):
         b = ctx.mpd(counts, spec, mu_ref, lo, hi, nb, n_avg=n_avg).cpu().numpy()
         assert (b == oracle.mpd(counts_np, n_avg, mu_ref, lo, hi, nb)).all(), (lo, hi, nb)
     edge = 100.0 / n_avg          # the quotient of a count present in the maps
