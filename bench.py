@@ -245,6 +245,13 @@ def main():
         conv = torch.empty((spec.p2, spec.p1), dtype=torch.float64, device="cuda")
         t_kern = timed(lambda: ctx.source_kernel(spec, "gaussian", 0.2, kernel=kern, stream=stream))
         t_conv = timed(lambda: ctx.convolve(final, kern, spec, n_avg=n_avg, out=conv, stream=stream))
+        # the same call with a kernel that is nonzero on every row (no row pair
+        # of zeros whose transform can be skipped)
+        gd = torch.Generator(device="cuda").manual_seed(12)
+        dense = torch.rand((spec.p2, spec.p1), dtype=torch.float64, device="cuda", generator=gd)
+        dense /= dense.sum()
+        t_conv_dense = timed(lambda: ctx.convolve(final, dense, spec, n_avg=n_avg, out=conv, stream=stream))
+        del dense
         # the high-resolution GERLUMPH side: a seeded synthetic 10000^2 count map
         # (uniform in [0, 90)) and the same source on its 25 x 25 Einstein radii
         spec10 = dataclasses.replace(spec, p1=10000, p2=10000, name="synthetic-10000sq")
@@ -258,6 +265,7 @@ def main():
         post = {"pixels": n_pix,
                 "timing": "median device time per call: copies and kernels on the stream, host work hidden",
                 "source_kernel_us": t_kern * 1e3, "convolve_ms": t_conv, "convolve_10000sq_ms": t_conv10,
+                "convolve_dense_kernel_ms": t_conv_dense,
                 "convolve_min_GBps": gbs(20 * n_pix, t_conv),
                 "count_histogram_us": t_hist * 1e3, "count_histogram_GBps": gbs(4 * n_pix, t_hist),
                 "mpd_100bins_us": t_mpd * 1e3, "mpd_GBps": gbs(4 * n_pix, t_mpd),

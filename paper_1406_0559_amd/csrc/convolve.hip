@@ -666,8 +666,10 @@ p2_rows_fwd_kernel(const int32_t* __restrict__ M, const double* __restrict__ K, 
                    cplx* __restrict__ A, const cplx* __restrict__ tw) {
     constexpr int T = p2_threads<N>(), E = N / T;
     __shared__ cplx lds[p2_lds<N>()];
+    __shared__ int any_nz;     // the kernel's row pair holds a nonzero value
     const int t = threadIdx.x;
     const int j0 = 2 * xcd_block(blockIdx.x, gridDim.x);
+    if (t == 0) any_nz = 0;    // ordered before its use by the M pair's barriers
 #pragma unroll
     for (int v = 0; v < 2; ++v) {
         cplx a[1][E];
@@ -683,22 +685,42 @@ p2_rows_fwd_kernel(const int32_t* __restrict__ M, const double* __restrict__ K, 
                 a[0][m] = cplx{__builtin_nontemporal_load(&K[(int64_t)j0 * N + i]),
                                __builtin_nontemporal_load(&K[(int64_t)(j0 + 1) * N + i])};
         }
-        p2_fft<N, 0, 1, 1>(a, lds, tw, false);
-        // unpack: X^(u) = (Z(u) + conj Z(-u)) / 2, Y^(u) = (Z(u) - conj Z(-u)) / 2i,
-        // stored at once (the M^ and K^ pieces of a chunk meet in L2)
+        // A source profile is zero beyond its radius, so most row pairs of a
+        // kernel are zeros, whose half spectra are zeros: those are stored
+        // without a transform (the decision is the workgroup's, taken on the
+        // values it has loaded; a dense kernel costs one more barrier).
+        bool zero_pair = false;
+        if (v == 1) {
+            bool nz = false;
 #pragma unroll
-        for (int m = 0; m < E; ++m) lds[p2_pad<N>(t + T * m)] = a[0][m];
-        __syncthreads();
+            for (int m = 0; m < E; ++m) nz = nz || a[0][m].x != 0.0 || a[0][m].y != 0.0;
+            if (nz) any_nz = 1;
+            __syncthreads();
+            zero_pair = any_nz == 0;
+        }
+        if (!zero_pair) {
+            p2_fft<N, 0, 1, 1>(a, lds, tw, false);
+            // unpack: X^(u) = (Z(u) + conj Z(-u)) / 2, Y^(u) = (Z(u) - conj Z(-u)) / 2i,
+            // stored at once (the M^ and K^ pieces of a chunk meet in L2)
+#pragma unroll
+            for (int m = 0; m < E; ++m) lds[p2_pad<N>(t + T * m)] = a[0][m];
+            __syncthreads();
+        }
 #pragma unroll
         for (int m = 0; m <= E / 2; ++m) {
             if (m == E / 2 && t != 0) continue;     // u = N / 2 belongs to thread 0
             const int u = t + T * m;
-            const cplx zu = a[0][m];
-            const cplx zm = lds[p2_pad<N>(u == 0 ? 0 : N - u)];
             cplx* __restrict__ o = A + (int64_t)v * p2 * (N / 2 + 1) +
                                    ((int64_t)(j0 / 8) * (N / 2 + 1) + u) * 8 + (j0 & 7);
-            o[0] = cplx{0.5 * (zu.x + zm.x), 0.5 * (zu.y - zm.y)};
-            o[1] = cplx{0.5 * (zu.y + zm.y), 0.5 * (zm.x - zu.x)};
+            if (zero_pair) {
+                o[0] = cplx{0.0, 0.0};
+                o[1] = cplx{0.0, 0.0};
+            } else {
+                const cplx zu = a[0][m];
+                const cplx zm = lds[p2_pad<N>(u == 0 ? 0 : N - u)];
+                o[0] = cplx{0.5 * (zu.x + zm.x), 0.5 * (zu.y - zm.y)};
+                o[1] = cplx{0.5 * (zu.y + zm.y), 0.5 * (zm.x - zu.x)};
+            }
         }
         __syncthreads();
         // keep the K rows' loads after the M pair's stores

@@ -68,6 +68,27 @@ def test_delta_kernel_and_flux(ctx):
     assert abs(out.sum() - M.sum()) < 1e-9 * M.sum()
 
 
+@pytest.mark.parametrize("p1,p2", [(512, 256), (256, 8192), (10000, 256)])
+def test_kernels_with_zero_row_pairs(ctx, p1, p2):
+    """Kernels that are zero on most rows, as source profiles are beyond
+    their radius: nonzero rows alone, in pairs, straddling a pair boundary,
+    the last row, and negative zeros elsewhere; then an all-zero kernel."""
+    rng = np.random.default_rng(p1 * 7 + p2)
+    spec = spec_of(p1, p2)
+    M = rng.integers(0, 1000, size=(p2, p1)).astype(np.int32)
+    K = np.full((p2, p1), -0.0)
+    for r in (0, 1, 5, 6, 7, 64, p2 // 2 + 1, p2 - 2, p2 - 1):
+        K[r] = rng.random(p1) * (rng.random(p1) < 0.3)
+    K[3, p1 - 1] = 1e-300                      # a lone tiny value keeps its pair
+    K /= K.sum()
+    out = ctx.convolve(torch.from_numpy(M).cuda(), torch.from_numpy(K).cuda(), spec, n_avg=2.0)
+    ref = ocv.convolve(M, K, 2.0)
+    assert np.abs(out.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+    zero = np.zeros((p2, p1))
+    out = ctx.convolve(torch.from_numpy(M).cuda(), torch.from_numpy(zero).cuda(), spec, n_avg=2.0)
+    assert not out.cpu().numpy().any()
+
+
 def test_finite_source_map_of_the_full_size_workload(ctx):
     """The 4096^2 GERLUMPH-like map convolved with a Gaussian disc of radius
     0.2 Einstein radii (1e16 cm for R_Ein = 5e16 cm), as magnification."""
