@@ -604,6 +604,11 @@ __global__ void p2_twiddle_kernel(cplx* __restrict__ tw, FftPlan P) {
 }
 
 
+// kz[0 .. n) = 0: no pair of K^ rows is known to hold zeros.
+__global__ void p2_clear_kernel(uint8_t* __restrict__ kz, int n) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) kz[e] = 0;
+}
+
 template <int N, int S, int NS, int V, int T = p2_threads<N>()>
 __device__ __forceinline__ void p2_fft(cplx (&a)[V][N / T], cplx* __restrict__ lds,
                                        const cplx* __restrict__ tw, bool inverse) {
@@ -663,7 +668,7 @@ template <int N>
 __global__ void __launch_bounds__(p2_threads<N>())
 __attribute__((amdgpu_waves_per_eu(N >= 2048 && N <= 4096 ? 4 : 1)))
 p2_rows_fwd_kernel(const int32_t* __restrict__ M, const double* __restrict__ K, int p2,
-                   cplx* __restrict__ A, const cplx* __restrict__ tw) {
+                   cplx* __restrict__ A, const cplx* __restrict__ tw, uint8_t* __restrict__ kz) {
     constexpr int T = p2_threads<N>(), E = N / T;
     __shared__ cplx lds[p2_lds<N>()];
     __shared__ int any_nz;     // the kernel's row pair holds a nonzero value
@@ -687,16 +692,21 @@ p2_rows_fwd_kernel(const int32_t* __restrict__ M, const double* __restrict__ K, 
         }
         // A source profile is zero beyond its radius, so most row pairs of a
         // kernel are zeros, whose half spectra are zeros: those are stored
-        // without a transform (the decision is the workgroup's, taken on the
-        // values it has loaded; a dense kernel costs one more barrier).
-        bool zero_pair = false;
+        // without a transform, and not stored at all when kz says that this
+        // pair's rows of K^ already hold zeros from the previous call with the
+        // same sides (the decision is the workgroup's, taken on the values it
+        // has loaded; a dense kernel costs one more barrier).
+        bool zero_pair = false, skip = false;
         if (v == 1) {
             bool nz = false;
 #pragma unroll
             for (int m = 0; m < E; ++m) nz = nz || a[0][m].x != 0.0 || a[0][m].y != 0.0;
             if (nz) any_nz = 1;
+            const bool was_zero = kz[j0 >> 1] != 0;   // read by all before thread 0 rewrites it
             __syncthreads();
             zero_pair = any_nz == 0;
+            skip = zero_pair && was_zero;
+            if (t == 0 && zero_pair != was_zero) kz[j0 >> 1] = zero_pair ? 1 : 0;
         }
         if (!zero_pair) {
             p2_fft<N, 0, 1, 1>(a, lds, tw, false);
@@ -708,7 +718,7 @@ p2_rows_fwd_kernel(const int32_t* __restrict__ M, const double* __restrict__ K, 
         }
 #pragma unroll
         for (int m = 0; m <= E / 2; ++m) {
-            if (m == E / 2 && t != 0) continue;     // u = N / 2 belongs to thread 0
+            if (skip || (m == E / 2 && t != 0)) continue;     // u = N / 2 belongs to thread 0
             const int u = t + T * m;
             cplx* __restrict__ o = A + (int64_t)v * p2 * (N / 2 + 1) +
                                    ((int64_t)(j0 / 8) * (N / 2 + 1) + u) * 8 + (j0 & 7);
@@ -864,8 +874,9 @@ FftPlan p2_plan_of(int n) {
 }
 
 template <int N>
-hipError_t p2_rows_fwd(const int32_t* M, const double* K, int p2, cplx* A, const cplx* tw, hipStream_t s) {
-    hipLaunchKernelGGL(p2_rows_fwd_kernel<N>, dim3(p2 / 2), dim3(p2_threads<N>()), 0, s, M, K, p2, A, tw);
+hipError_t p2_rows_fwd(const int32_t* M, const double* K, int p2, cplx* A, const cplx* tw, uint8_t* kz,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(p2_rows_fwd_kernel<N>, dim3(p2 / 2), dim3(p2_threads<N>()), 0, s, M, K, p2, A, tw, kz);
     return hipGetLastError();
 }
 template <int N>
@@ -881,8 +892,8 @@ hipError_t p2_rows_inv(const cplx* G, int p2, double scale, double* out, const c
 }
 
 hipError_t p2_rows_fwd_any(int n, const int32_t* M, const double* K, int p2, cplx* A, const cplx* tw,
-                           hipStream_t s) {
-#define RL_CALL(N) p2_rows_fwd<N>(M, K, p2, A, tw, s)
+                           uint8_t* kz, hipStream_t s) {
+#define RL_CALL(N) p2_rows_fwd<N>(M, K, p2, A, tw, kz, s)
     switch (n) {
         case 256: return RL_CALL(256);
         case 512: return RL_CALL(512);
@@ -924,7 +935,7 @@ hipError_t p2_rows_inv_any(int n, const cplx* G, int p2, double scale, double* o
 
 size_t p2_scratch_bytes(int p1, int p2) {
     const size_t h = (size_t)(p1 / 2 + 1) * p2;
-    return h * 3 * sizeof(cplx) + (size_t)(p1 + p2) * sizeof(cplx) + 256;
+    return h * 3 * sizeof(cplx) + (size_t)(p1 + p2) * sizeof(cplx) + (size_t)p2 + 256;
 }
 
 hipError_t p2_convolve(const int32_t* counts, const double* kernel, int p1, int p2, double n_avg,
@@ -934,13 +945,17 @@ hipError_t p2_convolve(const int32_t* counts, const double* kernel, int p1, int 
     cplx* G = A + (size_t)H * p2 * 2;                      // p2 / 4 x H x {4 rows}
     cplx* tw1 = G + (size_t)H * p2;                        // stage twiddles along x1
     cplx* tw2 = tw1 + p1;                                  // ... along x2
+    // p2 / 2 flags: the pair's rows of K^ hold zeros (kept with the twiddles:
+    // valid while the sides and the scratch buffer stay the same)
+    uint8_t* kz = reinterpret_cast<uint8_t*>(tw2 + p2);
     if (!twiddles_ready) {
         const FftPlan P1 = p2_plan_of(p1), P2 = p2_plan_of(p2);
         hipLaunchKernelGGL(p2_twiddle_kernel, dim3((p1 + 255) / 256), dim3(256), 0, s, tw1, P1);
         hipLaunchKernelGGL(p2_twiddle_kernel, dim3((p2 + 255) / 256), dim3(256), 0, s, tw2, P2);
+        hipLaunchKernelGGL(p2_clear_kernel, dim3((p2 / 2 + 255) / 256), dim3(256), 0, s, kz, p2 / 2);
     }
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = p2_rows_fwd_any(p1, counts, kernel, p2, A, tw1, s);
+    if (e == hipSuccess) e = p2_rows_fwd_any(p1, counts, kernel, p2, A, tw1, kz, s);
     if (e == hipSuccess) e = p2_cols_any(p2, A, G, H, tw2, s);
     if (e == hipSuccess)
         e = p2_rows_inv_any(p1, G, p2, 1.0 / ((double)p1 * (double)p2 * n_avg), out, tw1, s);

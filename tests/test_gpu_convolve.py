@@ -89,6 +89,48 @@ def test_kernels_with_zero_row_pairs(ctx, p1, p2):
     assert not out.cpu().numpy().any()
 
 
+def test_kernel_support_changing_between_calls():
+    """Pass A leaves rows of the kernel's spectrum that are known to hold
+    zeros from the previous call alone: a fresh context convolves with
+    kernels whose nonzero rows move from call to call (and an all-zero, a
+    dense kernel, and a call with other sides in between, which resets what
+    is known), every result against the oracle."""
+    c = rl.Context(0)
+    try:
+        rng = np.random.default_rng(23)
+        p1, p2 = 512, 256
+
+        def kernel(rows):
+            K = np.zeros((p2, p1))
+            for r in rows:
+                K[r] = rng.random(p1)
+            return K / K.sum() if K.any() else K
+
+        dense = rng.random((p2, p1))
+        dense /= dense.sum()
+        seq = [kernel((0, 1, 2)), kernel((100, 101, 150)), kernel((0, 1, 2)), np.zeros((p2, p1)),
+               kernel((0, p2 - 1)), "other", kernel((100, 101, 150)), dense, kernel((7,)),
+               kernel((0, 1, 2))]
+        spec = spec_of(p1, p2)
+        for K in seq:
+            if isinstance(K, str):
+                spec_o = spec_of(256, 512)
+                Mo = rng.integers(0, 900, size=(512, 256)).astype(np.int32)
+                Ko = rng.random((512, 256))
+                Ko /= Ko.sum()
+                out = c.convolve(torch.from_numpy(Mo).cuda(), torch.from_numpy(Ko).cuda(), spec_o, n_avg=2.0)
+                ref = ocv.convolve(Mo, Ko, 2.0)
+                assert np.abs(out.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+                continue
+            M = rng.integers(0, 900, size=(p2, p1)).astype(np.int32)
+            out = c.convolve(torch.from_numpy(M).cuda(), torch.from_numpy(K).cuda(), spec, n_avg=2.0)
+            ref = ocv.convolve(M, K, 2.0)
+            tol = 1e-12 * max(np.abs(ref).max(), 1.0)
+            assert np.abs(out.cpu().numpy() - ref).max() <= tol
+    finally:
+        c.close()
+
+
 def test_finite_source_map_of_the_full_size_workload(ctx):
     """The 4096^2 GERLUMPH-like map convolved with a Gaussian disc of radius
     0.2 Einstein radii (1e16 cm for R_Ein = 5e16 cm), as magnification."""
