@@ -668,7 +668,8 @@ template <int N>
 __global__ void __launch_bounds__(p2_threads<N>())
 __attribute__((amdgpu_waves_per_eu(N >= 2048 && N <= 4096 ? 4 : 1)))
 p2_rows_fwd_kernel(const int32_t* __restrict__ M, const double* __restrict__ K, int p2,
-                   cplx* __restrict__ A, const cplx* __restrict__ tw, uint8_t* __restrict__ kz) {
+                   cplx* __restrict__ A, const cplx* __restrict__ tw, uint8_t* __restrict__ kz,
+                   int32_t* __restrict__ kseg, cplx* __restrict__ kzero) {
     constexpr int T = p2_threads<N>(), E = N / T;
     __shared__ cplx lds[p2_lds<N>()];
     __shared__ int any_nz;     // the kernel's row pair holds a nonzero value
@@ -707,6 +708,10 @@ p2_rows_fwd_kernel(const int32_t* __restrict__ M, const double* __restrict__ K, 
             zero_pair = any_nz == 0;
             skip = zero_pair && was_zero;
             if (t == 0 && zero_pair != was_zero) kz[j0 >> 1] = zero_pair ? 1 : 0;
+            // a pair that is not all zeros marks its 64-row segment: pass B
+            // reads K^ only in marked segments, and pass C clears the marks
+            if (t == 0 && !zero_pair) kseg[j0 >> 6] = 1;
+            if (t == 0 && blockIdx.x == 0) *kzero = cplx{0.0, 0.0};
         }
         if (!zero_pair) {
             p2_fft<N, 0, 1, 1>(a, lds, tw, false);
@@ -751,7 +756,8 @@ __device__ __forceinline__ cplx nt_load(const cplx* p) {
 template <int N>
 __global__ void __launch_bounds__(p2_threads<N>())
 __attribute__((amdgpu_waves_per_eu(N >= 2048 && N <= 4096 ? 4 : 1)))
-p2_cols_kernel(const cplx* __restrict__ A, int H, cplx* __restrict__ G, const cplx* __restrict__ tw) {
+p2_cols_kernel(const cplx* __restrict__ A, int H, cplx* __restrict__ G, const cplx* __restrict__ tw,
+               const int32_t* __restrict__ kseg, const cplx* __restrict__ kzero) {
     constexpr int T = p2_threads<N>(), E = N / T;
     __shared__ cplx lds[p2_lds<N>()];
     const int t = threadIdx.x;
@@ -769,10 +775,22 @@ p2_cols_kernel(const cplx* __restrict__ A, int H, cplx* __restrict__ G, const cp
     // keep K^'s loads after M^'s transform: hoisted, they would hold registers
     // through it
     __builtin_amdgcn_sched_barrier(0);
+    // Rows of K^ in 64-row segments that pass A did not mark are zeros: the
+    // wave reads them from the one zero that pass A stores (a cached line,
+    // no HBM traffic). The wave's 64 rows lie in at most two segments, so
+    // the test is wave-uniform; the loads stay unconditional, with base and
+    // offset switched by a select and a mask (loads under a branch here gave
+    // wrong results on 8192-point columns).
+    const int w0 = __builtin_amdgcn_readfirstlane(t & ~63);
 #pragma unroll
     for (int m = 0; m < E; ++m) {
         const int i = t + T * m;
-        b[0][m] = nt_load(&colk[(int64_t)(i >> 3) * H * 8 + (i & 7)]);
+        const int r0 = w0 + T * m;
+        const int32_t need = kseg[r0 >> 6] | kseg[(r0 + 63) >> 6];
+        const int64_t mask = need != 0 ? -1 : 0;
+        const cplx* base = need != 0 ? colk : kzero;
+        const int64_t off = ((int64_t)(i >> 3) * H * 8 + (i & 7)) & mask;
+        b[0][m] = nt_load(base + off);
     }
     p2_fft<N, 0, 1, 1, T>(b, lds, tw, false);
 #pragma unroll
@@ -795,10 +813,13 @@ template <int N>
 __global__ void __launch_bounds__(p2_threads<N>())
 __attribute__((amdgpu_waves_per_eu(N >= 2048 && N <= 4096 ? 4 : 1)))
 p2_rows_inv_kernel(const cplx* __restrict__ G, int p2, double scale, double* __restrict__ out,
-                   const cplx* __restrict__ tw) {
+                   const cplx* __restrict__ tw, int32_t* __restrict__ kseg) {
     constexpr int T = p2_threads<N>(), E = N / T, H = N / 2 + 1, RW = p2_inv_rows<N>(), V = RW / 2;
     __shared__ cplx lds[p2_lds<N>()];
     const int t = threadIdx.x;
+    // pass B has read the segment marks: cleared for the next call's pass A
+    if (blockIdx.x == 0)
+        for (int e = t; e < p2 / 64 + 2; e += T) kseg[e] = 0;
     const int j0 = RW * xcd_block(blockIdx.x, gridDim.x);
     cplx a[V][E];
 #pragma unroll
@@ -875,25 +896,28 @@ FftPlan p2_plan_of(int n) {
 
 template <int N>
 hipError_t p2_rows_fwd(const int32_t* M, const double* K, int p2, cplx* A, const cplx* tw, uint8_t* kz,
+                       int32_t* kseg, cplx* kzero, hipStream_t s) {
+    hipLaunchKernelGGL(p2_rows_fwd_kernel<N>, dim3(p2 / 2), dim3(p2_threads<N>()), 0, s, M, K, p2, A, tw, kz, kseg,
+                       kzero);
+    return hipGetLastError();
+}
+template <int N>
+hipError_t p2_cols(const cplx* A, cplx* G, int H, const cplx* tw, const int32_t* kseg, const cplx* kzero,
+                   hipStream_t s) {
+    hipLaunchKernelGGL(p2_cols_kernel<N>, dim3(H), dim3(p2_threads<N>()), 0, s, A, H, G, tw, kseg, kzero);
+    return hipGetLastError();
+}
+template <int N>
+hipError_t p2_rows_inv(const cplx* G, int p2, double scale, double* out, const cplx* tw, int32_t* kseg,
                        hipStream_t s) {
-    hipLaunchKernelGGL(p2_rows_fwd_kernel<N>, dim3(p2 / 2), dim3(p2_threads<N>()), 0, s, M, K, p2, A, tw, kz);
-    return hipGetLastError();
-}
-template <int N>
-hipError_t p2_cols(const cplx* A, cplx* G, int H, const cplx* tw, hipStream_t s) {
-    hipLaunchKernelGGL(p2_cols_kernel<N>, dim3(H), dim3(p2_threads<N>()), 0, s, A, H, G, tw);
-    return hipGetLastError();
-}
-template <int N>
-hipError_t p2_rows_inv(const cplx* G, int p2, double scale, double* out, const cplx* tw, hipStream_t s) {
     hipLaunchKernelGGL(p2_rows_inv_kernel<N>, dim3(p2 / p2_inv_rows<N>()), dim3(p2_threads<N>()), 0, s, G, p2, scale,
-                       out, tw);
+                       out, tw, kseg);
     return hipGetLastError();
 }
 
 hipError_t p2_rows_fwd_any(int n, const int32_t* M, const double* K, int p2, cplx* A, const cplx* tw,
-                           uint8_t* kz, hipStream_t s) {
-#define RL_CALL(N) p2_rows_fwd<N>(M, K, p2, A, tw, kz, s)
+                           uint8_t* kz, int32_t* kseg, cplx* kzero, hipStream_t s) {
+#define RL_CALL(N) p2_rows_fwd<N>(M, K, p2, A, tw, kz, kseg, kzero, s)
     switch (n) {
         case 256: return RL_CALL(256);
         case 512: return RL_CALL(512);
@@ -905,8 +929,9 @@ hipError_t p2_rows_fwd_any(int n, const int32_t* M, const double* K, int p2, cpl
     }
 #undef RL_CALL
 }
-hipError_t p2_cols_any(int n, const cplx* A, cplx* G, int H, const cplx* tw, hipStream_t s) {
-#define RL_CALL(N) p2_cols<N>(A, G, H, tw, s)
+hipError_t p2_cols_any(int n, const cplx* A, cplx* G, int H, const cplx* tw, const int32_t* kseg,
+                       const cplx* kzero, hipStream_t s) {
+#define RL_CALL(N) p2_cols<N>(A, G, H, tw, kseg, kzero, s)
     switch (n) {
         case 256: return RL_CALL(256);
         case 512: return RL_CALL(512);
@@ -919,8 +944,8 @@ hipError_t p2_cols_any(int n, const cplx* A, cplx* G, int H, const cplx* tw, hip
 #undef RL_CALL
 }
 hipError_t p2_rows_inv_any(int n, const cplx* G, int p2, double scale, double* out, const cplx* tw,
-                           hipStream_t s) {
-#define RL_CALL(N) p2_rows_inv<N>(G, p2, scale, out, tw, s)
+                           int32_t* kseg, hipStream_t s) {
+#define RL_CALL(N) p2_rows_inv<N>(G, p2, scale, out, tw, kseg, s)
     switch (n) {
         case 256: return RL_CALL(256);
         case 512: return RL_CALL(512);
@@ -935,7 +960,10 @@ hipError_t p2_rows_inv_any(int n, const cplx* G, int p2, double scale, double* o
 
 size_t p2_scratch_bytes(int p1, int p2) {
     const size_t h = (size_t)(p1 / 2 + 1) * p2;
-    return h * 3 * sizeof(cplx) + (size_t)(p1 + p2) * sizeof(cplx) + (size_t)p2 + 256;
+    // planes A (two) and G, the twiddles, one zero, the pair flags (16-byte
+    // padded) and the segment marks
+    return h * 3 * sizeof(cplx) + (size_t)(p1 + p2 + 1) * sizeof(cplx) + (size_t)(p2 + 15) / 16 * 16 +
+           (size_t)(p2 / 64 + 2) * sizeof(int32_t) + 256;
 }
 
 hipError_t p2_convolve(const int32_t* counts, const double* kernel, int p1, int p2, double n_avg,
@@ -945,9 +973,13 @@ hipError_t p2_convolve(const int32_t* counts, const double* kernel, int p1, int 
     cplx* G = A + (size_t)H * p2 * 2;                      // p2 / 4 x H x {4 rows}
     cplx* tw1 = G + (size_t)H * p2;                        // stage twiddles along x1
     cplx* tw2 = tw1 + p1;                                  // ... along x2
+    cplx* kzero = tw2 + p2;                                // one zero for pass B
     // p2 / 2 flags: the pair's rows of K^ hold zeros (kept with the twiddles:
     // valid while the sides and the scratch buffer stay the same)
-    uint8_t* kz = reinterpret_cast<uint8_t*>(tw2 + p2);
+    uint8_t* kz = reinterpret_cast<uint8_t*>(kzero + 1);
+    // p2 / 64 + 2 segment marks (room for pass B's last wave to look one
+    // segment past the end)
+    int32_t* kseg = reinterpret_cast<int32_t*>(kz + ((p2 + 15) / 16) * 16);
     if (!twiddles_ready) {
         const FftPlan P1 = p2_plan_of(p1), P2 = p2_plan_of(p2);
         hipLaunchKernelGGL(p2_twiddle_kernel, dim3((p1 + 255) / 256), dim3(256), 0, s, tw1, P1);
@@ -955,10 +987,10 @@ hipError_t p2_convolve(const int32_t* counts, const double* kernel, int p1, int 
         hipLaunchKernelGGL(p2_clear_kernel, dim3((p2 / 2 + 255) / 256), dim3(256), 0, s, kz, p2 / 2);
     }
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = p2_rows_fwd_any(p1, counts, kernel, p2, A, tw1, kz, s);
-    if (e == hipSuccess) e = p2_cols_any(p2, A, G, H, tw2, s);
+    if (e == hipSuccess) e = p2_rows_fwd_any(p1, counts, kernel, p2, A, tw1, kz, kseg, kzero, s);
+    if (e == hipSuccess) e = p2_cols_any(p2, A, G, H, tw2, kseg, kzero, s);
     if (e == hipSuccess)
-        e = p2_rows_inv_any(p1, G, p2, 1.0 / ((double)p1 * (double)p2 * n_avg), out, tw1, s);
+        e = p2_rows_inv_any(p1, G, p2, 1.0 / ((double)p1 * (double)p2 * n_avg), out, tw1, kseg, s);
     return e;
 }
 
