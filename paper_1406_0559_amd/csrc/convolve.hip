@@ -609,11 +609,15 @@ __global__ void p2_clear_kernel(uint8_t* __restrict__ kz, int n) {
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) kz[e] = 0;
 }
 
-template <int N, int S, int NS, int V, int T = p2_threads<N>()>
+// SPLIT: the stages exchange real and imaginary parts one after the other
+// through an LDS row of doubles (half the LDS of a complex row, for one
+// butterfly per thread and stage).
+template <int N, int S, int NS, int V, int T = p2_threads<N>(), bool SPLIT = false>
 __device__ __forceinline__ void p2_fft(cplx (&a)[V][N / T], cplx* __restrict__ lds,
                                        const cplx* __restrict__ tw, bool inverse) {
     constexpr int E = N / T, R = p2_radix<N, S>(), B = E / R;
     constexpr bool kLast = NS * R == N;
+    static_assert(!SPLIT || (B == 1 && V == 1), "the split exchange takes one butterfly per thread");
     const double sg = inverse ? 1.0 : -1.0;
     const int t = threadIdx.x;
 #pragma unroll
@@ -637,20 +641,35 @@ __device__ __forceinline__ void p2_fft(cplx (&a)[V][N / T], cplx* __restrict__ l
             if constexpr (kLast) {
 #pragma unroll
                 for (int q = 0; q < R; ++q) a[v][b + q * B] = x[q];
+            } else if constexpr (SPLIT) {
+                double* __restrict__ ld = reinterpret_cast<double*>(lds);
+                const int base = (j / NS) * NS * R + k;
+#pragma unroll
+                for (int q = 0; q < R; ++q) ld[p2_pad<N>(base + q * NS)] = x[q].x;
+                __syncthreads();
+#pragma unroll
+                for (int m = 0; m < E; ++m) a[v][m].x = ld[p2_pad<N>(t + T * m)];
+                __syncthreads();
+#pragma unroll
+                for (int q = 0; q < R; ++q) ld[p2_pad<N>(base + q * NS)] = x[q].y;
+                __syncthreads();
+#pragma unroll
+                for (int m = 0; m < E; ++m) a[v][m].y = ld[p2_pad<N>(t + T * m)];
+                __syncthreads();
             } else {
                 const int base = (j / NS) * NS * R + k;
 #pragma unroll
                 for (int q = 0; q < R; ++q) lds[p2_pad<N>(base + q * NS)] = x[q];
             }
         }
-        if constexpr (!kLast) {
+        if constexpr (!kLast && !SPLIT) {
             __syncthreads();
 #pragma unroll
             for (int m = 0; m < E; ++m) a[v][m] = lds[p2_pad<N>(t + T * m)];
             __syncthreads();
         }
     }
-    if constexpr (!kLast) p2_fft<N, S + 1, NS * R, V, T>(a, lds, tw, inverse);
+    if constexpr (!kLast) p2_fft<N, S + 1, NS * R, V, T, SPLIT>(a, lds, tw, inverse);
 }
 
 // Bijective remap of a block id: blocks dispatched to the same XCD (block b
@@ -759,7 +778,14 @@ __attribute__((amdgpu_waves_per_eu(N >= 2048 && N <= 4096 ? 4 : 1)))
 p2_cols_kernel(const cplx* __restrict__ A, int H, cplx* __restrict__ G, const cplx* __restrict__ tw,
                const int32_t* __restrict__ kseg, const cplx* __restrict__ kzero) {
     constexpr int T = p2_threads<N>(), E = N / T;
-    __shared__ cplx lds[p2_lds<N>()];
+    // 10000-point columns: the transforms exchange through a row of doubles,
+    // and the real parts of M^'s transform wait in the other half of LDS
+    // while K^'s is formed, so that the two do not share the 128 registers
+    // of a lane (they spilled 236 bytes per lane)
+    constexpr bool kSplit = N == 10000;
+    constexpr int kLdsCplx = kSplit ? (p2_lds<N>() + N + 1) / 2 : p2_lds<N>();
+    __shared__ cplx lds[kLdsCplx];
+    double* __restrict__ park = reinterpret_cast<double*>(lds) + p2_lds<N>();
     const int t = threadIdx.x;
     const int u1 = xcd_block(blockIdx.x, gridDim.x);
     // chunk (x2 / 8, u1) of the M^ plane, then of the K^ plane, row x2 % 8
@@ -771,7 +797,11 @@ p2_cols_kernel(const cplx* __restrict__ A, int H, cplx* __restrict__ G, const cp
         const int i = t + T * m;
         a[0][m] = nt_load(&colm[(int64_t)(i >> 3) * H * 8 + (i & 7)]);
     }
-    p2_fft<N, 0, 1, 1, T>(a, lds, tw, false);
+    p2_fft<N, 0, 1, 1, T, kSplit>(a, lds, tw, false);
+    if constexpr (kSplit) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) park[t + T * m] = a[0][m].x;   // read back by this thread
+    }
     // keep K^'s loads after M^'s transform: hoisted, they would hold registers
     // through it
     __builtin_amdgcn_sched_barrier(0);
@@ -782,9 +812,14 @@ p2_cols_kernel(const cplx* __restrict__ A, int H, cplx* __restrict__ G, const cp
     // offset switched by a select and a mask (loads under a branch here gave
     // wrong results on 8192-point columns).
     const int w0 = __builtin_amdgcn_readfirstlane(t & ~63);
+    // the thread index through an empty asm: the offsets below are formed
+    // here, not shared with those of M^'s loads and held in registers through
+    // its transform (which spilled them)
+    int tk = t;
+    asm volatile("" : "+v"(tk));
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-        const int i = t + T * m;
+        const int i = tk + T * m;
         const int r0 = w0 + T * m;
         const int32_t need = kseg[r0 >> 6] | kseg[(r0 + 63) >> 6];
         const int64_t mask = need != 0 ? -1 : 0;
@@ -792,14 +827,22 @@ p2_cols_kernel(const cplx* __restrict__ A, int H, cplx* __restrict__ G, const cp
         const int64_t off = ((int64_t)(i >> 3) * H * 8 + (i & 7)) & mask;
         b[0][m] = nt_load(base + off);
     }
-    p2_fft<N, 0, 1, 1, T>(b, lds, tw, false);
+    p2_fft<N, 0, 1, 1, T, kSplit>(b, lds, tw, false);
+    if constexpr (kSplit) {
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int m = 0; m < E; ++m) a[0][m].x = park[t + T * m];
+    }
 #pragma unroll
     for (int m = 0; m < E; ++m) a[0][m] = cmul(a[0][m], b[0][m]);
-    p2_fft<N, 0, 1, 1, T>(a, lds, tw, true);
-    // chunk (x2 / 4, u1) holds rows x2 .. x2 + 3 (four consecutive lanes)
+    p2_fft<N, 0, 1, 1, T, kSplit>(a, lds, tw, true);
+    // chunk (x2 / 4, u1) holds rows x2 .. x2 + 3 (four consecutive lanes);
+    // the offsets are formed here (the index through an empty asm, as above)
+    int tg = t;
+    asm volatile("" : "+v"(tg));
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-        const int i = t + T * m;
+        const int i = tg + T * m;
         G[((int64_t)(i >> 2) * H + u1) * 4 + (i & 3)] = a[0][m];
     }
 }
