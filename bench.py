@@ -357,7 +357,7 @@ def main():
             Ls_ = rl.DeviceLenses(fs.x1, fs.x2, fs.m)
             cs, es = ctx.new_map(sp)
             best = None
-            for k in range(3):
+            for k in range(6):        # one warm-up, then the best of five
                 # device time: the zeroing and a GPU sleep are queued ahead of
                 # the events, so the call's host work overlaps them
                 with torch.cuda.stream(stream):
