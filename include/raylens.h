@@ -404,6 +404,21 @@ rl_status rl_source_kernel(rl_context* ctx, const rl_profile* profile, const rl_
 rl_status rl_convolve(rl_context* ctx, const int32_t* d_counts, const double* d_kernel,
                       const rl_window* win, double n_avg, double* d_out, hipStream_t stream);
 
+/* One map against several kernels (Section 2.4 with the data production of
+ * Section 3: each map is convolved with many disc profiles and Einstein-radius
+ * scalings, and each convolved map is reduced and discarded). Computes
+ * h_outs[q] = rl_convolve(d_counts, h_kernels[q]) for q < n_kernels, bit for
+ * bit, with the map's own transforms done once for the batch on the
+ * power-of-two path (sides 256 ... 8192 and 10000). h_kernels and h_outs are
+ * host arrays of n_kernels device pointers (double[p2 x p1] each); outputs
+ * must be distinct buffers. 1 <= n_kernels <= RL_MAX_CONVOLVE_BATCH. Scratch
+ * as for rl_convolve. Asynchronous; the pointer arrays are read before
+ * return. */
+#define RL_MAX_CONVOLVE_BATCH 4096
+rl_status rl_convolve_batch(rl_context* ctx, const int32_t* d_counts, const double* const* h_kernels,
+                            int32_t n_kernels, const rl_window* win, double n_avg, double* const* h_outs,
+                            hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

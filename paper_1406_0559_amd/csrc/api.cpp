@@ -1022,15 +1022,15 @@ rl_status rl_source_kernel(rl_context* ctx, const rl_profile* profile, const rl_
     return RL_OK;
 }
 
-rl_status rl_convolve(rl_context* ctx, const int32_t* d_counts, const double* d_kernel,
-                      const rl_window* win, double n_avg, double* d_out, hipStream_t stream) {
-    g_error.clear();
-    if (!ctx) return fail(RL_E_INVALID, "context is NULL");
-    RL_TRY(check_counts(d_counts, win));
-    if (!d_kernel || !d_out) return fail(RL_E_INVALID, "pointers are NULL");
-    if (!is_finite(n_avg) || !(n_avg > 0.0)) return fail(RL_E_INVALID, "n_avg must be finite and > 0");
-    if (!rl::fft_side_supported(win->p1) || !rl::fft_side_supported(win->p2))
-        return fail(RL_E_INVALID, "map sides must be products of 2, 3 and 5 in [2, %d]", rl::kMaxFftSide);
+}  // extern "C"
+
+namespace {
+
+// One map against n kernels (n = 1 for rl_convolve); the arrays are host
+// arrays of device pointers, validated by the caller.
+rl_status convolve_many(rl_context* ctx, const int32_t* d_counts, const double* const* d_kernels,
+                        int32_t n, const rl_window* win, double n_avg, double* const* d_outs,
+                        hipStream_t stream) {
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return hip_fail(dg.err, "hipSetDevice");
     RL_TRY(ensure_ready(ctx));
@@ -1038,7 +1038,7 @@ rl_status rl_convolve(rl_context* ctx, const int32_t* d_counts, const double* d_
     if (e != hipSuccess) return hip_fail(e, "convolution scratch");
     const bool tw_ready = ctx->fft_tw_gen == ctx->fft.gen && ctx->fft_tw_p1 == win->p1 &&
                           ctx->fft_tw_p2 == win->p2;
-    e = rl::launch_convolve(d_counts, d_kernel, win->p1, win->p2, n_avg, d_out, ctx->fft.ptr, tw_ready,
+    e = rl::launch_convolve(d_counts, d_kernels, n, win->p1, win->p2, n_avg, d_outs, ctx->fft.ptr, tw_ready,
                             stream);
     hipError_t e2 = ctx->fft.release(stream);
     if (e == hipSuccess) e = e2;
@@ -1050,6 +1050,42 @@ rl_status rl_convolve(rl_context* ctx, const int32_t* d_counts, const double* d_
     ctx->fft_tw_p1 = win->p1;
     ctx->fft_tw_p2 = win->p2;
     return RL_OK;
+}
+
+rl_status check_convolve(rl_context* ctx, const int32_t* d_counts, const rl_window* win, double n_avg) {
+    if (!ctx) return fail(RL_E_INVALID, "context is NULL");
+    RL_TRY(check_counts(d_counts, win));
+    if (!is_finite(n_avg) || !(n_avg > 0.0)) return fail(RL_E_INVALID, "n_avg must be finite and > 0");
+    if (!rl::fft_side_supported(win->p1) || !rl::fft_side_supported(win->p2))
+        return fail(RL_E_INVALID, "map sides must be products of 2, 3 and 5 in [2, %d]", rl::kMaxFftSide);
+    return RL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+rl_status rl_convolve(rl_context* ctx, const int32_t* d_counts, const double* d_kernel,
+                      const rl_window* win, double n_avg, double* d_out, hipStream_t stream) {
+    g_error.clear();
+    RL_TRY(check_convolve(ctx, d_counts, win, n_avg));
+    if (!d_kernel || !d_out) return fail(RL_E_INVALID, "pointers are NULL");
+    return convolve_many(ctx, d_counts, &d_kernel, 1, win, n_avg, &d_out, stream);
+}
+
+rl_status rl_convolve_batch(rl_context* ctx, const int32_t* d_counts, const double* const* h_kernels,
+                            int32_t n_kernels, const rl_window* win, double n_avg, double* const* h_outs,
+                            hipStream_t stream) {
+    g_error.clear();
+    RL_TRY(check_convolve(ctx, d_counts, win, n_avg));
+    if (n_kernels < 1 || n_kernels > RL_MAX_CONVOLVE_BATCH)
+        return fail(RL_E_INVALID, "n_kernels must be in [1, %d]", RL_MAX_CONVOLVE_BATCH);
+    if (!h_kernels || !h_outs) return fail(RL_E_INVALID, "pointer arrays are NULL");
+    for (int32_t q = 0; q < n_kernels; ++q) {
+        if (!h_kernels[q] || !h_outs[q]) return fail(RL_E_INVALID, "kernel or output %d is NULL", q);
+        for (int32_t r = 0; r < q; ++r)
+            if (h_outs[r] == h_outs[q]) return fail(RL_E_INVALID, "outputs %d and %d are the same buffer", r, q);
+    }
+    return convolve_many(ctx, d_counts, h_kernels, n_kernels, win, n_avg, h_outs, stream);
 }
 
 }  // extern "C"

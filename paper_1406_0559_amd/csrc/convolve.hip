@@ -428,7 +428,9 @@ __global__ void __launch_bounds__(256) balance_kernel(const double* __restrict__
             e = e < -900 ? -900 : (e > 900 ? 900 : e);
         }
         bal[0] = ldexp(1.0, e);
-        bal[1] = ldexp(1.0, -e);
+        // a kernel of zeros convolves to zeros: the factor on the way out is
+        // 0, not the rounding noise that F(M) leaves in the recovered F(K)
+        bal[1] = sk[0] == 0.0 ? 0.0 : ldexp(1.0, -e);
     }
 }
 
@@ -683,7 +685,9 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 // Pass A. Block = rows j0, j0 + 1 of the p2 x N maps M and K; the M pair and
 // the K pair are transformed one after the other (fewer live registers: two
 // workgroups fit a CU).
-template <int N>
+// PARTS: bit 0 transforms the map's row pairs, bit 1 the kernel's (a batch of
+// kernels against one map transforms the map once).
+template <int N, int PARTS = 3>
 __global__ void __launch_bounds__(p2_threads<N>())
 __attribute__((amdgpu_waves_per_eu(N >= 2048 && N <= 4096 ? 4 : 1)))
 p2_rows_fwd_kernel(const int32_t* __restrict__ M, const double* __restrict__ K, int p2,
@@ -695,8 +699,10 @@ p2_rows_fwd_kernel(const int32_t* __restrict__ M, const double* __restrict__ K, 
     const int t = threadIdx.x;
     const int j0 = 2 * xcd_block(blockIdx.x, gridDim.x);
     if (t == 0) any_nz = 0;    // ordered before its use by the M pair's barriers
+    if constexpr (PARTS == 2) __syncthreads();   // ... or by this one
 #pragma unroll
     for (int v = 0; v < 2; ++v) {
+        if (!((PARTS >> v) & 1)) continue;
         cplx a[1][E];
 #pragma unroll
         for (int m = 0; m < E; ++m) {
@@ -938,10 +944,10 @@ FftPlan p2_plan_of(int n) {
 }
 
 template <int N>
-hipError_t p2_rows_fwd(const int32_t* M, const double* K, int p2, cplx* A, const cplx* tw, uint8_t* kz,
+hipError_t p2_rows_fwd(int parts, const int32_t* M, const double* K, int p2, cplx* A, const cplx* tw, uint8_t* kz,
                        int32_t* kseg, cplx* kzero, hipStream_t s) {
-    hipLaunchKernelGGL(p2_rows_fwd_kernel<N>, dim3(p2 / 2), dim3(p2_threads<N>()), 0, s, M, K, p2, A, tw, kz, kseg,
-                       kzero);
+    auto k = parts == 1 ? p2_rows_fwd_kernel<N, 1> : (parts == 2 ? p2_rows_fwd_kernel<N, 2> : p2_rows_fwd_kernel<N, 3>);
+    hipLaunchKernelGGL(k, dim3(p2 / 2), dim3(p2_threads<N>()), 0, s, M, K, p2, A, tw, kz, kseg, kzero);
     return hipGetLastError();
 }
 template <int N>
@@ -958,9 +964,9 @@ hipError_t p2_rows_inv(const cplx* G, int p2, double scale, double* out, const c
     return hipGetLastError();
 }
 
-hipError_t p2_rows_fwd_any(int n, const int32_t* M, const double* K, int p2, cplx* A, const cplx* tw,
+hipError_t p2_rows_fwd_any(int n, int parts, const int32_t* M, const double* K, int p2, cplx* A, const cplx* tw,
                            uint8_t* kz, int32_t* kseg, cplx* kzero, hipStream_t s) {
-#define RL_CALL(N) p2_rows_fwd<N>(M, K, p2, A, tw, kz, kseg, kzero, s)
+#define RL_CALL(N) p2_rows_fwd<N>(parts, M, K, p2, A, tw, kz, kseg, kzero, s)
     switch (n) {
         case 256: return RL_CALL(256);
         case 512: return RL_CALL(512);
@@ -1009,8 +1015,11 @@ size_t p2_scratch_bytes(int p1, int p2) {
            (size_t)(p2 / 64 + 2) * sizeof(int32_t) + 256;
 }
 
-hipError_t p2_convolve(const int32_t* counts, const double* kernel, int p1, int p2, double n_avg,
-                       double* out, void* scratch, bool twiddles_ready, hipStream_t s) {
+// A map against n kernels: the map's row transforms once (pass A, map part),
+// then per kernel pass A's kernel part, pass B and pass C; with n = 1 pass A
+// does both parts in one launch.
+hipError_t p2_convolve(const int32_t* counts, const double* const* kernels, int n, int p1, int p2,
+                       double n_avg, double* const* outs, void* scratch, bool twiddles_ready, hipStream_t s) {
     const int H = p1 / 2 + 1;
     cplx* A = static_cast<cplx*>(scratch);                 // {M^, K^} x p2 / 8 x H x {eight rows}
     cplx* G = A + (size_t)H * p2 * 2;                      // p2 / 4 x H x {4 rows}
@@ -1030,10 +1039,13 @@ hipError_t p2_convolve(const int32_t* counts, const double* kernel, int p1, int 
         hipLaunchKernelGGL(p2_clear_kernel, dim3((p2 / 2 + 255) / 256), dim3(256), 0, s, kz, p2 / 2);
     }
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = p2_rows_fwd_any(p1, counts, kernel, p2, A, tw1, kz, kseg, kzero, s);
-    if (e == hipSuccess) e = p2_cols_any(p2, A, G, H, tw2, kseg, kzero, s);
-    if (e == hipSuccess)
-        e = p2_rows_inv_any(p1, G, p2, 1.0 / ((double)p1 * (double)p2 * n_avg), out, tw1, kseg, s);
+    if (e == hipSuccess && n > 1) e = p2_rows_fwd_any(p1, 1, counts, nullptr, p2, A, tw1, kz, kseg, kzero, s);
+    const double scale = 1.0 / ((double)p1 * (double)p2 * n_avg);
+    for (int q = 0; q < n && e == hipSuccess; ++q) {
+        e = p2_rows_fwd_any(p1, n > 1 ? 2 : 3, counts, kernels[q], p2, A, tw1, kz, kseg, kzero, s);
+        if (e == hipSuccess) e = p2_cols_any(p2, A, G, H, tw2, kseg, kzero, s);
+        if (e == hipSuccess) e = p2_rows_inv_any(p1, G, p2, scale, outs[q], tw1, kseg, s);
+    }
     return e;
 }
 
@@ -1183,10 +1195,9 @@ size_t convolve_scratch_bytes(int p1, int p2) {
     return 2 * plane + (size_t)(p1 + 2 * p2) * sizeof(cplx) + (2 * kNormBlocks + 2) * sizeof(double) + 256;
 }
 
-hipError_t launch_convolve(const int32_t* counts, const double* kernel, int p1, int p2, double n_avg,
-                           double* out, void* scratch, bool twiddles_ready, hipStream_t s) {
-    if (pow2_side(p1) && pow2_side(p2))
-        return p2_convolve(counts, kernel, p1, p2, n_avg, out, scratch, twiddles_ready, s);
+// Other sides: five passes per kernel.
+hipError_t general_convolve(const int32_t* counts, const double* kernel, int p1, int p2, double n_avg,
+                            double* out, void* scratch, bool twiddles_ready, hipStream_t s) {
     // plans for the x1 rows, the x2 row pairs and (long columns) the x2 rows
     FftPlan P1, P2, P2r;
     if (p1 > kMaxFftSide || p2 > kMaxFftSide || !make_plan(p1, &P1, max_radix(p1, 1, row_threads(p1))) ||
@@ -1225,6 +1236,17 @@ hipError_t launch_convolve(const int32_t* counts, const double* kernel, int p1, 
     if (e == hipSuccess) e = transpose(t, z, p1, p2, s);            // z: p2 x p1
     if (e == hipSuccess)
         e = rows<kInvOut>(nullptr, nullptr, z, out, p2, P1, tw1, 1.0 / ((double)n * n_avg), bal, s);
+    return e;
+}
+
+hipError_t launch_convolve(const int32_t* counts, const double* const* kernels, int n, int p1, int p2,
+                           double n_avg, double* const* outs, void* scratch, bool twiddles_ready, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (pow2_side(p1) && pow2_side(p2))
+        return p2_convolve(counts, kernels, n, p1, p2, n_avg, outs, scratch, twiddles_ready, s);
+    hipError_t e = hipSuccess;
+    for (int q = 0; q < n && e == hipSuccess; ++q)
+        e = general_convolve(counts, kernels[q], p1, p2, n_avg, outs[q], scratch, twiddles_ready || q > 0, s);
     return e;
 }
 

@@ -59,11 +59,14 @@ hipError_t launch_codec_unpack(const uint32_t* packed, int64_t n_pix, int bits, 
 // [2, kMaxFftSide].
 bool fft_side_supported(int n);
 size_t convolve_scratch_bytes(int p1, int p2);
-// The scratch holds the stage-twiddle tables of both axes at offsets fixed
-// by (p1, p2); twiddles_ready says that a previous call with the same sides
-// and the same scratch buffer left them there, so they are not recomputed.
-hipError_t launch_convolve(const int32_t* counts, const double* kernel, int p1, int p2, double n_avg,
-                           double* out, void* scratch, bool twiddles_ready, hipStream_t stream);
+// The map is convolved with kernels[0 .. n) into outs[0 .. n) (host arrays
+// of device pointers). The scratch holds the stage-twiddle tables of both
+// axes at offsets fixed by (p1, p2); twiddles_ready says that a previous call
+// with the same sides and the same scratch buffer left them there (and what
+// else the power-of-two path keeps with them), so they are not recomputed.
+hipError_t launch_convolve(const int32_t* counts, const double* const* kernels, int n, int p1, int p2,
+                           double n_avg, double* const* outs, void* scratch, bool twiddles_ready,
+                           hipStream_t stream);
 size_t source_scratch_bytes(int h1, int h2);
 hipError_t launch_source_kernel(int shape, double radius, double hole, double pix1, double pix2,
                                 int h1, int h2, int p1, int p2, double* kernel, double* scratch,

@@ -112,6 +112,7 @@ def load():
         "rl_codec_decode": [vp, vp, i32, vp, i64, P(rl_window), vp, vp],
         "rl_source_kernel": [vp, P(rl_profile), P(rl_window), vp, vp],
         "rl_convolve": [vp, vp, vp, P(rl_window), dbl, vp, vp],
+        "rl_convolve_batch": [vp, vp, P(vp), i32, P(rl_window), dbl, P(vp), vp],
         "rl_autotune": [vp, C.c_char_p, i32],
         "rl_get_tuning": [vp, C.c_int, i32, P(rl_tuning)],
         "rl_set_tuning": [vp, C.c_int, i32, P(rl_tuning)],
@@ -175,6 +176,7 @@ def rl_shoot_noalloc(ctx, lenses, macro, grid, win, precision, row_begin, row_en
 
 
 RL_NOALLOC_MAX_LENSES = 131072   # include/raylens.h
+RL_MAX_CONVOLVE_BATCH = 4096     # include/raylens.h
 
 
 def rl_normalise(ctx, d_counts, win, n_avg, d_mu, stream=None):
@@ -246,6 +248,14 @@ def rl_source_kernel(ctx, profile, win, d_kernel, stream=None):
 
 def rl_convolve(ctx, d_counts, d_kernel, win, n_avg, d_out, stream=None):
     _check(load().rl_convolve(ctx, d_counts, d_kernel, C.byref(win), n_avg, d_out, stream))
+
+
+def rl_convolve_batch(ctx, d_counts, d_kernels, win, n_avg, d_outs, stream=None):
+    """d_kernels, d_outs: sequences of device pointers of equal length."""
+    n = len(d_kernels)
+    ks = (C.c_void_p * n)(*d_kernels)
+    os_ = (C.c_void_p * len(d_outs))(*d_outs)
+    _check(load().rl_convolve_batch(ctx, d_counts, ks, n, C.byref(win), n_avg, os_, stream))
 
 
 def rl_autotune(ctx, cache_path=None, budget_ms=0):
@@ -515,6 +525,27 @@ class Context:
         rl_convolve(self.handle, counts.data_ptr(), kernel.data_ptr(), window_of(spec), n_avg,
                     out.data_ptr(), _stream_ptr(stream))
         return out
+
+    def convolve_batch(self, counts, kernels, spec, n_avg=1.0, outs=None, stream=None):
+        """The map convolved with each of `kernels` (rl_convolve_batch)."""
+        torch = _torch()
+        _check_counts(counts, spec, self.device)
+        kernels = list(kernels)
+        if not kernels:
+            raise ValueError("kernels is empty")
+        for q, k in enumerate(kernels):
+            _dev(k, torch.float64, spec.p1 * spec.p2, f"kernels[{q}]", self.device)
+        if outs is None:
+            outs = [torch.empty((spec.p2, spec.p1), dtype=torch.float64, device=counts.device)
+                    for _ in kernels]
+        outs = list(outs)
+        if len(outs) != len(kernels):
+            raise ValueError("outs and kernels differ in length")
+        for q, o in enumerate(outs):
+            _dev(o, torch.float64, spec.p1 * spec.p2, f"outs[{q}]", self.device)
+        rl_convolve_batch(self.handle, counts.data_ptr(), [k.data_ptr() for k in kernels], window_of(spec),
+                          n_avg, [o.data_ptr() for o in outs], _stream_ptr(stream))
+        return outs
 
     def autotune(self, cache_path=None, budget_ms=0):
         rl_autotune(self.handle, cache_path, budget_ms)

@@ -164,6 +164,14 @@ def test_autotune_validates_on_the_host(tmp_path):
         rl.rl_destroy(ctx)
 
 
+def test_binding_constants_match_the_header():
+    text = open(os.path.join(ROOT, "include", "raylens.h")).read()
+    for name in ("RL_NOALLOC_MAX_LENSES", "RL_MAX_CONVOLVE_BATCH"):
+        m = re.search(r"^#define\s+" + name + r"\s+(\d+)", text, flags=re.M)
+        assert m, name
+        assert int(m.group(1)) == getattr(rl, name), name
+
+
 def test_header_documents_every_entry_point():
     """Each declaration in the public header is preceded by a comment."""
     text = open(os.path.join(ROOT, "include", "raylens.h")).read()
@@ -254,6 +262,21 @@ def test_convolution_entry_points_validate_on_the_host():
             assert lib.rl_convolve(ctx, fake, fake, C.byref(ww), 1.0, fake, None) == rl.RL_E_INVALID
         assert lib.rl_convolve(ctx, fake, fake, C.byref(w), 0.0, fake, None) == rl.RL_E_INVALID
         assert lib.rl_convolve(ctx, fake, None, C.byref(w), 1.0, fake, None) == rl.RL_E_INVALID
+        # the batch form: counts, sizes, NULL arrays or entries, shared outputs
+        V = C.c_void_p
+        ks = (V * 3)(0x1000, 0x2000, 0x3000)
+        outs = (V * 3)(0x4000, 0x5000, 0x6000)
+        same = (V * 3)(0x4000, 0x5000, 0x4000)
+        holes = (V * 3)(0x1000, None, 0x3000)
+        bad = rl.rl_window(49, 64, 0.0, 0.0, 2.0, 2.0)
+        for args in ((fake, ks, 0, w, 1.0, outs), (fake, ks, rl.RL_MAX_CONVOLVE_BATCH + 1, w, 1.0, outs),
+                     (fake, None, 3, w, 1.0, outs), (fake, ks, 3, w, 1.0, None), (fake, holes, 3, w, 1.0, outs),
+                     (fake, ks, 3, w, 1.0, holes), (fake, ks, 3, w, 1.0, same), (None, ks, 3, w, 1.0, outs),
+                     (fake, ks, 3, w, 0.0, outs), (fake, ks, 3, bad, 1.0, outs)):
+            c, k, n, ww, na, o = args
+            assert lib.rl_convolve_batch(ctx, c, k, n, C.byref(ww), na, o, None) == rl.RL_E_INVALID, args
+        assert lib.rl_convolve_batch(ctx, fake, ks, 3, C.byref(w), 1.0, same, None) == rl.RL_E_INVALID
+        assert "outputs 0 and 2" in rl.rl_last_error()
     finally:
         rl.rl_destroy(ctx)
 

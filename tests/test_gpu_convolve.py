@@ -164,6 +164,38 @@ def test_convolution_of_a_10000sq_map_at_sampled_pixels(ctx):
     assert abs(mu.sum() * 40.0 - M.sum(dtype=np.int64)) < 1e-9 * M.sum(dtype=np.int64)
 
 
+@pytest.mark.parametrize("p1,p2", [(512, 256), (4096, 512), (256, 10000), (300, 120)])
+def test_batch_equals_single_calls(p1, p2):
+    """rl_convolve_batch (the map's transforms once, then each kernel) gives
+    the same bits as one rl_convolve per kernel: source profiles of several
+    sizes, a dense kernel and a zero kernel, on the power-of-two path and on
+    the general path (300 x 120, one five-pass convolution per kernel); the
+    first result also against the oracle."""
+    c = rl.Context(0)
+    try:
+        rng = np.random.default_rng(p1 + 3 * p2)
+        spec = spec_of(p1, p2)
+        M = torch.from_numpy(rng.integers(0, 900, size=(p2, p1)).astype(np.int32)).cuda()
+        dense = rng.random((p2, p1))
+        dense /= dense.sum()
+        kernels = [c.source_kernel(spec, "gaussian", 0.05), c.source_kernel(spec, "uniform", 0.11),
+                   torch.from_numpy(dense).cuda(), torch.zeros((p2, p1), dtype=torch.float64, device="cuda"),
+                   c.source_kernel(spec, "power", 0.08, 0.01)]
+        outs = c.convolve_batch(M, kernels, spec, n_avg=2.5)
+        torch.cuda.synchronize()
+        for q, k in enumerate(kernels):
+            one = c.convolve(M, k, spec, n_avg=2.5)
+            assert torch.equal(outs[q], one), q
+        ref = ocv.convolve(M.cpu().numpy(), kernels[0].cpu().numpy(), 2.5)
+        assert np.abs(outs[0].cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+        # a zero kernel convolves to exact zeros on both paths (the general one
+        # packs M + i 2^e K into one transform and takes the kernel's zero norm
+        # as the factor on the way out)
+        assert not outs[3].cpu().numpy().any()
+    finally:
+        c.close()
+
+
 def test_cached_twiddles_across_calls():
     """A fresh context convolves sides in the order A, A, B, A, C (C larger,
     so the scratch is reallocated), A: the stage-twiddle tables are reused
