@@ -410,8 +410,10 @@ rl_status rl_convolve(rl_context* ctx, const int32_t* d_counts, const double* d_
  * h_outs[q] = rl_convolve(d_counts, h_kernels[q]) for q < n_kernels, bit for
  * bit, with the map's own transforms done once for the batch on the
  * power-of-two path (sides 256 ... 8192 and 10000). h_kernels and h_outs are
- * host arrays of n_kernels device pointers (double[p2 x p1] each); outputs
- * must be distinct buffers. 1 <= n_kernels <= RL_MAX_CONVOLVE_BATCH. Scratch
+ * host arrays of n_kernels device pointers (double[p2 x p1] each); the
+ * outputs must not overlap each other, the kernels or the map (an output is
+ * written before the next kernel is read; equal pointers are refused with
+ * RL_E_INVALID). 1 <= n_kernels <= RL_MAX_CONVOLVE_BATCH. Scratch
  * as for rl_convolve. Asynchronous; the pointer arrays are read before
  * return. */
 #define RL_MAX_CONVOLVE_BATCH 4096

@@ -1080,10 +1080,16 @@ rl_status rl_convolve_batch(rl_context* ctx, const int32_t* d_counts, const doub
     if (n_kernels < 1 || n_kernels > RL_MAX_CONVOLVE_BATCH)
         return fail(RL_E_INVALID, "n_kernels must be in [1, %d]", RL_MAX_CONVOLVE_BATCH);
     if (!h_kernels || !h_outs) return fail(RL_E_INVALID, "pointer arrays are NULL");
+    // output q is written before kernel q + 1 is read: no output may be a
+    // kernel's or the map's buffer, nor another output
     for (int32_t q = 0; q < n_kernels; ++q) {
         if (!h_kernels[q] || !h_outs[q]) return fail(RL_E_INVALID, "kernel or output %d is NULL", q);
+        if (static_cast<const void*>(h_outs[q]) == static_cast<const void*>(d_counts))
+            return fail(RL_E_INVALID, "output %d is the map's buffer", q);
         for (int32_t r = 0; r < q; ++r)
             if (h_outs[r] == h_outs[q]) return fail(RL_E_INVALID, "outputs %d and %d are the same buffer", r, q);
+        for (int32_t r = 0; r < n_kernels; ++r)
+            if (h_outs[q] == h_kernels[r]) return fail(RL_E_INVALID, "output %d is kernel %d's buffer", q, r);
     }
     return convolve_many(ctx, d_counts, h_kernels, n_kernels, win, n_avg, h_outs, stream);
 }

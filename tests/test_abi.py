@@ -277,6 +277,11 @@ def test_convolution_entry_points_validate_on_the_host():
             assert lib.rl_convolve_batch(ctx, c, k, n, C.byref(ww), na, o, None) == rl.RL_E_INVALID, args
         assert lib.rl_convolve_batch(ctx, fake, ks, 3, C.byref(w), 1.0, same, None) == rl.RL_E_INVALID
         assert "outputs 0 and 2" in rl.rl_last_error()
+        onto_kernel = (V * 3)(0x4000, 0x3000, 0x6000)     # output 1 is kernel 2
+        assert lib.rl_convolve_batch(ctx, fake, ks, 3, C.byref(w), 1.0, onto_kernel, None) == rl.RL_E_INVALID
+        assert "output 1 is kernel 2" in rl.rl_last_error()
+        onto_map = (V * 3)(0x4000, 0x1000, 0x6000)        # output 1 is the map (fake)
+        assert lib.rl_convolve_batch(ctx, fake, ks, 3, C.byref(w), 1.0, onto_map, None) == rl.RL_E_INVALID
     finally:
         rl.rl_destroy(ctx)
 
