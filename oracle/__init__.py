@@ -40,12 +40,13 @@ def lib():
         L.oracle_count_histogram.argtypes = [vp, i64, i64, vp]
         L.oracle_mpd_thresholds.argtypes = [dbl, dbl, dbl, dbl, i32, vp]
         L.oracle_mpd.argtypes = [vp, i64, vp, i32, vp]
+        L.oracle_mpd_values.argtypes = [vp, i64, vp, i32, vp]
         L.oracle_probability_sums.argtypes = [vp, i64, dbl, dbl, vp, vp]
         L.oracle_codec_encode.argtypes = [vp, i64, vp, vp, vp, vp]
         L.oracle_codec_decode.argtypes = [vp, i64, i32, vp, i64, vp]
         for f in ("oracle_ray_positions", "oracle_bin", "oracle_shoot", "oracle_normalise",
                   "oracle_stats", "oracle_max_threads", "oracle_count_histogram",
-                  "oracle_mpd_thresholds", "oracle_mpd", "oracle_probability_sums",
+                  "oracle_mpd_thresholds", "oracle_mpd", "oracle_mpd_values", "oracle_probability_sums",
                   "oracle_codec_encode", "oracle_codec_decode"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -174,6 +175,18 @@ def mpd(counts, n_avg_value, mu_ref, log_lo, log_hi, nbins):
     bins = np.zeros(int(nbins) + 2, np.int64)
     if lib().oracle_mpd(_p(counts), counts.size, _p(thr), int(nbins), _p(bins)) != 0:
         raise ValueError("oracle_mpd: invalid arguments")
+    return bins
+
+
+def mpd_values(mu, mu_ref, log_lo, log_hi, nbins):
+    """Binned MPD of a map of real magnifications (a finite-source map) in
+    log10(mu / mu_ref): [underflow, nbins bins, overflow] pixel counts; the
+    thresholds are mu_ref 10^edge (mpd_thresholds with n_avg = 1)."""
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    thr = mpd_thresholds(1.0, mu_ref, log_lo, log_hi, nbins)
+    bins = np.zeros(int(nbins) + 2, np.int64)
+    if lib().oracle_mpd_values(_p(mu), mu.size, _p(thr), int(nbins), _p(bins)) != 0:
+        raise ValueError("oracle_mpd_values: invalid arguments")
     return bins
 
 

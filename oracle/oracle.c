@@ -258,6 +258,21 @@ int oracle_mpd(const int32_t* counts, int64_t n_pix, const double* thr, int32_t 
     return 0;
 }
 
+/* The binned MPD of a magnification map of real values (a finite-source map,
+ * Section 2.4, whose MPD is stored for every convolution as for every map,
+ * Section 3): the same rule as oracle_mpd, a value goes to the bin numbered
+ * by how many thresholds lie at or below it (NaN and -inf: none, bin 0). */
+int oracle_mpd_values(const double* mu, int64_t n_pix, const double* thr, int32_t nbins, int64_t* bins) {
+    if (n_pix < 0 || nbins < 1 || !thr || !bins || (n_pix > 0 && !mu)) return -1;
+    for (int32_t b = 0; b < nbins + 2; ++b) bins[b] = 0;
+    for (int64_t k = 0; k < n_pix; ++k) {
+        int32_t b = 0;
+        while (b <= nbins && thr[b] <= mu[k]) ++b;
+        bins[b] += 1;
+    }
+    return 0;
+}
+
 int oracle_probability_sums(const int32_t* counts, int64_t n_pix, double n_avg, double mu_lim,
                             int64_t* below, int64_t* above) {
     if (n_pix < 0 || !(n_avg > 0.0) || !isfinite(n_avg) || isnan(mu_lim) || !below || !above) return -1;

@@ -76,6 +76,9 @@ int oracle_mpd_thresholds(double n_avg, double mu_ref, double log_lo, double log
  * bins[1 + k] those with thr[k] <= N < thr[k + 1], bins[nbins + 1] those at
  * or above thr[nbins]. bins (nbins + 2 entries) is overwritten. */
 int oracle_mpd(const int32_t* counts, int64_t n_pix, const double* thr, int32_t nbins, int64_t* bins);
+/* The same binning of real magnification values (thresholds from
+ * oracle_mpd_thresholds with n_avg = 1). */
+int oracle_mpd_values(const double* mu, int64_t n_pix, const double* thr, int32_t nbins, int64_t* bins);
 
 /* Probability sums (Section 4: P(mu < mu_lim) and P(mu > mu_lim), which add
  * to one): *below counts pixels with N / N_avg < mu_lim, *above the rest. */

@@ -164,3 +164,45 @@ def test_bin_edges_are_half_open():
     assert thr[0] == 10.0 and thr[1] == 100.0
     bins = oracle.mpd(counts, 10.0, 1.0, 0.0, 1.0, 1)
     assert bins.tolist() == [2, 3, 1]
+
+
+# ---------------------------------------------------------------------------
+# MPDs of maps of real magnifications (finite-source maps)
+# ---------------------------------------------------------------------------
+
+def test_mpd_values_against_searchsorted():
+    """The bin of a value is the number of thresholds at or below it: the
+    insertion point of the value to the right of equal thresholds, which
+    numpy's searchsorted gives independently of the oracle's scan."""
+    rng = np.random.default_rng(41)
+    mu = 10.0 ** rng.uniform(-2.5, 2.5, size=20000)
+    thr = oracle.mpd_thresholds(1.0, 3.7, -1.5, 1.5, 100)
+    mu[:101] = thr                                        # exactly on every edge
+    mu[101:202] = np.nextafter(thr, -np.inf)              # just below every edge
+    got = oracle.mpd_values(mu, 3.7, -1.5, 1.5, 100)
+    expect = np.bincount(np.searchsorted(thr, mu, side="right"), minlength=102)
+    assert (got == expect).all()
+    assert got.sum() == mu.size
+
+
+def test_mpd_values_thresholds_are_mu_ref_times_powers_of_ten():
+    """With n_avg = 1 the edges are mu_ref 10^(lo + k (hi - lo) / nbins); the
+    bin of log10(mu / mu_ref) = lo + (k + 1/2) (hi - lo) / nbins is k."""
+    mu_ref, lo, hi, nb = 4.91, -1.5, 1.5, 100
+    thr = oracle.mpd_thresholds(1.0, mu_ref, lo, hi, nb)
+    k = np.arange(nb)
+    np.testing.assert_allclose(thr, mu_ref * 10.0 ** (lo + np.arange(nb + 1) * (hi - lo) / nb), rtol=1e-14)
+    mids = mu_ref * 10.0 ** (lo + (k + 0.5) * (hi - lo) / nb)
+    got = oracle.mpd_values(mids, mu_ref, lo, hi, nb)
+    assert (got[1:-1] == 1).all() and got[0] == 0 and got[-1] == 0
+
+
+def test_mpd_values_special_values():
+    """NaN and -inf are below every edge (underflow), +inf above (overflow);
+    zeros and negative values underflow; a constant map fills one bin."""
+    mu = np.array([np.nan, -np.inf, -1.0, 0.0, np.inf, 1e300])
+    got = oracle.mpd_values(mu, 1.0, -1.0, 1.0, 10)
+    assert got[0] == 4 and got[-1] == 2 and got.sum() == 6
+    c = np.full((30, 40), 2.0)
+    got = oracle.mpd_values(c, 1.0, -1.0, 1.0, 10)      # log10 2 = 0.301 lies in [0.2, 0.4)
+    assert got[1 + 6] == 1200 and got.sum() == 1200

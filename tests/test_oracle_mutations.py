@@ -34,6 +34,10 @@ MUTANTS = {
                      "const double ray_density = ((double)n1 * (double)n2) / (2.0 * h1 * h2);"),
     "mpd-scale-without-mu-ref": ("const double scale = n_avg * mu_ref;", "const double scale = n_avg;"),
     "mpd-edge-closed": ("while (b <= nbins && thr[b] <= c) ++b;", "while (b <= nbins && thr[b] < c) ++b;"),
+    "mpd-values-edge-closed": ("while (b <= nbins && thr[b] <= mu[k]) ++b;",
+                               "while (b <= nbins && thr[b] < mu[k]) ++b;"),
+    "mpd-values-overflow-dropped": ("while (b <= nbins && thr[b] <= mu[k]) ++b;",
+                                    "while (b < nbins && thr[b] <= mu[k]) ++b;"),
     "probability-sum-closed": ("if ((double)counts[k] / n_avg < mu_lim) lo += 1;",
                                "if ((double)counts[k] / n_avg <= mu_lim) lo += 1;"),
     "histogram-overflow-dropped": ("hist[c < n_values - 1 ? c : n_values - 1] += 1;",
