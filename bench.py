@@ -245,6 +245,9 @@ def main():
         conv = torch.empty((spec.p2, spec.p1), dtype=torch.float64, device="cuda")
         t_kern = timed(lambda: ctx.source_kernel(spec, "gaussian", 0.2, kernel=kern, stream=stream))
         t_conv = timed(lambda: ctx.convolve(final, kern, spec, n_avg=n_avg, out=conv, stream=stream))
+        # the MPD of the finite-source map (stored for every convolution)
+        mbins = torch.zeros(102, dtype=torch.int64, device="cuda")
+        t_mpdv = timed(lambda: ctx.mpd_values(conv, spec, mu_th_abs, -1.5, 1.5, 100, bins=mbins, stream=stream))
         # one map against four source sizes in one call (the map's transforms once)
         kerns4 = [ctx.source_kernel(spec, "gaussian", r, stream=stream) for r in (0.1, 0.2, 0.4, 0.8)]
         outs4 = [torch.empty_like(conv) for _ in kerns4]
@@ -272,6 +275,7 @@ def main():
                 "source_kernel_us": t_kern * 1e3, "convolve_ms": t_conv, "convolve_10000sq_ms": t_conv10,
                 "convolve_dense_kernel_ms": t_conv_dense,
                 "convolve_batch4_ms_per_kernel": t_batch4 / 4,
+                "mpd_of_convolved_map_us": t_mpdv * 1e3,
                 "convolve_min_GBps": gbs(20 * n_pix, t_conv),
                 "count_histogram_us": t_hist * 1e3, "count_histogram_GBps": gbs(4 * n_pix, t_hist),
                 "mpd_100bins_us": t_mpd * 1e3, "mpd_GBps": gbs(4 * n_pix, t_mpd),

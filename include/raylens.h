@@ -319,6 +319,17 @@ rl_status rl_mpd(rl_context* ctx, const int32_t* d_counts, const rl_window* win,
                  double mu_ref, double log_lo, double log_hi, int32_t nbins, int64_t* d_bins,
                  hipStream_t stream);
 
+/* Binned MPD of a map of real magnifications, such as a finite-source map
+ * from rl_convolve (Section 3: an MPD is stored for every convolution as for
+ * every map): the bins of rl_mpd with thresholds T_k = mu_ref 10^(log_lo +
+ * k (log_hi - log_lo) / nbins) in FP64, and a pixel with magnification mu goes
+ * to bin b = #{k : T_k <= mu} (NaN, -inf, zero and negative values to the
+ * underflow d_bins[0], +inf to the overflow d_bins[nbins + 1]). d_mu is
+ * double[p2 x p1]; d_bins int64[nbins + 2], caller-zeroed, accumulated.
+ * mu_ref finite > 0; log_lo < log_hi finite; 1 <= nbins <= 4096. Asynchronous. */
+rl_status rl_mpd_values(rl_context* ctx, const double* d_mu, const rl_window* win, double mu_ref,
+                        double log_lo, double log_hi, int32_t nbins, int64_t* d_bins, hipStream_t stream);
+
 /* Probability sums for mu < mu_lim and mu > mu_lim (Section 4, MPDs tool;
  * the two add up to one): *h_below = number of pixels with N / N_avg < mu_lim
  * (the FP64 quotient, compared in FP64; the quotient is monotone in N, so the

@@ -814,34 +814,36 @@ rl_status rl_count_histogram(rl_context* ctx, const int32_t* d_counts, const rl_
     return RL_OK;
 }
 
-rl_status rl_mpd(rl_context* ctx, const int32_t* d_counts, const rl_window* win, double n_avg,
-                 double mu_ref, double log_lo, double log_hi, int32_t nbins, int64_t* d_bins,
-                 hipStream_t stream) {
-    g_error.clear();
-    if (!ctx) return fail(RL_E_INVALID, "context is NULL");
-    RL_TRY(check_counts(d_counts, win));
-    if (!is_finite(n_avg) || !(n_avg > 0.0)) return fail(RL_E_INVALID, "n_avg must be finite and > 0");
+}  // extern "C"
+
+namespace {
+
+rl_status check_mpd_args(double mu_ref, double log_lo, double log_hi, int32_t nbins, const int64_t* d_bins) {
     if (!is_finite(mu_ref) || !(mu_ref > 0.0)) return fail(RL_E_INVALID, "mu_ref must be finite and > 0");
     if (!is_finite(log_lo) || !is_finite(log_hi) || !(log_hi > log_lo))
         return fail(RL_E_INVALID, "need finite log_lo < log_hi");
     if (nbins < 1 || nbins > rl::kMaxMpdBins) return fail(RL_E_INVALID, "nbins must be in [1, %d]", rl::kMaxMpdBins);
     if (!d_bins) return fail(RL_E_INVALID, "bins pointer is NULL");
+    return RL_OK;
+}
+
+// Thresholds scale 10^(log_lo + k (log_hi - log_lo) / nbins), k = 0..nbins,
+// in FP64 on the host; up to kMpdArgThr of them go with the launch, more
+// through scratch. launch(args, thr) starts the binning kernel.
+template <typename Launch>
+rl_status mpd_with_thresholds(rl_context* ctx, double scale, double log_lo, double log_hi, int32_t nbins,
+                              hipStream_t stream, Launch&& launch) {
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return hip_fail(dg.err, "hipSetDevice");
     RL_TRY(ensure_ready(ctx));
-    // count thresholds of the log10(mu / mu_ref) bin edges, in FP64 on the
-    // host; up to kMpdArgThr of them go with the launch, more through scratch
     const int nthr = nbins + 1;
     const double step = (log_hi - log_lo) / (double)nbins;
-    const double scale = n_avg * mu_ref;
     auto threshold = [&](int k) { return scale * std::pow(10.0, log_lo + (double)k * step); };
-    const int64_t n = (int64_t)win->p1 * win->p2;
     rl::MpdThresholds args{};
     hipError_t e;
     if (nthr <= rl::kMpdArgThr) {
         for (int k = 0; k < nthr; ++k) args.t[k] = threshold(k);
-        e = rl::launch_mpd(d_counts, n, args, nullptr, nthr, reinterpret_cast<unsigned long long*>(d_bins),
-                           stream);
+        e = launch(args, static_cast<const double*>(nullptr));
         if (e != hipSuccess) return hip_fail(e, "mpd launch");
         return RL_OK;
     }
@@ -853,12 +855,50 @@ rl_status rl_mpd(rl_context* ctx, const int32_t* d_counts, const rl_window* win,
     e = ctx->aux.acquire(bytes, stream);
     if (e != hipSuccess) return hip_fail(e, "threshold scratch");
     RL_TRY(stage_send(ctx, ctx->aux.ptr, bytes, stream));
-    e = rl::launch_mpd(d_counts, n, args, static_cast<const double*>(ctx->aux.ptr), nthr,
-                       reinterpret_cast<unsigned long long*>(d_bins), stream);
+    e = launch(args, static_cast<const double*>(ctx->aux.ptr));
     hipError_t e2 = ctx->aux.release(stream);
     if (e == hipSuccess) e = e2;
     if (e != hipSuccess) return hip_fail(e, "mpd launch");
     return RL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+rl_status rl_mpd(rl_context* ctx, const int32_t* d_counts, const rl_window* win, double n_avg,
+                 double mu_ref, double log_lo, double log_hi, int32_t nbins, int64_t* d_bins,
+                 hipStream_t stream) {
+    g_error.clear();
+    if (!ctx) return fail(RL_E_INVALID, "context is NULL");
+    RL_TRY(check_counts(d_counts, win));
+    if (!is_finite(n_avg) || !(n_avg > 0.0)) return fail(RL_E_INVALID, "n_avg must be finite and > 0");
+    RL_TRY(check_mpd_args(mu_ref, log_lo, log_hi, nbins, d_bins));
+    // count thresholds: N >= n_avg mu_ref 10^edge
+    const int64_t n = (int64_t)win->p1 * win->p2;
+    return mpd_with_thresholds(ctx, n_avg * mu_ref, log_lo, log_hi, nbins, stream,
+                               [&](const rl::MpdThresholds& a, const double* thr) {
+                                   return rl::launch_mpd(d_counts, n, a, thr, nbins + 1,
+                                                         reinterpret_cast<unsigned long long*>(d_bins), stream);
+                               });
+}
+
+rl_status rl_mpd_values(rl_context* ctx, const double* d_mu, const rl_window* win, double mu_ref,
+                        double log_lo, double log_hi, int32_t nbins, int64_t* d_bins, hipStream_t stream) {
+    g_error.clear();
+    if (!ctx) return fail(RL_E_INVALID, "context is NULL");
+    RL_TRY(check_window(win));
+    if (!d_mu) return fail(RL_E_INVALID, "map pointer is NULL");
+    RL_TRY(check_mpd_args(mu_ref, log_lo, log_hi, nbins, d_bins));
+    // magnification thresholds: mu >= mu_ref 10^edge (the count rule with n_avg = 1)
+    const int64_t n = (int64_t)win->p1 * win->p2;
+    const float c0 = (float)(std::log10(mu_ref) + log_lo);
+    const float inv_step = (float)((double)nbins / (log_hi - log_lo));
+    return mpd_with_thresholds(ctx, 1.0 * mu_ref, log_lo, log_hi, nbins, stream,
+                               [&](const rl::MpdThresholds& a, const double* thr) {
+                                   return rl::launch_mpd_values(d_mu, n, a, thr, nbins + 1, c0, inv_step,
+                                                                reinterpret_cast<unsigned long long*>(d_bins),
+                                                                stream);
+                               });
 }
 
 rl_status rl_probability_sums(rl_context* ctx, const int32_t* d_counts, const rl_window* win,

@@ -34,6 +34,11 @@ struct MpdThresholds {
 };
 hipError_t launch_mpd(const int32_t* counts, int64_t n, const MpdThresholds& args, const double* thr,
                       int nthr, unsigned long long* bins, hipStream_t stream);
+// The same binning of a map of real magnifications (thresholds mu_ref 10^edge);
+// c0 = log10 mu_ref + log_lo and inv_step = nbins / (log_hi - log_lo) only
+// guide the search (a guessed bin is kept if the thresholds confirm it).
+hipError_t launch_mpd_values(const double* mu, int64_t n, const MpdThresholds& args, const double* thr,
+                             int nthr, float c0, float inv_step, unsigned long long* bins, hipStream_t stream);
 // record word 0 counts the pixels below t_below
 hipError_t launch_prob_sum(const int32_t* counts, int64_t n, int64_t t_below,
                            unsigned long long* out, hipStream_t s);

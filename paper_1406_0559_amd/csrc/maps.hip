@@ -200,6 +200,81 @@ __global__ void __launch_bounds__(kHistThreads) mpd_kernel(const int32_t* __rest
     }
 }
 
+// Calls f(v) for every value of x[0 .. n) once, over the whole grid, with
+// 16-byte loads (two values) for the aligned body, kInFlight in flight per
+// thread, and scalar loads for a leading value and the last one.
+template <typename F>
+__device__ __forceinline__ void grid_values(const double* __restrict__ x, int64_t n, F&& f) {
+    const uintptr_t addr = reinterpret_cast<uintptr_t>(x);
+    int64_t head = (addr & 15u) ? 1 : 0;
+    if (head > n) head = n;
+    const int64_t nv = (n - head) >> 1;
+    const int64_t tail0 = head + nv * 2;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    const double2* __restrict__ v = reinterpret_cast<const double2*>(x + head);
+    int64_t k = tid;
+    for (; k + (kInFlight - 1) * nth < nv; k += kInFlight * nth) {
+        double2 q[kInFlight];
+#pragma unroll
+        for (int u = 0; u < kInFlight; ++u) q[u] = v[k + u * nth];
+#pragma unroll
+        for (int u = 0; u < kInFlight; ++u) {
+            f(q[u].x);
+            f(q[u].y);
+        }
+    }
+    for (; k < nv; k += nth) {
+        const double2 q = v[k];
+        f(q.x);
+        f(q.y);
+    }
+    if (tid < head) f(x[tid]);
+    if (tid < n - tail0) f(x[tail0 + tid]);
+}
+
+// Binned MPD of a map of real magnifications (a finite-source map): the bin
+// of a value is the number of thresholds at or below it (NaN: none), found by
+// a binary search in LDS; bins counted in `reps` interleaved LDS copies as in
+// mpd_kernel. Thresholds from the kernel argument (at most kMpdArgThr) or thr.
+// The bin is first guessed from an FP32 logarithm, g = floor((log10 mu - c0)
+// * inv_step) + 1 clamped to [0, nthr] (c0 = log10 mu_ref + log_lo, inv_step =
+// nbins / (log_hi - log_lo)), and kept only if the FP64 thresholds on either
+// side confirm it, T_(g-1) <= mu < T_g; otherwise the binary search decides.
+// The result is the threshold rule's in every case: the guess only saves the
+// search. Values that are not > 0 (zero, negative, NaN) take bin 0 at once.
+__device__ __forceinline__ int mpd_value_bin(const double* __restrict__ st, int nthr, double x, float c0,
+                                             float inv_step) {
+    if (!(x > 0.0)) return 0;
+    const float l = __log2f((float)x) * 0.30102999566f;            // log10 x, FP32
+    const float gf = fminf(fmaxf(floorf((l - c0) * inv_step) + 1.0f, 0.0f), (float)nthr);
+    const int g = (int)gf;
+    const bool lo_ok = g == 0 || st[g - 1] <= x;
+    const bool hi_ok = g == nthr || x < st[g];
+    return (lo_ok && hi_ok) ? g : mpd_bin(st, nthr, x);
+}
+
+__global__ void __launch_bounds__(kHistThreads) mpd_values_kernel(const double* __restrict__ mu, int64_t n,
+                                                         MpdThresholds targ, const double* __restrict__ thr,
+                                                         int nthr, int reps, float c0, float inv_step,
+                                                         unsigned long long* __restrict__ bins) {
+    extern __shared__ __align__(16) char smem[];
+    double* st = reinterpret_cast<double*>(smem);
+    unsigned int* sb = reinterpret_cast<unsigned int*>(st + nthr);
+    const bool in_arg = nthr <= kMpdArgThr;
+    for (int e = threadIdx.x; e < nthr; e += blockDim.x) st[e] = in_arg ? targ.t[e] : thr[e];
+    for (int e = threadIdx.x; e < (nthr + 1) * reps; e += blockDim.x) sb[e] = 0;
+    __syncthreads();
+    const int r = threadIdx.x & (reps - 1);
+    grid_values(mu, n, [&](double x) { atomicAdd(&sb[mpd_value_bin(st, nthr, x, c0, inv_step) * reps + r], 1u); });
+    __syncthreads();
+    for (int e = threadIdx.x; e <= nthr; e += blockDim.x) {
+        unsigned long long t = 0;
+        for (int q = 0; q < reps; ++q) t += sb[e * reps + q];
+        if (t) atomicAdd(&bins[e], t);
+    }
+}
+
 // Pixels with N < t_below: the host finds t_below as the first count whose
 // FP64 quotient N / N_avg is not below mu_lim (the quotient is monotone in N),
 // so this is the definition's decision, taken once per count value.
@@ -509,6 +584,18 @@ hipError_t launch_mpd(const int32_t* counts, int64_t n, const MpdThresholds& arg
                        (size_t)kMpdLut * sizeof(uint16_t);
     hipLaunchKernelGGL(mpd_kernel, dim3(grid_for(n, kHistThreads * 16, kHistBlocks)), dim3(kHistThreads), lds, s,
                        counts, n, args, thr, nthr, reps, bins);
+    return hipGetLastError();
+}
+
+hipError_t launch_mpd_values(const double* mu, int64_t n, const MpdThresholds& args, const double* thr,
+                             int nthr, float c0, float inv_step, unsigned long long* bins, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t fixed = (int64_t)nthr * (int64_t)sizeof(double);
+    const int64_t spare = (65536 - fixed) / (int64_t)sizeof(unsigned int);
+    const int reps = hist_reps(nthr + 1, spare < kHistLds ? spare : kHistLds);
+    const size_t lds = (size_t)nthr * sizeof(double) + (size_t)(nthr + 1) * reps * sizeof(unsigned int);
+    hipLaunchKernelGGL(mpd_values_kernel, dim3(grid_for(n, kHistThreads * 8, kHistBlocks)), dim3(kHistThreads), lds,
+                       s, mu, n, args, thr, nthr, reps, c0, inv_step, bins);
     return hipGetLastError();
 }
 

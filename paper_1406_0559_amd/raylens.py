@@ -106,6 +106,7 @@ def load():
         "rl_shoot_batch": [vp, P(rl_map_desc), i32, C.c_int, vp],
         "rl_count_histogram": [vp, vp, P(rl_window), i64, vp, vp],
         "rl_mpd": [vp, vp, P(rl_window), dbl, dbl, dbl, dbl, i32, vp, vp],
+        "rl_mpd_values": [vp, vp, P(rl_window), dbl, dbl, dbl, i32, vp, vp],
         "rl_probability_sums": [vp, vp, P(rl_window), dbl, dbl, P(i64), P(i64), vp],
         "rl_mpd_moments": [vp, vp, i32, i32, i64, vp, vp, vp],
         "rl_codec_encode": [vp, vp, P(rl_window), vp, i64, vp, i64, P(i64), P(i32), vp],
@@ -214,6 +215,10 @@ def rl_count_histogram(ctx, d_counts, win, n_values, d_hist, stream=None):
 def rl_mpd(ctx, d_counts, win, n_avg, mu_ref, log_lo, log_hi, nbins, d_bins, stream=None):
     _check(load().rl_mpd(ctx, d_counts, C.byref(win), n_avg, mu_ref, log_lo, log_hi, nbins, d_bins,
                          stream))
+
+
+def rl_mpd_values(ctx, d_mu, win, mu_ref, log_lo, log_hi, nbins, d_bins, stream=None):
+    _check(load().rl_mpd_values(ctx, d_mu, C.byref(win), mu_ref, log_lo, log_hi, nbins, d_bins, stream))
 
 
 def rl_probability_sums(ctx, d_counts, win, n_avg, mu_lim, stream=None):
@@ -454,6 +459,18 @@ class Context:
         _dev(bins, torch.int64, int(nbins) + 2, "bins", self.device)
         rl_mpd(self.handle, counts.data_ptr(), window_of(spec), n_avg, mu_ref, log_lo, log_hi,
                int(nbins), bins.data_ptr(), _stream_ptr(stream))
+        return bins
+
+    def mpd_values(self, mu, spec, mu_ref, log_lo, log_hi, nbins, bins=None, stream=None):
+        """The binned MPD of a map of real magnifications (e.g. a finite-source
+        map from convolve): [underflow, nbins bins, overflow]."""
+        torch = _torch()
+        _dev(mu, torch.float64, spec.p1 * spec.p2, "mu", self.device)
+        if bins is None:
+            bins = torch.zeros(int(nbins) + 2, dtype=torch.int64, device=mu.device)
+        _dev(bins, torch.int64, int(nbins) + 2, "bins", self.device)
+        rl_mpd_values(self.handle, mu.data_ptr(), window_of(spec), mu_ref, log_lo, log_hi, int(nbins),
+                      bins.data_ptr(), _stream_ptr(stream))
         return bins
 
     def probability_sums(self, counts, spec, mu_lim, n_avg=None, stream=None):

@@ -164,6 +164,23 @@ def test_autotune_validates_on_the_host(tmp_path):
         rl.rl_destroy(ctx)
 
 
+def test_mpd_of_real_maps_validates_on_the_host():
+    lib = rl.load()
+    ctx = rl.rl_create(0)
+    try:
+        w = rl.rl_window(64, 64, 0.0, 0.0, 2.0, 2.0)
+        fake = C.c_void_p(0x1000)
+        bad = [(None, w, 1.0, -1.0, 1.0, 10, fake), (fake, w, 0.0, -1.0, 1.0, 10, fake),
+               (fake, w, math.inf, -1.0, 1.0, 10, fake), (fake, w, 1.0, 1.0, -1.0, 10, fake),
+               (fake, w, 1.0, -1.0, math.nan, 10, fake), (fake, w, 1.0, -1.0, 1.0, 0, fake),
+               (fake, w, 1.0, -1.0, 1.0, 4097, fake), (fake, w, 1.0, -1.0, 1.0, 10, None),
+               (fake, rl.rl_window(0, 64, 0.0, 0.0, 2.0, 2.0), 1.0, -1.0, 1.0, 10, fake)]
+        for mu, ww, ref, lo, hi, nb, bins in bad:
+            assert lib.rl_mpd_values(ctx, mu, C.byref(ww), ref, lo, hi, nb, bins, None) == rl.RL_E_INVALID
+    finally:
+        rl.rl_destroy(ctx)
+
+
 def test_binding_constants_match_the_header():
     text = open(os.path.join(ROOT, "include", "raylens.h")).read()
     for name in ("RL_NOALLOC_MAX_LENSES", "RL_MAX_CONVOLVE_BATCH"):
