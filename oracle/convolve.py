@@ -67,6 +67,36 @@ def source_kernel(shape, p1, p2, pix1, pix2, radius, hole=0.0, subsamples=SUBSAM
     return K / total
 
 
+def table_kernel(x, y, b, p1, p2, pix1, pix2):
+    """Kernel of a tabulated profile (the disc profiles of Section 3.1 stored
+    as profile.bin: N_x x values, N_y y values, then N_x N_y brightness values,
+    x fastest), positions in the map's units: each pixel (i, j) around the
+    source centre sums the brightness of the samples it holds, sample (x, y)
+    being in pixel (floor(x / pix1 + 1/2), floor(y / pix2 + 1/2)); the sums are
+    taken in the table's order (y, then x), centred on pixel (0, 0) with
+    wrap-around and normalised to unit sum like source_kernel."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64).reshape(len(y), len(x))
+    ix = np.floor(x / pix1 + 0.5).astype(np.int64)
+    iy = np.floor(y / pix2 + 0.5).astype(np.int64)
+    h1, h2 = int(np.abs(ix).max()), int(np.abs(iy).max())
+    if 2 * h1 + 1 > p1 or 2 * h2 + 1 > p2:
+        raise ValueError("source larger than the map")
+    compact = np.zeros((2 * h2 + 1, 2 * h1 + 1), np.float64)
+    for ky in range(len(y)):
+        for kx in range(len(x)):
+            compact[iy[ky] + h2, ix[kx] + h1] += b[ky, kx]
+    total = compact.sum()
+    if not total > 0:
+        raise ValueError("empty source kernel")
+    K = np.zeros((p2, p1), np.float64)
+    for j in range(-h2, h2 + 1):
+        for i in range(-h1, h1 + 1):
+            K[j % p2, i % p1] = compact[j + h2, i + h1] / total
+    return K
+
+
 def convolve(counts, kernel, n_avg=1.0):
     """C = F^-1[F(M) F(K)] / n_avg in FP64 (eq. 6); circular."""
     M = np.asarray(counts, dtype=np.float64)

@@ -131,3 +131,53 @@ def test_fft_convolution_with_an_asymmetric_kernel_equals_the_defining_sum():
     K[:4, :3] = rng.random((4, 3))
     K[-2:, -1] = rng.random(2)
     assert np.allclose(cv.convolve(M, K, 3.0), cv.convolve_direct(M, K, 3.0), rtol=0, atol=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# Kernels of tabulated profiles (profile.bin)
+# ---------------------------------------------------------------------------
+
+def subsample_table(shape, radius, hole, pix1, pix2, n1, n2, s=8):
+    """A profile tabulated at the sub-sample points that source_kernel
+    averages over, pixels -n .. n on each axis: float32 positions, as the
+    files store them."""
+    off = (np.arange(s) + 0.5) / s - 0.5
+    x = ((np.arange(-n1, n1 + 1)[:, None] + off[None, :]).ravel() * pix1).astype(np.float32)
+    y = ((np.arange(-n2, n2 + 1)[:, None] + off[None, :]).ravel() * pix2).astype(np.float32)
+    X, Y = np.meshgrid(x.astype(np.float64), y.astype(np.float64))
+    b = cv.brightness(shape, np.hypot(X, Y), radius, hole).astype(np.float32)
+    return x, y, b
+
+
+@pytest.mark.parametrize("shape,R,hole", [("uniform", 3.3, 0.0), ("gaussian", 4.1, 0.0), ("power", 5.2, 0.7)])
+def test_table_kernel_at_the_subsample_points_is_the_analytic_kernel(shape, R, hole):
+    """Tabulated at the points where source_kernel samples the profile, a
+    profile binned by table_kernel gives source_kernel's kernel: each pixel
+    holds the same 64 samples, summed instead of averaged, and both kernels
+    are normalised (to float32 precision of the tabulated brightness)."""
+    pix1, pix2, p1, p2 = 1.0, 0.8, 48, 40
+    n1, n2 = int(math.ceil(R / pix1)), int(math.ceil(R / pix2))
+    x, y, b = subsample_table(shape, R, hole, pix1, pix2, n1, n2)
+    got = cv.table_kernel(x, y, b, p1, p2, pix1, pix2)
+    ref = cv.source_kernel(shape, p1, p2, pix1, pix2, R, hole)
+    assert np.abs(got - ref).max() <= 1e-6 * ref.max()
+    assert abs(got.sum() - 1.0) < 1e-12
+
+
+def test_table_kernel_of_one_sample_is_a_delta():
+    K = cv.table_kernel([0.0], [0.0], [5.0], 16, 8, 1.0, 1.0)
+    assert K[0, 0] == 1.0 and K.sum() == 1.0
+    # off-centre sample: pixel (floor(x / pix + 1/2), ...), wrapped
+    K = cv.table_kernel([-1.49], [2.51], [2.0], 16, 8, 1.0, 1.0)
+    assert K[3, 16 - 1] == 1.0 and K.sum() == 1.0
+
+
+def test_table_kernel_box_edges_are_half_open():
+    """A sample exactly on a box edge x = (i + 1/2) pix belongs to pixel i + 1."""
+    K = cv.table_kernel([0.5, -0.5], [0.0], [1.0, 3.0], 8, 8, 1.0, 1.0)
+    assert K[0, 1] == 0.25 and K[0, 0] == 0.75
+
+
+def test_table_kernel_of_a_source_too_large_is_refused():
+    with pytest.raises(ValueError):
+        cv.table_kernel([-5.0, 5.0], [0.0], [1.0, 1.0], 8, 8, 1.0, 1.0)

@@ -96,6 +96,12 @@ PY_MUTANTS = {
                     "I = (np.maximum(r, core) / radius) ** (-0.5)"),
     "hole-ignored": ("return np.where((r < radius) & (r >= hole), I, 0.0)",
                      "return np.where(r < radius, I, 0.0)"),
+    "table-boxes-not-centred": ("ix = np.floor(x / pix1 + 0.5).astype(np.int64)",
+                                "ix = np.floor(x / pix1).astype(np.int64)"),
+    "table-axes-swapped": ("compact[iy[ky] + h2, ix[kx] + h1] += b[ky, kx]",
+                           "compact[iy[ky] + h2, ix[kx] + h1] += b.T.reshape(b.shape)[ky, kx]"),
+    "table-not-normalised": ("K[j % p2, i % p1] = compact[j + h2, i + h1] / total",
+                             "K[j % p2, i % p1] = compact[j + h2, i + h1]"),
 }
 
 _BOOT = """
