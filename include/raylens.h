@@ -405,6 +405,26 @@ typedef struct {
 rl_status rl_source_kernel(rl_context* ctx, const rl_profile* profile, const rl_window* win,
                            double* d_kernel, hipStream_t stream);
 
+/* Largest axis of a tabulated profile accepted by rl_source_kernel_table. */
+#define RL_MAX_TABLE_AXIS 16384
+
+/* Convolution kernel of a tabulated source profile (Section 3.1: the disc
+ * profiles are given as tables, stored as N_x x positions, N_y y positions,
+ * then N_x N_y brightness values with x fastest). h_x[nx], h_y[ny] and
+ * h_b[ny x nx] are HOST arrays of FP32, positions in Einstein radii relative
+ * to the source centre, in any order; the library copies them before it
+ * returns. Sample (x, y) lies in pixel (floor(x / pix1 + 1/2),
+ * floor(y / pix2 + 1/2)), pix = width / p, taken in FP64; each pixel sums its
+ * samples in table order (y, then x), and the kernel is centred on pixel
+ * (0, 0) with wrap-around and normalised to unit sum like rl_source_kernel.
+ * d_kernel is double[p2 x p1], overwritten. Errors (RL_E_INVALID, nothing
+ * launched): 1 <= nx, ny <= RL_MAX_TABLE_AXIS violated, a position not
+ * finite, a pixel box 2 h + 1 wider than p on either axis, a brightness not
+ * finite or negative, or every brightness 0. Asynchronous. */
+rl_status rl_source_kernel_table(rl_context* ctx, const float* h_x, int32_t nx, const float* h_y, int32_t ny,
+                                 const float* h_b, const rl_window* win, double* d_kernel,
+                                 hipStream_t stream);
+
 /* Finite-source map (Section 2.4, eq. 6): d_out = F^-1[F(M) F(K)] / n_avg, the
  * circular convolution of the count map M (int32, p2 x p1) with the kernel K
  * (double, p2 x p1, e.g. from rl_source_kernel) divided by n_avg (pass N_avg

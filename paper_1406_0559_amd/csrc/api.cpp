@@ -1062,6 +1062,65 @@ rl_status rl_source_kernel(rl_context* ctx, const rl_profile* profile, const rl_
     return RL_OK;
 }
 
+rl_status rl_source_kernel_table(rl_context* ctx, const float* h_x, int32_t nx, const float* h_y, int32_t ny,
+                                 const float* h_b, const rl_window* win, double* d_kernel, hipStream_t stream) {
+    g_error.clear();
+    if (!ctx) return fail(RL_E_INVALID, "context is NULL");
+    RL_TRY(check_window(win));
+    if (!h_x || !h_y || !h_b || !d_kernel) return fail(RL_E_INVALID, "pointers are NULL");
+    if (nx < 1 || ny < 1 || nx > RL_MAX_TABLE_AXIS || ny > RL_MAX_TABLE_AXIS)
+        return fail(RL_E_INVALID, "table axes must hold 1 .. RL_MAX_TABLE_AXIS samples");
+    const double pix1 = win->width1 / (double)win->p1, pix2 = win->width2 / (double)win->p2;
+    // The half-widths of the pixel box, in the same FP64 arithmetic as the bins
+    // the kernels compute; a position too far out for an int is refused first.
+    auto half = [](const float* v, int32_t n, double pix, int32_t p, int32_t* h) -> bool {
+        double m = 0.0;
+        for (int32_t k = 0; k < n; ++k) {
+            if (!is_finite(v[k])) return false;
+            const double c = std::floor((double)v[k] / pix + 0.5);
+            m = std::max(m, std::fabs(c));
+        }
+        if (2.0 * m + 1.0 > (double)p) return false;
+        *h = (int32_t)m;
+        return true;
+    };
+    int32_t h1 = 0, h2 = 0;
+    if (!half(h_x, nx, pix1, win->p1, &h1) || !half(h_y, ny, pix2, win->p2, &h2))
+        return fail(RL_E_INVALID, "table positions must be finite and the source no larger than the map");
+    bool any = false;
+    const int64_t nb = (int64_t)nx * ny;
+    for (int64_t k = 0; k < nb; ++k) {
+        if (!is_finite(h_b[k]) || h_b[k] < 0.0f)
+            return fail(RL_E_INVALID, "table brightness must be finite and >= 0");
+        any = any || h_b[k] > 0.0f;
+    }
+    if (!any) return fail(RL_E_INVALID, "empty source kernel: every brightness is 0");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return hip_fail(dg.err, "hipSetDevice");
+    RL_TRY(ensure_ready(ctx));
+    const size_t off = rl::table_data_offset(nx, ny, h1, h2);
+    const size_t bytes = ((size_t)nx + ny + (size_t)nb) * sizeof(float);
+    hipError_t e = ctx->aux.acquire(rl::table_scratch_bytes(nx, ny, h1, h2), stream);
+    if (e != hipSuccess) return hip_fail(e, "table scratch");
+    char* host = nullptr;
+    rl_status st = stage_reserve(ctx, bytes, &host);
+    if (st == RL_OK) {
+        std::memcpy(host, h_x, (size_t)nx * sizeof(float));
+        std::memcpy(host + (size_t)nx * sizeof(float), h_y, (size_t)ny * sizeof(float));
+        std::memcpy(host + ((size_t)nx + ny) * sizeof(float), h_b, (size_t)nb * sizeof(float));
+        st = stage_send(ctx, static_cast<char*>(ctx->aux.ptr) + off, bytes, stream);
+    }
+    if (st != RL_OK) {
+        (void)ctx->aux.release(stream);
+        return st;
+    }
+    e = rl::launch_table_kernel(nx, ny, pix1, pix2, h1, h2, win->p1, win->p2, d_kernel, ctx->aux.ptr, stream);
+    hipError_t e2 = ctx->aux.release(stream);
+    if (e == hipSuccess) e = e2;
+    if (e != hipSuccess) return hip_fail(e, "table kernel launch");
+    return RL_OK;
+}
+
 }  // extern "C"
 
 namespace {

@@ -1131,6 +1131,63 @@ __global__ void __launch_bounds__(256) fill_source_kernel(const double* __restri
     k[(int64_t)jj * p1 + ii] = v;
 }
 
+// Tabulated profiles. Sample k of an axis with positions v lies in pixel
+// floor(v[k] / pix + 1/2), taken in FP64 from the FP32 position; bins[k] holds
+// that pixel + h (0 .. 2 h). The x and y axes share one launch: k < nx is x.
+__global__ void __launch_bounds__(256) table_bins_kernel(const float* __restrict__ x, int nx,
+                                                         const float* __restrict__ y, int ny, double pix1,
+                                                         double pix2, int h1, int h2, int32_t* __restrict__ bins) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nx) bins[k] = (int)floor((double)x[k] / pix1 + 0.5) + h1;
+    else if (k < nx + ny) bins[k] = (int)floor((double)y[k - nx] / pix2 + 0.5) + h2;
+}
+
+// Stable bucket order of one axis (n samples, bins 0 .. nb - 1): sample k goes
+// to order[start[bin k] + number of earlier samples in its bin], start[b] =
+// number of samples in bins below b, start[nb] = n. Each thread counts over the
+// whole axis, which holds thousands of samples at most.
+__global__ void __launch_bounds__(256) table_order_kernel(const int32_t* __restrict__ bins, int n, int nb,
+                                                          int32_t* __restrict__ order, int32_t* __restrict__ start) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) {
+        const int bt = bins[t];
+        int r = 0;
+        for (int k = 0; k < n; ++k) {
+            const int b = bins[k];
+            r += (b < bt) | ((b == bt) & (k < t));
+        }
+        order[r] = t;
+    }
+    if (t <= nb) {
+        int c = 0;
+        for (int k = 0; k < n; ++k) c += bins[k] < t;
+        start[t] = c;
+    }
+}
+
+// Pixel (i, j) of the compact (2 h1 + 1) x (2 h2 + 1) box sums the brightness
+// of the samples it holds in the table's order: rows ky ascending, then
+// columns kx ascending, starting from 0.
+__global__ void __launch_bounds__(256) table_samples_kernel(const float* __restrict__ b, int nx,
+                                                            const int32_t* __restrict__ ox,
+                                                            const int32_t* __restrict__ sx,
+                                                            const int32_t* __restrict__ oy,
+                                                            const int32_t* __restrict__ sy, int h1, int h2,
+                                                            double* __restrict__ compact) {
+    const int w = 2 * h1 + 1;
+    const int64_t total = (int64_t)w * (2 * h2 + 1);
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(q % w), j = (int)(q / w);
+        double s = 0.0;
+        for (int a = sy[j]; a < sy[j + 1]; ++a) {
+            const float* row = b + (int64_t)oy[a] * nx;
+            for (int c = sx[i]; c < sx[i + 1]; ++c) s += (double)row[ox[c]];
+        }
+        compact[q] = s;
+    }
+}
+
 int grid_of(int64_t n, int cap) {
     int64_t g = (n + 255) / 256;
     return (int)(g < 1 ? 1 : (g > cap ? cap : g));
@@ -1252,6 +1309,46 @@ hipError_t launch_convolve(const int32_t* counts, const double* const* kernels, 
 
 size_t source_scratch_bytes(int h1, int h2) {
     return ((size_t)(2 * h1 + 1) * (2 * h2 + 1) + 2) * sizeof(double) + 256;
+}
+
+// Table scratch: total (2 doubles), compact box, then int32 bins (nx + ny),
+// orders (nx + ny), starts (2 h1 + 2, 2 h2 + 2), then the FP32 table
+// (x, y, b) that the caller copies in at table_data_offset.
+size_t table_data_offset(int nx, int ny, int h1, int h2) {
+    const size_t ints = 2 * ((size_t)nx + ny) + (2 * (size_t)h1 + 2) + (2 * (size_t)h2 + 2);
+    const size_t off = ((size_t)(2 * h1 + 1) * (2 * h2 + 1) + 2) * sizeof(double) + ints * sizeof(int32_t);
+    return (off + 255) & ~(size_t)255;
+}
+
+size_t table_scratch_bytes(int nx, int ny, int h1, int h2) {
+    return table_data_offset(nx, ny, h1, h2) + ((size_t)nx + ny + (size_t)nx * ny) * sizeof(float) + 256;
+}
+
+hipError_t launch_table_kernel(int nx, int ny, double pix1, double pix2, int h1, int h2, int p1, int p2,
+                               double* kernel, void* scratch, hipStream_t s) {
+    const int64_t m = (int64_t)(2 * h1 + 1) * (2 * h2 + 1);
+    double* total = static_cast<double*>(scratch);
+    double* compact = total + 2;
+    int32_t* bins = reinterpret_cast<int32_t*>(compact + m);
+    int32_t* ox = bins + nx + ny;
+    int32_t* oy = ox + nx;
+    int32_t* sx = oy + ny;
+    int32_t* sy = sx + 2 * h1 + 2;
+    const float* x = reinterpret_cast<const float*>(static_cast<char*>(scratch) + table_data_offset(nx, ny, h1, h2));
+    const float* y = x + nx;
+    const float* b = y + ny;
+    hipLaunchKernelGGL(table_bins_kernel, dim3((nx + ny + 255) / 256), dim3(256), 0, s, x, nx, y, ny, pix1, pix2,
+                       h1, h2, bins);
+    hipLaunchKernelGGL(table_order_kernel, dim3((std::max(nx, 2 * h1 + 2) + 255) / 256), dim3(256), 0, s, bins,
+                       nx, 2 * h1 + 1, ox, sx);
+    hipLaunchKernelGGL(table_order_kernel, dim3((std::max(ny, 2 * h2 + 2) + 255) / 256), dim3(256), 0, s,
+                       bins + nx, ny, 2 * h2 + 1, oy, sy);
+    hipLaunchKernelGGL(table_samples_kernel, dim3((unsigned)std::min<int64_t>((m + 255) / 256, 65536)), dim3(256),
+                       0, s, b, nx, ox, sx, oy, sy, h1, h2, compact);
+    hipLaunchKernelGGL(ordered_sum_kernel, dim3(1), dim3(1024), 0, s, compact, m, total);
+    hipLaunchKernelGGL(fill_source_kernel, dim3((p1 + 255) / 256, p2), dim3(256), 0, s, compact, h1, h2, p1,
+                       p2, total, kernel);
+    return hipGetLastError();
 }
 
 hipError_t launch_source_kernel(int shape, double radius, double hole, double pix1, double pix2,

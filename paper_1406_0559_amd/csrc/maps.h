@@ -76,6 +76,10 @@ size_t source_scratch_bytes(int h1, int h2);
 hipError_t launch_source_kernel(int shape, double radius, double hole, double pix1, double pix2,
                                 int h1, int h2, int p1, int p2, double* kernel, double* scratch,
                                 hipStream_t stream);
+size_t table_data_offset(int nx, int ny, int h1, int h2);
+size_t table_scratch_bytes(int nx, int ny, int h1, int h2);
+hipError_t launch_table_kernel(int nx, int ny, double pix1, double pix2, int h1, int h2, int p1, int p2,
+                               double* kernel, void* scratch, hipStream_t stream);
 constexpr int kMaxFftSide = 10240;
 
 }  // namespace rl

@@ -112,6 +112,7 @@ def load():
         "rl_codec_encode": [vp, vp, P(rl_window), vp, i64, vp, i64, P(i64), P(i32), vp],
         "rl_codec_decode": [vp, vp, i32, vp, i64, P(rl_window), vp, vp],
         "rl_source_kernel": [vp, P(rl_profile), P(rl_window), vp, vp],
+        "rl_source_kernel_table": [vp, vp, i32, vp, i32, vp, P(rl_window), vp, vp],
         "rl_convolve": [vp, vp, vp, P(rl_window), dbl, vp, vp],
         "rl_convolve_batch": [vp, vp, P(vp), i32, P(rl_window), dbl, P(vp), vp],
         "rl_autotune": [vp, C.c_char_p, i32],
@@ -178,6 +179,7 @@ def rl_shoot_noalloc(ctx, lenses, macro, grid, win, precision, row_begin, row_en
 
 RL_NOALLOC_MAX_LENSES = 131072   # include/raylens.h
 RL_MAX_CONVOLVE_BATCH = 4096     # include/raylens.h
+RL_MAX_TABLE_AXIS = 16384        # include/raylens.h
 
 
 def rl_normalise(ctx, d_counts, win, n_avg, d_mu, stream=None):
@@ -249,6 +251,26 @@ def rl_codec_decode(ctx, d_packed, bits, d_values, n_distinct, win, d_counts, st
 
 def rl_source_kernel(ctx, profile, win, d_kernel, stream=None):
     _check(load().rl_source_kernel(ctx, C.byref(profile), C.byref(win), d_kernel, stream))
+
+
+def rl_source_kernel_table(ctx, h_x, nx, h_y, ny, h_b, win, d_kernel, stream=None):
+    _check(load().rl_source_kernel_table(ctx, h_x, nx, h_y, ny, h_b, C.byref(win), d_kernel, stream))
+
+
+def read_profile_table(path):
+    """A tabulated source profile file (Section 3.1): int32 N_x, int32 N_y,
+    then FP32 x[N_x], y[N_y] and brightness[N_y x N_x], x fastest, all
+    little-endian. Returns (x, y, b) as numpy float32 arrays, b of shape
+    (N_y, N_x)."""
+    import numpy as np
+    raw = np.fromfile(path, dtype=np.uint8)
+    if raw.size < 8:
+        raise ValueError(f"{path}: too short for a profile table header")
+    nx, ny = (int(v) for v in raw[:8].view("<i4"))
+    if nx < 1 or ny < 1 or raw.size != 8 + 4 * (nx + ny + nx * ny):
+        raise ValueError(f"{path}: header {nx} x {ny} does not match the file size {raw.size}")
+    body = raw[8:].view("<f4").astype(np.float32)
+    return body[:nx].copy(), body[nx:nx + ny].copy(), body[nx + ny:].reshape(ny, nx).copy()
 
 
 def rl_convolve(ctx, d_counts, d_kernel, win, n_avg, d_out, stream=None):
@@ -530,6 +552,24 @@ class Context:
         _dev(kernel, torch.float64, spec.p1 * spec.p2, "kernel", self.device)
         rl_source_kernel(self.handle, rl_profile(PROFILES[shape], radius, hole), window_of(spec),
                          kernel.data_ptr(), _stream_ptr(stream))
+        return kernel
+
+    def source_kernel_table(self, spec, x, y, b, kernel=None, stream=None):
+        """Kernel of a tabulated profile: x[N_x], y[N_y] positions in Einstein
+        radii around the source centre, b[N_y, N_x] brightness (x fastest),
+        host arrays converted to contiguous FP32."""
+        import numpy as np
+        torch = _torch()
+        x = np.ascontiguousarray(x, dtype=np.float32).ravel()
+        y = np.ascontiguousarray(y, dtype=np.float32).ravel()
+        b = np.ascontiguousarray(b, dtype=np.float32).ravel()
+        if b.size != x.size * y.size:
+            raise ValueError(f"brightness holds {b.size} values, not {y.size} x {x.size}")
+        if kernel is None:
+            kernel = torch.empty((spec.p2, spec.p1), dtype=torch.float64, device=f"cuda:{self.device}")
+        _dev(kernel, torch.float64, spec.p1 * spec.p2, "kernel", self.device)
+        rl_source_kernel_table(self.handle, x.ctypes.data, x.size, y.ctypes.data, y.size, b.ctypes.data,
+                               window_of(spec), kernel.data_ptr(), _stream_ptr(stream))
         return kernel
 
     def convolve(self, counts, kernel, spec, n_avg=1.0, out=None, stream=None):

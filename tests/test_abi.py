@@ -183,7 +183,7 @@ def test_mpd_of_real_maps_validates_on_the_host():
 
 def test_binding_constants_match_the_header():
     text = open(os.path.join(ROOT, "include", "raylens.h")).read()
-    for name in ("RL_NOALLOC_MAX_LENSES", "RL_MAX_CONVOLVE_BATCH"):
+    for name in ("RL_NOALLOC_MAX_LENSES", "RL_MAX_CONVOLVE_BATCH", "RL_MAX_TABLE_AXIS"):
         m = re.search(r"^#define\s+" + name + r"\s+(\d+)", text, flags=re.M)
         assert m, name
         assert int(m.group(1)) == getattr(rl, name), name
@@ -299,6 +299,22 @@ def test_convolution_entry_points_validate_on_the_host():
         assert "output 1 is kernel 2" in rl.rl_last_error()
         onto_map = (V * 3)(0x4000, 0x1000, 0x6000)        # output 1 is the map (fake)
         assert lib.rl_convolve_batch(ctx, fake, ks, 3, C.byref(w), 1.0, onto_map, None) == rl.RL_E_INVALID
+        # tabulated profiles: axis sizes, positions, brightness, box size
+        F = C.c_float
+        xs = (F * 3)(-0.02, 0.0, 0.02)
+        b9 = (F * 9)(*([1.0] * 9))
+        table = lambda x, nx, y, ny, b, ww=w: lib.rl_source_kernel_table(ctx, x, nx, y, ny, b, C.byref(ww),
+                                                                         fake, None)
+        assert table(xs, 0, xs, 3, b9) == rl.RL_E_INVALID
+        assert table(xs, 3, xs, rl.RL_MAX_TABLE_AXIS + 1, b9) == rl.RL_E_INVALID
+        assert table(None, 3, xs, 3, b9) == rl.RL_E_INVALID
+        assert table(xs, 3, xs, 3, None) == rl.RL_E_INVALID
+        for bad_x in ((F * 3)(-0.02, math.nan, 0.02), (F * 3)(-0.02, 0.0, 1.5)):
+            assert table(bad_x, 3, xs, 3, b9) == rl.RL_E_INVALID, list(bad_x)
+        assert "larger than the map" in rl.rl_last_error()
+        for bad_b in ((F * 9)(*([1.0] * 8 + [-1.0])), (F * 9)(*([1.0] * 8 + [math.inf])), (F * 9)(*([0.0] * 9))):
+            assert table(xs, 3, xs, 3, bad_b) == rl.RL_E_INVALID, list(bad_b)
+        assert "every brightness is 0" in rl.rl_last_error()
     finally:
         rl.rl_destroy(ctx)
 
@@ -335,3 +351,22 @@ def test_binding_refuses_host_tensors_before_any_library_call():
                 call()
     finally:
         ctx.close()
+
+
+def test_profile_table_reader(tmp_path):
+    """read_profile_table: int32 N_x, N_y, then FP32 x, y and brightness (x
+    fastest); a header that does not match the size is refused."""
+    import numpy as np
+    x = np.array([-0.5, 0.0, 0.5], np.float32)
+    y = np.array([-1.0, 1.0], np.float32)
+    b = np.arange(6, dtype=np.float32).reshape(2, 3)
+    f = tmp_path / "profile.bin"
+    with open(f, "wb") as fh:
+        fh.write(np.array([3, 2], "<i4").tobytes() + x.astype("<f4").tobytes() + y.astype("<f4").tobytes()
+                 + b.astype("<f4").tobytes())
+    gx, gy, gb = rl.read_profile_table(f)
+    assert np.array_equal(gx, x) and np.array_equal(gy, y) and np.array_equal(gb, b)
+    short = tmp_path / "short.bin"
+    short.write_bytes(f.read_bytes()[:-4])
+    with pytest.raises(ValueError):
+        rl.read_profile_table(short)

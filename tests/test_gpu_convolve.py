@@ -35,6 +35,73 @@ def test_source_kernel_matches_the_oracle(ctx, shape, radius, hole):
     assert abs(k.sum() - 1.0) < 1e-12
 
 
+def subsample_table(shape, radius, hole, pix1, pix2, n1, n2, s=8):
+    """The profile tabulated at the 8 x 8 sub-sample points of pixels -n .. n
+    on each axis (ascending, as profile files store them), FP32."""
+    off = (np.arange(s) + 0.5) / s - 0.5
+    x = ((np.arange(-n1, n1 + 1)[:, None] + off[None, :]).ravel() * pix1).astype(np.float32)
+    y = ((np.arange(-n2, n2 + 1)[:, None] + off[None, :]).ravel() * pix2).astype(np.float32)
+    X, Y = np.meshgrid(x.astype(np.float64), y.astype(np.float64))
+    return x, y, ocv.brightness(shape, np.hypot(X, Y), radius, hole).astype(np.float32)
+
+
+@pytest.mark.parametrize("shape,radius,hole", [("uniform", 0.237, 0.0), ("gaussian", 0.311, 0.0),
+                                               ("power", 0.419, 0.05)])
+def test_table_kernel_matches_the_oracle_and_the_analytic_kernel(ctx, shape, radius, hole):
+    """A profile tabulated at the analytic kernel's sub-sample points: the
+    GPU table kernel equals the oracle's to rounding of the normalisation and
+    the analytic kernel to FP32 precision of the table."""
+    spec = spec_of(128, 64, 4.0, 3.0)
+    pix1, pix2 = spec.W1 / spec.p1, spec.W2 / spec.p2
+    n1, n2 = int(np.ceil(radius / pix1)), int(np.ceil(radius / pix2))
+    x, y, b = subsample_table(shape, radius, hole, pix1, pix2, n1, n2)
+    k = ctx.source_kernel_table(spec, x, y, b).cpu().numpy()
+    ref = ocv.table_kernel(x, y, b, spec.p1, spec.p2, pix1, pix2)
+    assert np.abs(k - ref).max() <= 1e-13 * ref.max()
+    assert abs(k.sum() - 1.0) < 1e-12
+    ana = ctx.source_kernel(spec, shape, radius, hole).cpu().numpy()
+    assert np.abs(k - ana).max() <= 1e-6 * ana.max()
+
+
+@pytest.mark.parametrize("seed,nx,ny,p1,p2", [(1, 37, 53, 64, 48), (2, 1, 1, 16, 16), (3, 300, 7, 256, 30),
+                                              (4, 1000, 1000, 1024, 1024)])
+def test_table_kernel_of_unordered_tables(ctx, seed, nx, ny, p1, p2):
+    """Positions in random order, some exactly on pixel edges (pix = 1/32 and
+    1/64, so the edges are FP32 numbers), repeated positions and zero
+    brightness: the same pixels and per-pixel sums as the oracle."""
+    rng = np.random.default_rng(seed)
+    spec = spec_of(p1, p2, p1 / 32.0, p2 / 64.0)
+    pix1, pix2 = spec.W1 / spec.p1, spec.W2 / spec.p2
+    hx, hy = min(p1 // 2 - 1, 9), min(p2 // 2 - 1, 9)
+    x = rng.uniform(-hx * pix1, hx * pix1, nx)
+    y = rng.uniform(-hy * pix2, hy * pix2, ny)
+    x[: nx // 4] = (rng.integers(-hx, hx, nx // 4) + 0.5) * pix1      # on box edges
+    y[: ny // 4] = (rng.integers(-hy, hy, ny // 4) + 0.5) * pix2
+    if nx > 3:
+        x[-1] = x[-2]
+    b = rng.exponential(1.0, (ny, nx))
+    b[rng.random((ny, nx)) < 0.2] = 0.0
+    b.flat[0] = 1.0
+    x, y, b = x.astype(np.float32), y.astype(np.float32), b.astype(np.float32)
+    k = ctx.source_kernel_table(spec, x, y, b).cpu().numpy()
+    ref = ocv.table_kernel(x, y, b, p1, p2, pix1, pix2)
+    assert np.array_equal(k != 0, ref != 0)
+    assert np.abs(k - ref).max() <= 1e-13 * ref.max()
+    assert abs(k.sum() - 1.0) < 1e-12
+
+
+def test_convolution_with_a_table_kernel(ctx):
+    """The table kernel feeds the convolution like the analytic one."""
+    rng = np.random.default_rng(11)
+    spec = spec_of(256, 256)
+    x, y, b = subsample_table("gaussian", 0.2, 0.0, 4.0 / 256, 4.0 / 256, 13, 13)
+    counts = torch.from_numpy(rng.poisson(50.0, (256, 256)).astype(np.int32)).cuda()
+    k = ctx.source_kernel_table(spec, x, y, b)
+    out = ctx.convolve(counts, k, spec, 50.0).cpu().numpy()
+    ref = ocv.convolve(counts.cpu().numpy(), ocv.table_kernel(x, y, b, 256, 256, 4.0 / 256, 4.0 / 256), 50.0)
+    assert np.abs(out - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
 # Powers of two, mixed radices (2, 3, 4, 5), odd sides, rows longer than 4096
 # (the 160 KiB LDS class) and columns longer than 5120 (the split pass); then
 # every side of the three-pass path (256 .. 8192 and 10000) along each axis,
