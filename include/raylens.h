@@ -408,14 +408,15 @@ rl_status rl_source_kernel(rl_context* ctx, const rl_profile* profile, const rl_
 /* Largest axis of a tabulated profile accepted by rl_source_kernel_table. */
 #define RL_MAX_TABLE_AXIS 16384
 
-/* Convolution kernel of a tabulated source profile (Section 3.1: the disc
- * profiles are given as tables, stored as N_x x positions, N_y y positions,
- * then N_x N_y brightness values with x fastest). h_x[nx], h_y[ny] and
- * h_b[ny x nx] are HOST arrays of FP32, positions in Einstein radii relative
- * to the source centre, in any order; the library copies them before it
- * returns. Sample (x, y) lies in pixel (floor(x / pix1 + 1/2),
- * floor(y / pix2 + 1/2)), pix = width / p, taken in FP64; each pixel sums its
- * samples in table order (y, then x), and the kernel is centred on pixel
+/* Convolution kernel of a tabulated source profile (Section 3.2, the disc
+ * table: profiles are stored on a regular grid of 1000 to 3000 points per axis
+ * as the x positions, the y positions, then the brightness values; read with
+ * x fastest). h_x[nx], h_y[ny] and h_b[ny x nx] are HOST arrays of FP32,
+ * positions in Einstein radii relative to the source centre, in any order;
+ * the library copies them before it returns. Sample (x, y) lies in pixel
+ * (floor(x / pix1 + 1/2), floor(y / pix2 + 1/2)), pix = width / p, taken in
+ * FP64; each pixel sums its samples in a fixed order (reproducible, equal to
+ * the table-order sum up to rounding), and the kernel is centred on pixel
  * (0, 0) with wrap-around and normalised to unit sum like rl_source_kernel.
  * d_kernel is double[p2 x p1], overwritten. Errors (RL_E_INVALID, nothing
  * launched): 1 <= nx, ny <= RL_MAX_TABLE_AXIS violated, a position not

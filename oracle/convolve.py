@@ -68,13 +68,14 @@ def source_kernel(shape, p1, p2, pix1, pix2, radius, hole=0.0, subsamples=SUBSAM
 
 
 def table_kernel(x, y, b, p1, p2, pix1, pix2):
-    """Kernel of a tabulated profile (the disc profiles of Section 3.1 stored
-    as profile.bin: N_x x values, N_y y values, then N_x N_y brightness values,
-    x fastest), positions in the map's units: each pixel (i, j) around the
-    source centre sums the brightness of the samples it holds, sample (x, y)
-    being in pixel (floor(x / pix1 + 1/2), floor(y / pix2 + 1/2)); the sums are
-    taken in the table's order (y, then x), centred on pixel (0, 0) with
-    wrap-around and normalised to unit sum like source_kernel."""
+    """Kernel of a tabulated profile (the disc profiles of Section 3.1, stored
+    as in the disc table of Section 3.2: N_x x values, N_y y values, then N_x
+    N_y brightness values, read with x fastest), positions in the map's units:
+    each pixel (i, j) around the source centre sums the brightness of the
+    samples it holds, sample (x, y) being in pixel (floor(x / pix1 + 1/2),
+    floor(y / pix2 + 1/2)); the sums are taken in the table's order (y, then
+    x), centred on pixel (0, 0) with wrap-around and normalised to unit sum
+    like source_kernel."""
     x = np.asarray(x, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64).reshape(len(y), len(x))

@@ -1166,8 +1166,11 @@ __global__ void __launch_bounds__(256) table_order_kernel(const int32_t* __restr
 }
 
 // Pixel (i, j) of the compact (2 h1 + 1) x (2 h2 + 1) box sums the brightness
-// of the samples it holds in the table's order: rows ky ascending, then
-// columns kx ascending, starting from 0.
+// of the samples it holds: one wave per pixel, item e of its rows x columns
+// product (table order, rows outer) on lane e mod 64, each lane summing its
+// items in order, then a fixed butterfly. Reproducible, and equal to the sum in
+// table order up to rounding; a paper-sized table (1000 - 3000 points per axis)
+// puts hundreds of samples in each pixel.
 __global__ void __launch_bounds__(256) table_samples_kernel(const float* __restrict__ b, int nx,
                                                             const int32_t* __restrict__ ox,
                                                             const int32_t* __restrict__ sx,
@@ -1176,15 +1179,20 @@ __global__ void __launch_bounds__(256) table_samples_kernel(const float* __restr
                                                             double* __restrict__ compact) {
     const int w = 2 * h1 + 1;
     const int64_t total = (int64_t)w * (2 * h2 + 1);
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
-         q += (int64_t)gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x % 64;
+    const int wpb = blockDim.x / 64;
+    for (int64_t q = (int64_t)blockIdx.x * wpb + threadIdx.x / 64; q < total; q += (int64_t)gridDim.x * wpb) {
         const int i = (int)(q % w), j = (int)(q / w);
+        const int a0 = sy[j], c0 = sx[i], nc = sx[i + 1] - c0;
+        const int ne = (sy[j + 1] - a0) * nc;
         double s = 0.0;
-        for (int a = sy[j]; a < sy[j + 1]; ++a) {
-            const float* row = b + (int64_t)oy[a] * nx;
-            for (int c = sx[i]; c < sx[i + 1]; ++c) s += (double)row[ox[c]];
+        for (int e = lane; e < ne; e += 64) {
+            const int a = e / nc, c = e - a * nc;
+            s += (double)b[(int64_t)oy[a0 + a] * nx + ox[c0 + c]];
         }
-        compact[q] = s;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+        if (lane == 0) compact[q] = s;
     }
 }
 
@@ -1343,8 +1351,8 @@ hipError_t launch_table_kernel(int nx, int ny, double pix1, double pix2, int h1,
                        nx, 2 * h1 + 1, ox, sx);
     hipLaunchKernelGGL(table_order_kernel, dim3((std::max(ny, 2 * h2 + 2) + 255) / 256), dim3(256), 0, s,
                        bins + nx, ny, 2 * h2 + 1, oy, sy);
-    hipLaunchKernelGGL(table_samples_kernel, dim3((unsigned)std::min<int64_t>((m + 255) / 256, 65536)), dim3(256),
-                       0, s, b, nx, ox, sx, oy, sy, h1, h2, compact);
+    hipLaunchKernelGGL(table_samples_kernel, dim3((unsigned)std::min<int64_t>((m + 3) / 4, 65536)), dim3(256), 0,
+                       s, b, nx, ox, sx, oy, sy, h1, h2, compact);
     hipLaunchKernelGGL(ordered_sum_kernel, dim3(1), dim3(1024), 0, s, compact, m, total);
     hipLaunchKernelGGL(fill_source_kernel, dim3((p1 + 255) / 256, p2), dim3(256), 0, s, compact, h1, h2, p1,
                        p2, total, kernel);

@@ -257,20 +257,23 @@ def rl_source_kernel_table(ctx, h_x, nx, h_y, ny, h_b, win, d_kernel, stream=Non
     _check(load().rl_source_kernel_table(ctx, h_x, nx, h_y, ny, h_b, C.byref(win), d_kernel, stream))
 
 
-def read_profile_table(path):
-    """A tabulated source profile file (Section 3.1): int32 N_x, int32 N_y,
-    then FP32 x[N_x], y[N_y] and brightness[N_y x N_x], x fastest, all
-    little-endian. Returns (x, y, b) as numpy float32 arrays, b of shape
-    (N_y, N_x)."""
+def read_profile_table(path, nx, ny):
+    """A tabulated disc profile as the GERLUMPH profile files store it (Section
+    3.2, the disc table): FP32 throughout, the N_x x positions, the N_y y
+    positions, then the N_x N_y brightness values, read here with x fastest
+    and little-endian; N_x and N_y come from the profile's metadata, not from
+    this file. Returns (x, y, b) as numpy float32 arrays, b of shape
+    (N_y, N_x). Positions are in the profile's physical units: scale them to
+    Einstein radii before building a kernel."""
     import numpy as np
-    raw = np.fromfile(path, dtype=np.uint8)
-    if raw.size < 8:
-        raise ValueError(f"{path}: too short for a profile table header")
-    nx, ny = (int(v) for v in raw[:8].view("<i4"))
-    if nx < 1 or ny < 1 or raw.size != 8 + 4 * (nx + ny + nx * ny):
-        raise ValueError(f"{path}: header {nx} x {ny} does not match the file size {raw.size}")
-    body = raw[8:].view("<f4").astype(np.float32)
-    return body[:nx].copy(), body[nx:nx + ny].copy(), body[nx + ny:].reshape(ny, nx).copy()
+    nx, ny = int(nx), int(ny)
+    if nx < 1 or ny < 1:
+        raise ValueError(f"grid {nx} x {ny}: both sides must be >= 1")
+    raw = np.fromfile(path, dtype="<f4")
+    if raw.size != nx + ny + nx * ny:
+        raise ValueError(f"{path}: {raw.size} values, a {nx} x {ny} grid needs {nx + ny + nx * ny}")
+    raw = raw.astype(np.float32)
+    return raw[:nx].copy(), raw[nx:nx + ny].copy(), raw[nx + ny:].reshape(ny, nx).copy()
 
 
 def rl_convolve(ctx, d_counts, d_kernel, win, n_avg, d_out, stream=None):

@@ -354,19 +354,16 @@ def test_binding_refuses_host_tensors_before_any_library_call():
 
 
 def test_profile_table_reader(tmp_path):
-    """read_profile_table: int32 N_x, N_y, then FP32 x, y and brightness (x
-    fastest); a header that does not match the size is refused."""
+    """read_profile_table: FP32 x, y and brightness (x fastest), the grid's
+    sides given by the caller; a size that does not match is refused."""
     import numpy as np
     x = np.array([-0.5, 0.0, 0.5], np.float32)
     y = np.array([-1.0, 1.0], np.float32)
     b = np.arange(6, dtype=np.float32).reshape(2, 3)
     f = tmp_path / "profile.bin"
-    with open(f, "wb") as fh:
-        fh.write(np.array([3, 2], "<i4").tobytes() + x.astype("<f4").tobytes() + y.astype("<f4").tobytes()
-                 + b.astype("<f4").tobytes())
-    gx, gy, gb = rl.read_profile_table(f)
+    f.write_bytes(x.astype("<f4").tobytes() + y.astype("<f4").tobytes() + b.astype("<f4").tobytes())
+    gx, gy, gb = rl.read_profile_table(f, 3, 2)
     assert np.array_equal(gx, x) and np.array_equal(gy, y) and np.array_equal(gb, b)
-    short = tmp_path / "short.bin"
-    short.write_bytes(f.read_bytes()[:-4])
-    with pytest.raises(ValueError):
-        rl.read_profile_table(short)
+    for nx, ny in ((4, 2), (3, 3), (0, 2)):
+        with pytest.raises(ValueError):
+            rl.read_profile_table(f, nx, ny)

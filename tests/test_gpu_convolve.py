@@ -68,7 +68,8 @@ def test_table_kernel_matches_the_oracle_and_the_analytic_kernel(ctx, shape, rad
 def test_table_kernel_of_unordered_tables(ctx, seed, nx, ny, p1, p2):
     """Positions in random order, some exactly on pixel edges (pix = 1/32 and
     1/64, so the edges are FP32 numbers), repeated positions and zero
-    brightness: the same pixels and per-pixel sums as the oracle."""
+    brightness: the same pixels as the oracle (bit-exact zero pattern) and its
+    per-pixel sums to rounding."""
     rng = np.random.default_rng(seed)
     spec = spec_of(p1, p2, p1 / 32.0, p2 / 64.0)
     pix1, pix2 = spec.W1 / spec.p1, spec.W2 / spec.p2
@@ -85,6 +86,22 @@ def test_table_kernel_of_unordered_tables(ctx, seed, nx, ny, p1, p2):
     x, y, b = x.astype(np.float32), y.astype(np.float32), b.astype(np.float32)
     k = ctx.source_kernel_table(spec, x, y, b).cpu().numpy()
     ref = ocv.table_kernel(x, y, b, p1, p2, pix1, pix2)
+    assert np.array_equal(k != 0, ref != 0)
+    assert np.abs(k - ref).max() <= 1e-13 * ref.max()
+    assert abs(k.sum() - 1.0) < 1e-12
+
+
+def test_table_kernel_of_a_paper_sized_grid(ctx):
+    """A regular grid of the size the disc profiles are stored on (1000 to
+    3000 points per axis), ascending: hundreds of samples per pixel, summed in
+    a different order than the oracle's, equal to rounding."""
+    spec = spec_of(512, 512, 8.0, 8.0)
+    x = np.linspace(-0.31, 0.31, 1500).astype(np.float32)
+    y = np.linspace(-0.27, 0.27, 1200).astype(np.float32)
+    X, Y = np.meshgrid(x.astype(np.float64), y.astype(np.float64))
+    b = ocv.brightness("power", np.hypot(X, Y), 0.3, 0.02).astype(np.float32)
+    k = ctx.source_kernel_table(spec, x, y, b).cpu().numpy()
+    ref = ocv.table_kernel(x, y, b, 512, 512, 8.0 / 512, 8.0 / 512)
     assert np.array_equal(k != 0, ref != 0)
     assert np.abs(k - ref).max() <= 1e-13 * ref.max()
     assert abs(k.sum() - 1.0) < 1e-12
