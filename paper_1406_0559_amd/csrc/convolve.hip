@@ -1145,24 +1145,27 @@ __global__ void __launch_bounds__(256) table_bins_kernel(const float* __restrict
 // Stable bucket order of one axis (n samples, bins 0 .. nb - 1): sample k goes
 // to order[start[bin k] + number of earlier samples in its bin], start[b] =
 // number of samples in bins below b, start[nb] = n. Each thread counts over the
-// whole axis, which holds thousands of samples at most.
+// whole axis, which the workgroup stages through LDS 256 bins at a time (every
+// thread reads the same entry: a broadcast).
 __global__ void __launch_bounds__(256) table_order_kernel(const int32_t* __restrict__ bins, int n, int nb,
                                                           int32_t* __restrict__ order, int32_t* __restrict__ start) {
+    __shared__ int32_t tile[256];
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) {
-        const int bt = bins[t];
-        int r = 0;
-        for (int k = 0; k < n; ++k) {
-            const int b = bins[k];
-            r += (b < bt) | ((b == bt) & (k < t));
+    const int bt = t < n ? bins[t] : 0;
+    int r = 0, c = 0;
+    for (int k0 = 0; k0 < n; k0 += 256) {
+        const int m = min(256, n - k0);
+        __syncthreads();
+        if ((int)threadIdx.x < m) tile[threadIdx.x] = bins[k0 + threadIdx.x];
+        __syncthreads();
+        for (int u = 0; u < m; ++u) {
+            const int b = tile[u];
+            r += (b < bt) | ((b == bt) & (k0 + u < t));
+            c += b < t;
         }
-        order[r] = t;
     }
-    if (t <= nb) {
-        int c = 0;
-        for (int k = 0; k < n; ++k) c += bins[k] < t;
-        start[t] = c;
-    }
+    if (t < n) order[r] = t;
+    if (t <= nb) start[t] = c;
 }
 
 // Pixel (i, j) of the compact (2 h1 + 1) x (2 h2 + 1) box sums the brightness
