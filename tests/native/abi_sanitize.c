@@ -104,6 +104,10 @@ int main(void) {
     EXPECT(rl_mpd(ctx, fake_i, &W, 1.0, 1.0, 1.0, -1.0, 10, fake_l, NULL), RL_E_INVALID);
     EXPECT(rl_mpd(ctx, fake_i, &W, 1.0, 1.0, -1.0, 1.0, 0, fake_l, NULL), RL_E_INVALID);
     EXPECT(rl_mpd(ctx, fake_i, &W, 1.0, 1.0, -1.0, 1.0, 5000, fake_l, NULL), RL_E_INVALID);
+    EXPECT(rl_mpd_values(ctx, fake_d, &W, 1.0, 1.0, -1.0, 10, fake_l, NULL), RL_E_INVALID);
+    EXPECT(rl_mpd_values(ctx, fake_d, &W, NAN, -1.0, 1.0, 10, fake_l, NULL), RL_E_INVALID);
+    EXPECT(rl_mpd_values(ctx, fake_d, &W, 1.0, -1.0, 1.0, 0, fake_l, NULL), RL_E_INVALID);
+    EXPECT(rl_mpd_values(ctx, NULL, &W, 1.0, -1.0, 1.0, 10, fake_l, NULL), RL_E_INVALID);
     EXPECT(rl_mpd(ctx, fake_i, &W, -1.0, 1.0, -1.0, 1.0, 10, fake_l, NULL), RL_E_INVALID);
     int64_t lo = 0, hi = 0;
     EXPECT(rl_probability_sums(ctx, fake_i, &W, 1.0, 1.0, NULL, &hi, NULL), RL_E_INVALID);
@@ -127,6 +131,27 @@ int main(void) {
     EXPECT(rl_convolve(ctx, fake_i, fake_d, &W7, 1.0, fake_d, NULL), RL_E_INVALID);
     EXPECT(rl_convolve(ctx, fake_i, fake_d, &W, 0.0, fake_d, NULL), RL_E_INVALID);
     EXPECT(rl_convolve(ctx, fake_i, NULL, &W, 1.0, fake_d, NULL), RL_E_INVALID);
+    const double* ks[3] = {fake_d, fake_d + 1, fake_d + 2};
+    double* outs[3] = {fake_d + 3, fake_d + 1, fake_d + 3};
+    EXPECT(rl_convolve_batch(ctx, fake_i, ks, 0, &W, 1.0, outs, NULL), RL_E_INVALID);
+    EXPECT(rl_convolve_batch(ctx, fake_i, ks, RL_MAX_CONVOLVE_BATCH + 1, &W, 1.0, outs, NULL), RL_E_INVALID);
+    EXPECT(rl_convolve_batch(ctx, fake_i, ks, 3, &W, 1.0, outs, NULL), RL_E_INVALID); /* outputs alias */
+
+    /* tabulated profiles: the host loops over the tables (positions far out of
+     * int range, NaN, negative or all-zero brightness) */
+    const float tx[3] = {-0.1f, 0.0f, 0.1f};
+    const float tfar[3] = {-0.1f, 3.0e38f, 0.1f};
+    const float tnan[3] = {-0.1f, NAN, 0.1f};
+    const float tb[9] = {1, 1, 1, 1, 1, 1, 1, 1, 1};
+    const float tneg[9] = {1, 1, 1, 1, -1, 1, 1, 1, 1};
+    const float tzero[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    EXPECT(rl_source_kernel_table(ctx, tx, 0, tx, 3, tb, &W, fake_d, NULL), RL_E_INVALID);
+    EXPECT(rl_source_kernel_table(ctx, tx, 3, tx, RL_MAX_TABLE_AXIS + 1, tb, &W, fake_d, NULL), RL_E_INVALID);
+    EXPECT(rl_source_kernel_table(ctx, tfar, 3, tx, 3, tb, &W, fake_d, NULL), RL_E_INVALID);
+    EXPECT(rl_source_kernel_table(ctx, tx, 3, tnan, 3, tb, &W, fake_d, NULL), RL_E_INVALID);
+    EXPECT(rl_source_kernel_table(ctx, tx, 3, tx, 3, tneg, &W, fake_d, NULL), RL_E_INVALID);
+    EXPECT(rl_source_kernel_table(ctx, tx, 3, tx, 3, tzero, &W, fake_d, NULL), RL_E_INVALID);
+    EXPECT(rl_source_kernel_table(ctx, tx, 3, tx, 3, tb, &W, NULL, NULL), RL_E_INVALID);
 
     if (rl_last_error()[0] == '\0') return 1;
     EXPECT(rl_destroy(ctx), RL_OK);
