@@ -4,6 +4,7 @@
 #include "raylens.h"
 
 #include <algorithm>
+#include <cfloat>
 #include <climits>
 #include <cmath>
 #include <cstdarg>
@@ -1087,13 +1088,16 @@ rl_status rl_source_kernel_table(rl_context* ctx, const float* h_x, int32_t nx, 
     int32_t h1 = 0, h2 = 0;
     if (!half(h_x, nx, pix1, win->p1, &h1) || !half(h_y, ny, pix2, win->p2, &h2))
         return fail(RL_E_INVALID, "table positions must be finite and the source no larger than the map");
-    bool any = false;
+    // Branch-free over the (millions of) brightness values: NaN, negative and
+    // infinite values all fail v >= 0 && v <= FLT_MAX.
+    int bad = 0, any = 0;
     const int64_t nb = (int64_t)nx * ny;
     for (int64_t k = 0; k < nb; ++k) {
-        if (!is_finite(h_b[k]) || h_b[k] < 0.0f)
-            return fail(RL_E_INVALID, "table brightness must be finite and >= 0");
-        any = any || h_b[k] > 0.0f;
+        const float v = h_b[k];
+        bad |= !(v >= 0.0f && v <= FLT_MAX);
+        any |= v > 0.0f;
     }
+    if (bad) return fail(RL_E_INVALID, "table brightness must be finite and >= 0");
     if (!any) return fail(RL_E_INVALID, "empty source kernel: every brightness is 0");
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return hip_fail(dg.err, "hipSetDevice");
