@@ -1144,28 +1144,28 @@ __global__ void __launch_bounds__(256) table_bins_kernel(const float* __restrict
 
 // Stable bucket order of one axis (n samples, bins 0 .. nb - 1): sample k goes
 // to order[start[bin k] + number of earlier samples in its bin], start[b] =
-// number of samples in bins below b, start[nb] = n. Each thread counts over the
-// whole axis, which the workgroup stages through LDS 256 bins at a time (every
-// thread reads the same entry: a broadcast).
+// number of samples in bins below b, start[nb] = n. One wave per output: wave
+// w < n ranks sample w, wave n + b counts start[b]; its lanes split the axis
+// and a butterfly adds their counts (thousands of waves: the quadratic count
+// is spread over the whole chip instead of a few workgroups).
 __global__ void __launch_bounds__(256) table_order_kernel(const int32_t* __restrict__ bins, int n, int nb,
                                                           int32_t* __restrict__ order, int32_t* __restrict__ start) {
-    __shared__ int32_t tile[256];
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int bt = t < n ? bins[t] : 0;
-    int r = 0, c = 0;
-    for (int k0 = 0; k0 < n; k0 += 256) {
-        const int m = min(256, n - k0);
-        __syncthreads();
-        if ((int)threadIdx.x < m) tile[threadIdx.x] = bins[k0 + threadIdx.x];
-        __syncthreads();
-        for (int u = 0; u < m; ++u) {
-            const int b = tile[u];
-            r += (b < bt) | ((b == bt) & (k0 + u < t));
-            c += b < t;
-        }
+    const int lane = threadIdx.x % 64;
+    const int w = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64);
+    if (w > n + nb) return;     // wave-uniform
+    const bool rank = w < n;
+    const int bt = rank ? bins[w] : w - n;
+    int cnt = 0;
+    for (int k = lane; k < n; k += 64) {
+        const int b = bins[k];
+        cnt += rank ? ((b < bt) | ((b == bt) & (k < w))) : (b < bt);
     }
-    if (t < n) order[r] = t;
-    if (t <= nb) start[t] = c;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+    if (lane == 0) {
+        if (rank) order[cnt] = w;
+        else start[bt] = cnt;
+    }
 }
 
 // Pixel (i, j) of the compact (2 h1 + 1) x (2 h2 + 1) box sums the brightness
@@ -1350,10 +1350,11 @@ hipError_t launch_table_kernel(int nx, int ny, double pix1, double pix2, int h1,
     const float* b = y + ny;
     hipLaunchKernelGGL(table_bins_kernel, dim3((nx + ny + 255) / 256), dim3(256), 0, s, x, nx, y, ny, pix1, pix2,
                        h1, h2, bins);
-    hipLaunchKernelGGL(table_order_kernel, dim3((std::max(nx, 2 * h1 + 2) + 255) / 256), dim3(256), 0, s, bins,
-                       nx, 2 * h1 + 1, ox, sx);
-    hipLaunchKernelGGL(table_order_kernel, dim3((std::max(ny, 2 * h2 + 2) + 255) / 256), dim3(256), 0, s,
-                       bins + nx, ny, 2 * h2 + 1, oy, sy);
+    // one wave per sample and per start entry: n + nb + 1 waves, four per workgroup
+    hipLaunchKernelGGL(table_order_kernel, dim3((nx + 2 * h1 + 2 + 3) / 4), dim3(256), 0, s, bins, nx, 2 * h1 + 1,
+                       ox, sx);
+    hipLaunchKernelGGL(table_order_kernel, dim3((ny + 2 * h2 + 2 + 3) / 4), dim3(256), 0, s, bins + nx, ny,
+                       2 * h2 + 1, oy, sy);
     hipLaunchKernelGGL(table_samples_kernel, dim3((unsigned)std::min<int64_t>((m + 3) / 4, 65536)), dim3(256), 0,
                        s, b, nx, ox, sx, oy, sy, h1, h2, compact);
     hipLaunchKernelGGL(ordered_sum_kernel, dim3(1), dim3(1024), 0, s, compact, m, total);
