@@ -107,6 +107,24 @@ def test_table_kernel_of_a_paper_sized_grid(ctx):
     assert abs(k.sum() - 1.0) < 1e-12
 
 
+def test_table_kernel_at_the_largest_axis(ctx):
+    """RL_MAX_TABLE_AXIS samples on one axis (random order), two on the other;
+    one more sample is refused before any work."""
+    rng = np.random.default_rng(21)
+    spec = spec_of(128, 64, 4.0, 2.0)
+    n = rl.RL_MAX_TABLE_AXIS
+    x = rng.uniform(-0.5, 0.5, n).astype(np.float32)
+    y = np.array([-0.01, 0.02], np.float32)
+    b = rng.exponential(1.0, (2, n)).astype(np.float32)
+    k = ctx.source_kernel_table(spec, x, y, b).cpu().numpy()
+    ref = ocv.table_kernel(x, y, b, 128, 64, 4.0 / 128, 2.0 / 64)
+    assert np.array_equal(k != 0, ref != 0)
+    assert np.abs(k - ref).max() <= 1e-13 * ref.max()
+    x1 = np.zeros(n + 1, np.float32)
+    with pytest.raises(rl.RaylensError):
+        ctx.source_kernel_table(spec, x1, y, np.ones((2, n + 1), np.float32))
+
+
 def test_convolution_with_a_table_kernel(ctx):
     """The table kernel feeds the convolution like the analytic one."""
     rng = np.random.default_rng(11)
